@@ -1,0 +1,174 @@
+"""FP64 CPU oracle of the single-pulse detection path (arXiv:1611.09704).
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  The product library
+never calls it, and it shares no code with the HIP path: the C file next to this
+one is compiled with gcc, on its own, into ``libspd_oracle.so``.
+
+The functions follow the paper's steps:
+
+* ``chan_stream`` -- Sec. 2.1, Eq. (MSD03), the serial streaming update;
+* ``chan_merge`` -- Sec. 2.1, Eq. (MSD04), the pairwise merge;
+* ``stream_step`` / ``detect`` -- Sec. 2.1-2.3 and Algorithm 1: statistics per
+  unit, sigma_N from Eq. (sd02) or the linear form Eq. (sd03), the highest SNR
+  over the width list and the first width that reaches it;
+* ``select`` -- Sec. 2.4, the SNR threshold and the candidate list.
+
+The readings taken where the paper is silent or garbled are listed in the
+header of ``spd_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "spd_oracle.c")
+_LIB = os.path.join(_HERE, "libspd_oracle.so")
+_lock = threading.Lock()
+_lib = None
+
+SCOPES = {"row": 0, "plane": 1}
+SIGMA_MODES = {"sqrtn": 0, "linear": 1, "auto": 2, "linear_literal": 3}
+FLAG_ZERO_VAR = 1
+FLAG_LINEAR = 2
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP over rows)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            lib = ctypes.CDLL(_LIB)
+            d, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+            lib.oracle_chan_stream.argtypes = [d, i64, d]
+            lib.oracle_chan_stream.restype = None
+            lib.oracle_chan_merge.argtypes = [d, d, d]
+            lib.oracle_chan_merge.restype = None
+            lib.oracle_stream_step.argtypes = [d, i64, i64, i64, d, i32, ctypes.c_int, ctypes.c_int,
+                                               ctypes.c_double, d, d, d, d, ctypes.c_int]
+            lib.oracle_stream_step.restype = ctypes.c_int
+            lib.oracle_select.argtypes = [d, d, i64, i64, d, ctypes.c_double, i64, d, d, d, d, i64]
+            lib.oracle_select.restype = i64
+            lib.oracle_max_threads.argtypes = []
+            lib.oracle_max_threads.restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_threads() -> int:
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
+def chan_stream(x) -> np.ndarray:
+    """(n, T, S) of a sequence by the streaming update, Eq. (MSD03)."""
+    x = np.ascontiguousarray(x, dtype=np.float64).ravel()
+    out = np.zeros(3)
+    _load().oracle_chan_stream(_ptr(x), x.size, _ptr(out))
+    return out
+
+
+def chan_merge(a, b) -> np.ndarray:
+    """Merge two (n, T, S) partials with Eq. (MSD04)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    out = np.zeros(3)
+    _load().oracle_chan_merge(_ptr(a), _ptr(b), _ptr(out))
+    return out
+
+
+def new_state(n_units: int) -> np.ndarray:
+    """Empty running state {n, T, S, n_y, T_y, S_y} per unit."""
+    return np.zeros((n_units, 6))
+
+
+def stream_step(x, widths, *, new_col_begin=0, state=None, scope="row", sigma_mode="sqrtn",
+                kappa=1.0, nthreads=None):
+    """One step over a plane view; returns (state, stats, snr, widx).
+
+    ``stats`` has one row per unit: mean, sigma, sigma_Nmax, linear coefficient,
+    flags.  ``snr``/``widx`` have shape (R, L_view - Nmax + 1); ``widx`` indexes
+    ``widths``.
+    """
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim != 2:
+        raise ValueError("plane must be 2-D")
+    R, L = x.shape
+    W = np.ascontiguousarray(widths, dtype=np.int32)
+    nmax = int(W[-1])
+    n_units = 1 if scope == "plane" else R
+    if state is None:
+        state = new_state(n_units)
+    state = np.ascontiguousarray(state, dtype=np.float64).copy()
+    if state.shape != (n_units, 6):
+        raise ValueError("state shape mismatch")
+    stats = np.zeros((n_units, 5))
+    n_out = L - nmax + 1
+    if n_out < 1:
+        raise ValueError("plane shorter than the widest boxcar")
+    snr = np.zeros((R, n_out))
+    widx = np.zeros((R, n_out), dtype=np.int32)
+    rc = _load().oracle_stream_step(_ptr(x), R, L, int(new_col_begin), _ptr(W), W.size,
+                                    SCOPES[scope], SIGMA_MODES[sigma_mode], float(kappa),
+                                    _ptr(state), _ptr(stats), _ptr(snr), _ptr(widx),
+                                    int(nthreads or default_threads()))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    return state, stats, snr, widx
+
+
+def select(snr, widx, widths, threshold, t_offset=0):
+    """Candidate list of Sec. 2.4 as a dict of arrays (row-major order)."""
+    snr = np.ascontiguousarray(snr, dtype=np.float64)
+    widx = np.ascontiguousarray(widx, dtype=np.int32)
+    W = np.ascontiguousarray(widths, dtype=np.int32)
+    R, n_out = snr.shape
+    lib = _load()
+    cap = 0
+    total = lib.oracle_select(_ptr(snr), _ptr(widx), R, n_out, _ptr(W), float(threshold),
+                              int(t_offset), None, None, None, None, cap)
+    rows = np.zeros(total, dtype=np.int64)
+    ts = np.zeros(total, dtype=np.int64)
+    ss = np.zeros(total)
+    ws = np.zeros(total, dtype=np.int32)
+    lib.oracle_select(_ptr(snr), _ptr(widx), R, n_out, _ptr(W), float(threshold), int(t_offset),
+                      _ptr(rows), _ptr(ts), _ptr(ss), _ptr(ws), total)
+    return {"row": rows, "t": ts, "snr": ss, "width": ws}
+
+
+def detect(x, widths, threshold, *, scope="row", sigma_mode="sqrtn", kappa=1.0, nthreads=None):
+    """The whole path on one plane, one shot: stats, snr, widx and candidates."""
+    _, stats, snr, widx = stream_step(x, widths, scope=scope, sigma_mode=sigma_mode,
+                                      kappa=kappa, nthreads=nthreads)
+    cands = select(snr, widx, widths, threshold)
+    return {"stats": stats, "snr": snr, "widx": widx, "cands": cands}
+
+
+def dequantize_u8(q, scale, zero) -> np.ndarray:
+    """Exact FP64 value of a per-row quantised plane: x = scale_r * (q - zero_r)."""
+    q = np.asarray(q, dtype=np.float64)
+    s = np.asarray(scale, dtype=np.float64).reshape(-1, 1)
+    z = np.asarray(zero, dtype=np.float64).reshape(-1, 1)
+    return s * (q - z)
