@@ -1,0 +1,199 @@
+/*
+ * spd.h -- C ABI of libspd, the MI355X (gfx950) single-pulse detection path of
+ * Adamek & Armour, "A Real-time Single Pulse Detection Algorithm for GPUs"
+ * (arXiv:1611.09704).
+ *
+ * The path runs over a plane of de-dispersed time series, one row per DM
+ * trial, time contiguous (Sec. 1, Sec. 2.3):
+ *   1. msd_compute       mean and standard deviation per unit (Sec. 2.1,
+ *                        Eq. MSD03 inside a block, Eq. MSD04 across blocks),
+ *                        plus sigma of the widest boxcar when the linear
+ *                        approximation of Sec. 2.2 Eq. (sd03) is in use;
+ *   2. boxcar_snr        boxcars of every listed width at every sample, their
+ *                        SNR with sigma_N from Eq. (sd02) or Eq. (sd03), and
+ *                        the highest SNR with its width (Sec. 2.3,
+ *                        Algorithm 1); optionally fused with step 3;
+ *   3. select_candidates the SNR threshold of Sec. 2.4, producing an unordered
+ *                        list of (DM-trial row, time, SNR, width).
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE memory owned by the caller unless marked [host].
+ *     The library keeps no pointer after a call returns.
+ *   - Every call validates its arguments on the host first.  On any error
+ *     nothing is enqueued, the call returns a non-zero spd_status and
+ *     spd_last_error() (thread-local) describes the problem.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
+ *     and the call returns without synchronising.  A launch failure reported
+ *     by the HIP runtime returns SPD_E_DEVICE.
+ *   - None of these entry points allocates device memory.  Scratch space is
+ *     the caller's `workspace`, sized by spd_workspace_bytes().
+ *   - Calls are re-entrant; calls on different streams may overlap as long as
+ *     they do not share output or workspace buffers.
+ *   - Readings of the paper (all shared with the CPU oracle):
+ *       * Eq. (MSD03) is applied with its update term squared; sigma is the
+ *         population value sqrt(S/n).
+ *       * The width-w boxcar at t is B_w(t) = sum_{k<w} x[t+k]; its SNR is
+ *         (B_w(t) - w*mean) / sigma_w.  Outputs exist for t in [0, n_cols-Nmax]
+ *         where Nmax = the largest width.
+ *       * sigma_w = sqrt(w)*sigma + (w-1)*lin_coef, lin_coef = 0 under
+ *         Eq. (sd02).  Under Eq. (sd03) (anchored reading) lin_coef =
+ *         (sigma_Nmax - sqrt(Nmax)*sigma)/(Nmax-1); the literal printed form
+ *         uses sigma_Nmax/(Nmax-1).  sigma_Nmax is the population standard
+ *         deviation of B_Nmax(t) over the unit's valid starts.
+ *       * The highest SNR keeps the FIRST width that reaches it (strict '>').
+ *       * A unit with sigma == 0 is flagged SPD_FLAG_ZERO_VAR: all its SNRs
+ *         are 0 and all width indices 0.  A width whose sigma_w <= 0 gives 0.
+ *       * A sample is a candidate iff its highest SNR >= threshold.
+ */
+#ifndef SPD_H
+#define SPD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPD_ABI_VERSION 1
+#define SPD_MAX_WIDTHS 256     /* |W| limit: width indices are stored as uint8 */
+#define SPD_MAX_NMAX 4096      /* largest supported boxcar width              */
+
+typedef enum {
+    SPD_OK = 0,
+    SPD_E_INVALID = 1,      /* bad argument (message in spd_last_error)         */
+    SPD_E_UNSUPPORTED = 2,  /* valid request this build does not handle          */
+    SPD_E_NOMEM = 3,        /* workspace too small / allocation failed          */
+    SPD_E_DEVICE = 4,       /* the HIP runtime reported an error                */
+    SPD_E_AGAIN = 5         /* serving: queue full or nothing ready (retry)      */
+} spd_status;
+
+typedef enum { SPD_F32 = 0, SPD_F16 = 1, SPD_U8 = 2 } spd_dtype;
+typedef enum { SPD_SCOPE_ROW = 0, SPD_SCOPE_PLANE = 1 } spd_scope;
+typedef enum {
+    SPD_SIGMA_SQRTN = 0,          /* Eq. (sd02): sigma_w = sqrt(w)*sigma                */
+    SPD_SIGMA_LINEAR = 1,         /* Eq. (sd03), anchored reading, every unit           */
+    SPD_SIGMA_AUTO = 2,           /* anchored Eq. (sd03) where rho > 1 + kappa, else sd02 */
+    SPD_SIGMA_LINEAR_LITERAL = 3  /* Eq. (sd03) exactly as printed                      */
+} spd_sigma_mode;
+
+#define SPD_FLAG_ZERO_VAR 1u   /* sigma == 0: SNR 0, width index 0 */
+#define SPD_FLAG_LINEAR 2u     /* the linear term of Eq. (sd03) is applied */
+
+/* A DM-trial x time plane.  Element [r][t] lives at
+ * (const char*)data + (r*row_stride + t)*elem_size, elem_size 4/2/1 for
+ * F32/F16/U8.  For U8 the value is x = row_scale[r]*(q - row_zero[r]).
+ * Rows whose start is 16-byte aligned take the vector-load path.            */
+typedef struct {
+    const void* data;
+    int32_t dtype;           /* spd_dtype */
+    int32_t reserved0;
+    int64_t n_rows;          /* >= 1 */
+    int64_t n_cols;          /* >= Nmax */
+    int64_t row_stride;      /* elements, >= n_cols */
+    const float* row_scale;  /* U8 only, [n_rows] */
+    const float* row_zero;   /* U8 only, [n_rows] */
+} spd_plane;
+
+typedef struct {
+    const int32_t* widths;   /* [host] strictly increasing, widths[0] >= 1, last <= SPD_MAX_NMAX */
+    int32_t n_widths;        /* 1 .. SPD_MAX_WIDTHS */
+    float threshold;         /* f_T of Sec. 2.4, in SNR units; finite */
+    int32_t scope;           /* spd_scope: statistics per row, or one set for the plane */
+    int32_t sigma_mode;      /* spd_sigma_mode */
+    float auto_kappa;        /* AUTO: linear iff sigma_Nmax/(sqrt(Nmax)*sigma) > 1 + kappa */
+    int32_t reserved0;
+} spd_params;
+
+/* Running FP64 statistics of one unit: count, sum and sum of squared
+ * deviations of the raw samples, and the same for B_Nmax(t) (Sec. 2.1).     */
+typedef struct { double n, T, S, n_y, T_y, S_y; } spd_msd_state;
+
+/* Per-unit statistics consumed by boxcar_snr. */
+typedef struct {
+    double mean, sigma, sigma_nmax, lin_coef;
+    uint32_t flags;          /* SPD_FLAG_* */
+    uint32_t reserved0;
+} spd_row_stats;
+
+/* One candidate of Sec. 2.4: DM-trial row, time (window start + t_offset),
+ * highest SNR and the boxcar width that produced it.                        */
+typedef struct {
+    int32_t row;
+    int32_t width;
+    int64_t t;
+    float snr;
+    uint32_t reserved0;
+} spd_candidate;
+
+/* ABI version (SPD_ABI_VERSION of the built library). */
+int spd_abi_version(void);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char* spd_last_error(void);
+
+/* Bytes of device workspace msd_compute needs for this plane and params, or 0
+ * when the arguments are invalid (see spd_last_error).                     */
+size_t spd_workspace_bytes(const spd_plane* x, const spd_params* p);
+
+/*
+ * msd_compute -- Sec. 2.1: per-unit mean and standard deviation.
+ *   A unit is a row (SPD_SCOPE_ROW) or the whole plane (SPD_SCOPE_PLANE).
+ *   Each block of a row is reduced in FP32 with the streaming update
+ *   (Eq. MSD03) and the pairwise merge (Eq. MSD04) inside the block; the
+ *   block partials are then merged across blocks in FP64 (Eq. MSD04).
+ *   Raw-sample statistics use columns [new_col_begin, n_cols).  When
+ *   sigma_mode != SPD_SIGMA_SQRTN, the statistics of B_Nmax(t) over every
+ *   valid start t in [0, n_cols-Nmax] are gathered in the same pass.
+ *   state       [n_units] or NULL.  accumulate=1: *state is merged with this
+ *               call's statistics (Eq. MSD04) and the result is written back
+ *               (streaming over chunks; the caller passes the previous
+ *               chunk's last Nmax-1 columns as a halo and sets
+ *               new_col_begin = Nmax-1).  accumulate=0: *state is overwritten.
+ *               state may be NULL only when accumulate == 0.
+ *   stats       [n_units] output: mean, sigma, sigma_Nmax, lin_coef, flags
+ *               from the (merged) state.
+ *   workspace   >= spd_workspace_bytes(x, p) bytes, 256-byte aligned.
+ */
+spd_status msd_compute(const spd_plane* x, const spd_params* p, int64_t new_col_begin,
+                       int32_t accumulate, spd_msd_state* state, spd_row_stats* stats,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * boxcar_snr -- Sec. 2.2-2.3, Algorithm 1: for every row r and start
+ *   t in [0, n_out) with n_out = n_cols - Nmax + 1, the highest
+ *   (B_w(t) - w*mean)/sigma_w over the width list and the index (into
+ *   p->widths) of the first width reaching it.
+ *   stats       [n_units] from msd_compute (unit = row, or one for the plane).
+ *   snr_out     [n_rows][out_stride] float, or NULL.
+ *   widx_out    [n_rows][out_stride] uint8 index into p->widths, or NULL.
+ *   out_stride  elements, >= n_out when an output is given.
+ *   cand        when not NULL, the threshold of Sec. 2.4 is fused: every
+ *               (r, t) with snr >= p->threshold is appended, unordered, as
+ *               {r, widths[idx], t + t_offset, snr}.  At most cand_capacity
+ *               entries are written; *cand_count (device int64, reset by the
+ *               call) receives the total number found, which may exceed the
+ *               capacity -- the caller then grows the list and re-runs.
+ *   At least one of snr_out, widx_out, cand must be given.
+ */
+spd_status boxcar_snr(const spd_plane* x, const spd_params* p, const spd_row_stats* stats,
+                      float* snr_out, uint8_t* widx_out, int64_t out_stride, int64_t t_offset,
+                      spd_candidate* cand, int64_t cand_capacity, int64_t* cand_count,
+                      void* stream);
+
+/*
+ * select_candidates -- Sec. 2.4 on stored outputs: every (r, t) with
+ *   snr[r*out_stride + t] >= p->threshold, t < n_out_cols, becomes
+ *   {r, p->widths[widx[...]], t + t_offset, snr}.  Unordered; capacity and
+ *   *cand_count behave as in boxcar_snr.
+ */
+spd_status select_candidates(const float* snr, const uint8_t* widx, int64_t n_rows,
+                             int64_t n_out_cols, int64_t out_stride, const spd_params* p,
+                             int64_t t_offset, spd_candidate* cand, int64_t cand_capacity,
+                             int64_t* cand_count, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPD_H */

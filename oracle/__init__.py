@@ -172,3 +172,16 @@ def dequantize_u8(q, scale, zero) -> np.ndarray:
     s = np.asarray(scale, dtype=np.float64).reshape(-1, 1)
     z = np.asarray(zero, dtype=np.float64).reshape(-1, 1)
     return s * (q - z)
+
+
+def snr_at(row, t, width, unit_stats):
+    """SNR of one boxcar, Sec. 2.3 with sigma_w of Eq. (sd02)/(sd03):
+    (sum_{k<w} x[t+k] - w*mean) / (sqrt(w)*sigma + (w-1)*coef); 0 for a
+    ZERO_VAR unit or a non-positive sigma_w.  ``unit_stats`` is one row of the
+    ``stats`` array returned by ``stream_step``."""
+    mean, sigma, _, coef, flags = (float(v) for v in unit_stats)
+    sw = np.sqrt(width) * sigma + (width - 1) * coef
+    if int(flags) & FLAG_ZERO_VAR or not sw > 0.0:
+        return 0.0
+    b = float(np.sum(np.asarray(row[t:t + width], dtype=np.float64)))
+    return (b - width * mean) / sw

@@ -1,0 +1,244 @@
+"""ctypes binding of libspd (include/spd.h).
+
+Argument marshalling only: every step of the detection path runs in the HIP
+kernels of libspd.so.  Torch tensors provide device memory and the current
+HIP stream.  If the library is missing, loading raises -- there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspd.so")
+
+SPD_F32, SPD_F16, SPD_U8 = 0, 1, 2
+SCOPES = {"row": 0, "plane": 1}
+SIGMA_MODES = {"sqrtn": 0, "linear": 1, "auto": 2, "linear_literal": 3}
+FLAG_ZERO_VAR, FLAG_LINEAR = 1, 2
+STATUS = {0: "SPD_OK", 1: "SPD_E_INVALID", 2: "SPD_E_UNSUPPORTED", 3: "SPD_E_NOMEM",
+          4: "SPD_E_DEVICE", 5: "SPD_E_AGAIN"}
+
+CANDIDATE_DTYPE = np.dtype([("row", "<i4"), ("width", "<i4"), ("t", "<i8"), ("snr", "<f4"),
+                            ("reserved", "<u4")])
+STATS_FIELDS = 5          # mean, sigma, sigma_nmax, lin_coef, flags|reserved (as doubles)
+STATE_FIELDS = 6          # n, T, S, n_y, T_y, S_y
+
+
+class SpdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), message))
+        self.status = status
+
+
+class SpdPlane(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("row_stride", ctypes.c_int64),
+                ("row_scale", ctypes.c_void_p), ("row_zero", ctypes.c_void_p)]
+
+
+class SpdParams(ctypes.Structure):
+    _fields_ = [("widths", ctypes.POINTER(ctypes.c_int32)), ("n_widths", ctypes.c_int32),
+                ("threshold", ctypes.c_float), ("scope", ctypes.c_int32), ("sigma_mode", ctypes.c_int32),
+                ("auto_kappa", ctypes.c_float), ("reserved0", ctypes.c_int32)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def lib_path() -> str:
+    return LIB_PATH
+
+
+def load():
+    """Load libspd.so (raises if it has not been built)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libspd.so not found at %s; build it with "
+                              "`python -m paper_1611_09704_amd.build`" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        P = ctypes.POINTER
+        lib.spd_abi_version.restype = ctypes.c_int
+        lib.spd_last_error.restype = ctypes.c_char_p
+        lib.spd_workspace_bytes.argtypes = [P(SpdPlane), P(SpdParams)]
+        lib.spd_workspace_bytes.restype = ctypes.c_size_t
+        lib.msd_compute.argtypes = [P(SpdPlane), P(SpdParams), i64, i32, vp, vp, vp, ctypes.c_size_t, vp]
+        lib.msd_compute.restype = ctypes.c_int
+        lib.boxcar_snr.argtypes = [P(SpdPlane), P(SpdParams), vp, vp, vp, i64, i64, vp, i64, vp, vp]
+        lib.boxcar_snr.restype = ctypes.c_int
+        lib.select_candidates.argtypes = [vp, vp, i64, i64, i64, P(SpdParams), i64, vp, i64, vp, vp]
+        lib.select_candidates.restype = ctypes.c_int
+        _lib = lib
+        return lib
+
+
+def abi_version() -> int:
+    return load().spd_abi_version()
+
+
+def _check(status: int):
+    if status != 0:
+        raise SpdError(status, load().spd_last_error().decode())
+
+
+class Params:
+    """Width list, threshold and options of one detection (spd_params)."""
+
+    def __init__(self, widths: Sequence[int], threshold: float, scope: str = "row",
+                 sigma_mode: str = "sqrtn", kappa: float = 1.0):
+        self.widths = [int(w) for w in widths]
+        self._w = (ctypes.c_int32 * len(self.widths))(*self.widths)
+        self.threshold = float(threshold)
+        self.scope = scope
+        self.sigma_mode = sigma_mode
+        self.kappa = float(kappa)
+        self.c = SpdParams(ctypes.cast(self._w, ctypes.POINTER(ctypes.c_int32)), len(self.widths),
+                           self.threshold, SCOPES[scope], SIGMA_MODES[sigma_mode], self.kappa, 0)
+
+    @property
+    def nmax(self) -> int:
+        return self.widths[-1]
+
+    def n_units(self, n_rows: int) -> int:
+        return 1 if self.scope == "plane" else n_rows
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def plane_struct(x: torch.Tensor, scale: Optional[torch.Tensor] = None,
+                 zero: Optional[torch.Tensor] = None) -> SpdPlane:
+    """spd_plane view of a 2-D device tensor (rows = DM trials, time contiguous)."""
+    if x.dim() != 2 or x.stride(1) != 1:
+        raise ValueError("plane must be 2-D with a contiguous time axis")
+    if not x.is_cuda:
+        raise ValueError("plane must be a device tensor")
+    if x.dtype == torch.float32:
+        dt = SPD_F32
+    elif x.dtype == torch.float16:
+        dt = SPD_F16
+    elif x.dtype == torch.uint8:
+        dt = SPD_U8
+        if scale is None or zero is None:
+            raise ValueError("uint8 plane needs per-row scale and zero")
+    else:
+        raise ValueError("unsupported plane dtype %s" % x.dtype)
+    return SpdPlane(x.data_ptr(), dt, 0, x.shape[0], x.shape[1], x.stride(0),
+                    scale.data_ptr() if scale is not None else None,
+                    zero.data_ptr() if zero is not None else None)
+
+
+def workspace_bytes(x: torch.Tensor, params: Params, scale=None, zero=None) -> int:
+    pl = plane_struct(x, scale, zero)
+    n = load().spd_workspace_bytes(ctypes.byref(pl), ctypes.byref(params.c))
+    if n == 0:
+        _check(1)
+    return n
+
+
+def msd_compute(x: torch.Tensor, params: Params, *, scale=None, zero=None, new_col_begin: int = 0,
+                accumulate: bool = False, state: Optional[torch.Tensor] = None,
+                stats: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+                stream=None) -> torch.Tensor:
+    """Per-unit statistics (Sec. 2.1-2.2); returns stats as float64 [units, 5]."""
+    lib = load()
+    pl = plane_struct(x, scale, zero)
+    units = params.n_units(x.shape[0])
+    if stats is None:
+        stats = torch.empty((units, STATS_FIELDS), dtype=torch.float64, device=x.device)
+    need = lib.spd_workspace_bytes(ctypes.byref(pl), ctypes.byref(params.c))
+    if need == 0:
+        _check(1)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    _check(lib.msd_compute(ctypes.byref(pl), ctypes.byref(params.c), int(new_col_begin), int(bool(accumulate)),
+                           state.data_ptr() if state is not None else None, stats.data_ptr(),
+                           workspace.data_ptr(), workspace.numel() * workspace.element_size(), _stream(stream)))
+    return stats
+
+
+def boxcar_snr(x: torch.Tensor, params: Params, stats: torch.Tensor, *, scale=None, zero=None,
+               snr: Optional[torch.Tensor] = None, widx: Optional[torch.Tensor] = None,
+               out_stride: Optional[int] = None, t_offset: int = 0, cand: Optional[torch.Tensor] = None,
+               cand_count: Optional[torch.Tensor] = None, stream=None) -> None:
+    """Boxcar bank, SNR and per-sample max/argmax (Sec. 2.3), optional fused threshold."""
+    lib = load()
+    pl = plane_struct(x, scale, zero)
+    if out_stride is None:
+        out_stride = snr.stride(0) if snr is not None else (widx.stride(0) if widx is not None else 0)
+    cap = cand.shape[0] if cand is not None else 0
+    _check(lib.boxcar_snr(ctypes.byref(pl), ctypes.byref(params.c), stats.data_ptr(),
+                          snr.data_ptr() if snr is not None else None,
+                          widx.data_ptr() if widx is not None else None, int(out_stride), int(t_offset),
+                          cand.data_ptr() if cand is not None else None, int(cap),
+                          cand_count.data_ptr() if cand_count is not None else None, _stream(stream)))
+
+
+def select_candidates(snr: torch.Tensor, widx: torch.Tensor, params: Params, *, n_out_cols: Optional[int] = None,
+                      t_offset: int = 0, cand: torch.Tensor, cand_count: torch.Tensor, stream=None) -> None:
+    """Threshold of Sec. 2.4 over stored snr / width-index arrays."""
+    lib = load()
+    n_rows = snr.shape[0]
+    ncols = snr.shape[1] if n_out_cols is None else int(n_out_cols)
+    _check(lib.select_candidates(snr.data_ptr(), widx.data_ptr(), n_rows, ncols, snr.stride(0),
+                                 ctypes.byref(params.c), int(t_offset), cand.data_ptr(), cand.shape[0],
+                                 cand_count.data_ptr(), _stream(stream)))
+
+
+def new_candidates(capacity: int, device) -> torch.Tensor:
+    return torch.empty((max(1, int(capacity)), CANDIDATE_DTYPE.itemsize), dtype=torch.uint8, device=device)
+
+
+def candidates_to_numpy(cand: torch.Tensor, count: int) -> np.ndarray:
+    n = min(int(count), cand.shape[0])
+    raw = cand[:n].cpu().numpy().tobytes()
+    return np.frombuffer(raw, dtype=CANDIDATE_DTYPE).copy()
+
+
+def stats_flags(stats: torch.Tensor) -> torch.Tensor:
+    """The uint32 flags word of each spd_row_stats row."""
+    return stats.view(torch.int32)[:, 8]
+
+
+def detect(x: torch.Tensor, widths: Sequence[int], threshold: float, *, scope: str = "row",
+           sigma_mode: str = "sqrtn", kappa: float = 1.0, scale=None, zero=None, outputs: bool = True,
+           fused_select: bool = True, capacity: int = 1 << 16, stream=None) -> dict:
+    """The whole path on one plane: msd_compute, boxcar_snr (+ fused threshold),
+    or boxcar_snr then select_candidates.  Grows the candidate list and re-runs
+    if it overflows.  Synchronises the stream before returning."""
+    params = Params(widths, threshold, scope, sigma_mode, kappa)
+    stats = msd_compute(x, params, scale=scale, zero=zero, stream=stream)
+    nout = x.shape[1] - params.nmax + 1
+    snr = torch.empty((x.shape[0], nout), dtype=torch.float32, device=x.device) if outputs else None
+    widx = torch.empty((x.shape[0], nout), dtype=torch.uint8, device=x.device) if outputs else None
+    count = torch.zeros(1, dtype=torch.int64, device=x.device)
+    while True:
+        cand = new_candidates(capacity, x.device)
+        if fused_select or not outputs:
+            boxcar_snr(x, params, stats, scale=scale, zero=zero, snr=snr, widx=widx, cand=cand,
+                       cand_count=count, stream=stream)
+        else:
+            boxcar_snr(x, params, stats, scale=scale, zero=zero, snr=snr, widx=widx, stream=stream)
+            select_candidates(snr, widx, params, cand=cand, cand_count=count, stream=stream)
+        n = int(count.item())
+        if n <= cand.shape[0]:
+            break
+        capacity = n
+    return {"params": params, "stats": stats, "snr": snr, "widx": widx,
+            "cands": candidates_to_numpy(cand, n), "n_cands": n}

@@ -1,0 +1,298 @@
+// spd_abi.hip -- host side of the C ABI declared in include/spd.h:
+// argument validation (before anything is enqueued), launch planning and
+// the thread-local error string.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "spd_abi_internal.h"
+#include "spd_kernels.h"
+
+namespace spd {
+
+static thread_local std::string g_err;
+
+spd_status fail(spd_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+void clear_error() { g_err.clear(); }
+
+spd_status device_status(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return SPD_OK;
+    return fail(SPD_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int elem_size(int dtype) { return dtype == SPD_F32 ? 4 : dtype == SPD_F16 ? 2 : 1; }
+
+spd_status check_params(const spd_params* p)
+{
+    if (!p) return fail(SPD_E_INVALID, "params is NULL");
+    if (!p->widths) return fail(SPD_E_INVALID, "widths is NULL");
+    if (p->n_widths < 1 || p->n_widths > SPD_MAX_WIDTHS)
+        return fail(SPD_E_INVALID, "n_widths=%d outside [1, %d]", p->n_widths, SPD_MAX_WIDTHS);
+    if (p->widths[0] < 1) return fail(SPD_E_INVALID, "widths[0]=%d < 1", p->widths[0]);
+    for (int i = 1; i < p->n_widths; ++i)
+        if (p->widths[i] <= p->widths[i - 1])
+            return fail(SPD_E_INVALID, "widths not strictly increasing at index %d", i);
+    if (p->widths[p->n_widths - 1] > SPD_MAX_NMAX)
+        return fail(SPD_E_INVALID, "largest width %d > %d", p->widths[p->n_widths - 1], SPD_MAX_NMAX);
+    if (!isfinite(p->threshold)) return fail(SPD_E_INVALID, "threshold is not finite");
+    if (p->scope != SPD_SCOPE_ROW && p->scope != SPD_SCOPE_PLANE)
+        return fail(SPD_E_INVALID, "scope=%d unknown", p->scope);
+    if (p->sigma_mode < SPD_SIGMA_SQRTN || p->sigma_mode > SPD_SIGMA_LINEAR_LITERAL)
+        return fail(SPD_E_INVALID, "sigma_mode=%d unknown", p->sigma_mode);
+    if (p->sigma_mode == SPD_SIGMA_AUTO && !(isfinite(p->auto_kappa) && p->auto_kappa >= 0.f))
+        return fail(SPD_E_INVALID, "auto_kappa must be finite and >= 0");
+    return SPD_OK;
+}
+
+spd_status check_plane(const spd_plane* x, const spd_params* p)
+{
+    if (!x) return fail(SPD_E_INVALID, "plane is NULL");
+    if (!x->data) return fail(SPD_E_INVALID, "plane data is NULL");
+    if (x->dtype != SPD_F32 && x->dtype != SPD_F16 && x->dtype != SPD_U8)
+        return fail(SPD_E_INVALID, "dtype=%d unknown", x->dtype);
+    if (x->n_rows < 1) return fail(SPD_E_INVALID, "n_rows=%lld < 1", (long long)x->n_rows);
+    if (x->n_rows > 0x7fffffffLL) return fail(SPD_E_INVALID, "n_rows too large");
+    if (x->row_stride < x->n_cols)
+        return fail(SPD_E_INVALID, "row_stride=%lld < n_cols=%lld", (long long)x->row_stride,
+                    (long long)x->n_cols);
+    if (((uintptr_t)x->data) % (uintptr_t)elem_size(x->dtype))
+        return fail(SPD_E_INVALID, "data pointer not aligned to its element size");
+    if (x->dtype == SPD_U8 && (!x->row_scale || !x->row_zero))
+        return fail(SPD_E_INVALID, "U8 plane needs row_scale and row_zero");
+    const int nmax = p->widths[p->n_widths - 1];
+    if (x->n_cols < nmax)
+        return fail(SPD_E_INVALID, "n_cols=%lld shorter than the widest boxcar %d", (long long)x->n_cols, nmax);
+    return SPD_OK;
+}
+
+PlaneArg plane_arg(const spd_plane* x)
+{
+    PlaneArg a;
+    a.data = x->data;
+    a.n_rows = x->n_rows;
+    a.n_cols = x->n_cols;
+    a.stride = x->row_stride;
+    a.scale = x->row_scale;
+    a.zero = x->row_zero;
+    return a;
+}
+
+bool plane_vec_ok(const spd_plane* x)
+{
+    const uintptr_t need = 4u * (uintptr_t)elem_size(x->dtype);
+    return ((uintptr_t)x->data % need) == 0 && (x->row_stride % 4) == 0;
+}
+
+MsdLayout msd_layout(const spd_plane* x)
+{
+    MsdLayout m;
+    const int64_t total = x->n_rows * x->n_cols;
+    int64_t bc = 4096;
+    while (bc < 65536 && (total + bc - 1) / bc > 16384) bc <<= 1;
+    m.bc = bc;
+    m.nblk = (x->n_cols + bc - 1) / bc;
+    m.ws_bytes = (size_t)x->n_rows * (size_t)m.nblk * 6 * sizeof(double);
+    return m;
+}
+
+// Presummed LDS arrays and per-width steps for the boxcar kernel.
+bool build_width_plan(const spd_params* p, int X, WidthPlan& wp, BoxcarArgs& ba, int& waves)
+{
+    const int n = p->n_widths;
+    const int* W = p->widths;
+    memset(&wp, 0, sizeof wp);
+    wp.n = n;
+    wp.nmax = W[n - 1];
+    wp.n_groups = (n + kGroup - 1) / kGroup;
+    std::map<int, int> freq;
+    for (int i = 0; i < n; ++i) {
+        const int g = W[i] - (i ? W[i - 1] : 0);
+        if (g > 1) freq[g]++;
+    }
+    std::vector<std::pair<int, int>> cand(freq.begin(), freq.end());
+    std::sort(cand.begin(), cand.end(), [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+        return a.second != b.second ? a.second > b.second : a.first < b.first;
+    });
+    std::vector<int> gaps{1};
+    for (auto& c : cand)
+        if (c.second >= 2 && c.first <= 16 && (int)gaps.size() < kMaxArrays) gaps.push_back(c.first);
+
+    const int np = 64 * X + wp.nmax - 1;
+    const int npw = (np + 3) & ~3;
+    const size_t tables = (size_t)kTableFloats * 4;
+    const size_t lds_cap = 65536;
+    for (;;) {
+        const size_t per_wave = ((size_t)gaps.size() * npw + 64 * X) * 4;
+        if (tables + per_wave <= lds_cap || gaps.size() == 1) break;
+        gaps.pop_back();
+    }
+    const size_t per_wave = ((size_t)gaps.size() * npw + 64 * X) * 4;
+    if (tables + per_wave > lds_cap) return false;
+    waves = (int)std::min<size_t>(4, (lds_cap - tables) / per_wave);
+    wp.n_arr = (int)gaps.size();
+    for (int a = 0; a < wp.n_arr; ++a) wp.arr_gap[a] = gaps[a];
+    bool unit = true;
+    for (int i = 0; i < n; ++i) {
+        const int prev = i ? W[i - 1] : 0;
+        const int g = W[i] - prev;
+        int best = 0;
+        for (int a = 0; a < wp.n_arr; ++a)
+            if (g % gaps[a] == 0 && gaps[a] > gaps[best]) best = a;
+        const int cnt = g / gaps[best];
+        if (cnt != 1) unit = false;
+        wp.off[i] = (uint32_t)(best * npw + prev);
+        wp.cg[i] = (uint32_t)cnt | ((uint32_t)gaps[best] << 16);
+        wp.width[i] = (int16_t)W[i];
+    }
+    for (int i = n; i < wp.n_groups * kGroup; ++i) {     // padding reads the zero region
+        wp.off[i] = (uint32_t)(wp.n_arr * npw);
+        wp.cg[i] = 1u | (1u << 16);
+        wp.width[i] = (int16_t)W[n - 1];
+    }
+    wp.unit_counts = unit ? 1 : 0;
+    ba.npw = npw;
+    ba.wave_floats = wp.n_arr * npw + 64 * X;
+    return true;
+}
+
+}  // namespace spd
+
+using namespace spd;
+
+extern "C" {
+
+int spd_abi_version(void) { return SPD_ABI_VERSION; }
+
+const char* spd_last_error(void) { return g_err.c_str(); }
+
+size_t spd_workspace_bytes(const spd_plane* x, const spd_params* p)
+{
+    clear_error();
+    if (check_params(p) || check_plane(x, p)) return 0;
+    return msd_layout(x).ws_bytes;
+}
+
+spd_status msd_compute(const spd_plane* x, const spd_params* p, int64_t new_col_begin, int32_t accumulate,
+                       spd_msd_state* state, spd_row_stats* stats, void* workspace, size_t workspace_bytes,
+                       void* stream)
+{
+    clear_error();
+    spd_status st;
+    if ((st = check_params(p)) || (st = check_plane(x, p))) return st;
+    if (!stats) return fail(SPD_E_INVALID, "stats is NULL");
+    if (accumulate && !state) return fail(SPD_E_INVALID, "accumulate=1 needs a state");
+    if (new_col_begin < 0 || new_col_begin > x->n_cols)
+        return fail(SPD_E_INVALID, "new_col_begin=%lld outside [0, n_cols]", (long long)new_col_begin);
+    const MsdLayout m = msd_layout(x);
+    if (!workspace) return fail(SPD_E_INVALID, "workspace is NULL");
+    if (((uintptr_t)workspace) % 256) return fail(SPD_E_INVALID, "workspace not 256-byte aligned");
+    if (workspace_bytes < m.ws_bytes)
+        return fail(SPD_E_NOMEM, "workspace %zu bytes < %zu needed", workspace_bytes, m.ws_bytes);
+    const int nmax = p->widths[p->n_widths - 1];
+    const int64_t nout = x->n_cols - nmax + 1;
+    const bool need_y = p->sigma_mode != SPD_SIGMA_SQRTN;
+    if ((uint64_t)x->n_rows * (uint64_t)m.nblk > kMaxGrid)
+        return fail(SPD_E_UNSUPPORTED, "plane too large for one launch (%lld blocks)",
+                    (long long)(x->n_rows * m.nblk));
+    hipStream_t s = (hipStream_t)stream;
+    double* part = (double*)workspace;
+    hipError_t e = launch_msd(x->dtype, plane_arg(x), plane_vec_ok(x), need_y, new_col_begin, m.bc, m.nblk,
+                              nmax, nout, part, s);
+    if (e != hipSuccess) return device_status(e, "msd partial launch");
+    const bool plane = p->scope == SPD_SCOPE_PLANE;
+    const int64_t units = plane ? 1 : x->n_rows;
+    const int64_t per_unit = plane ? x->n_rows * m.nblk : m.nblk;
+    e = launch_finalize(part, units, per_unit, need_y, accumulate != 0, state, stats, nmax, p->sigma_mode,
+                        (double)p->auto_kappa, s);
+    return device_status(e, "msd finalize launch");
+}
+
+spd_status boxcar_snr(const spd_plane* x, const spd_params* p, const spd_row_stats* stats, float* snr_out,
+                      uint8_t* widx_out, int64_t out_stride, int64_t t_offset, spd_candidate* cand,
+                      int64_t cand_capacity, int64_t* cand_count, void* stream)
+{
+    clear_error();
+    spd_status st;
+    if ((st = check_params(p)) || (st = check_plane(x, p))) return st;
+    if (!stats) return fail(SPD_E_INVALID, "stats is NULL");
+    if (!snr_out && !widx_out && !cand) return fail(SPD_E_INVALID, "no output requested");
+    const int nmax = p->widths[p->n_widths - 1];
+    const int64_t nout = x->n_cols - nmax + 1;
+    if ((snr_out || widx_out) && out_stride < nout)
+        return fail(SPD_E_INVALID, "out_stride=%lld < %lld outputs per row", (long long)out_stride, (long long)nout);
+    if (cand && (!cand_count || cand_capacity < 0))
+        return fail(SPD_E_INVALID, "candidate list needs cand_count and capacity >= 0");
+    const int X = 4;
+    WidthPlan wp;
+    BoxcarArgs ba;
+    memset(&ba, 0, sizeof ba);
+    int waves = 4;
+    if (!build_width_plan(p, X, wp, ba, waves)) return fail(SPD_E_UNSUPPORTED, "width list does not fit in LDS");
+    ba.scope = p->scope;
+    ba.nout = nout;
+    ba.tiles_per_row = (nout + (int64_t)waves * 64 * X - 1) / ((int64_t)waves * 64 * X);
+    ba.snr = snr_out;
+    ba.widx = widx_out;
+    ba.out_stride = out_stride;
+    ba.t_offset = t_offset;
+    ba.cand = cand;
+    ba.cand_capacity = cand_capacity;
+    ba.cand_count = cand_count;
+    ba.threshold = p->threshold;
+    hipStream_t s = (hipStream_t)stream;
+    if (cand) {
+        hipError_t e = launch_zero_count(cand_count, s);
+        if (e != hipSuccess) return device_status(e, "count reset launch");
+    }
+    const uint64_t ntiles = (uint64_t)x->n_rows * (uint64_t)ba.tiles_per_row;
+    if (ntiles > kMaxGrid) return fail(SPD_E_UNSUPPORTED, "plane too large for one launch");
+    hipError_t e = launch_boxcar(x->dtype, plane_arg(x), plane_vec_ok(x), stats, ba, wp, X, waves, ntiles, s);
+    return device_status(e, "boxcar launch");
+}
+
+spd_status select_candidates(const float* snr, const uint8_t* widx, int64_t n_rows, int64_t n_out_cols,
+                             int64_t out_stride, const spd_params* p, int64_t t_offset, spd_candidate* cand,
+                             int64_t cand_capacity, int64_t* cand_count, void* stream)
+{
+    clear_error();
+    spd_status st;
+    if ((st = check_params(p))) return st;
+    if (!snr || !widx) return fail(SPD_E_INVALID, "snr and widx are required");
+    if (n_rows < 1 || n_out_cols < 0) return fail(SPD_E_INVALID, "bad shape");
+    if (out_stride < n_out_cols) return fail(SPD_E_INVALID, "out_stride < n_out_cols");
+    if (!cand || !cand_count || cand_capacity < 0)
+        return fail(SPD_E_INVALID, "candidate list needs cand, cand_count and capacity >= 0");
+    if ((uint64_t)n_rows * (uint64_t)((n_out_cols + 1023) / 1024) > kMaxGrid)
+        return fail(SPD_E_UNSUPPORTED, "output too large for one launch");
+    SelectArgs sa;
+    memset(&sa, 0, sizeof sa);
+    for (int i = 0; i < p->n_widths; ++i) sa.width[i] = p->widths[i];
+    sa.threshold = p->threshold;
+    sa.t_offset = t_offset;
+    sa.cand = cand;
+    sa.cand_capacity = cand_capacity;
+    sa.cand_count = cand_count;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_zero_count(cand_count, s);
+    if (e != hipSuccess) return device_status(e, "count reset launch");
+    e = launch_select(snr, widx, n_rows, n_out_cols, out_stride, sa, s);
+    return device_status(e, "select launch");
+}
+
+}  // extern "C"

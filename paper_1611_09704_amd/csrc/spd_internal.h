@@ -1,0 +1,76 @@
+// spd_internal.h -- types shared by the host and device parts of libspd.
+// (Library-internal; the public boundary is include/spd.h.)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "spd.h"
+
+namespace spd {
+
+constexpr int kWave = 64;           // CDNA wavefront
+constexpr int kGroup = 8;           // widths evaluated between two argmax bookkeeping steps
+constexpr int kMaxArrays = 4;       // presummed LDS arrays per wave (gap sizes)
+constexpr int kMaxWidthsPadded = SPD_MAX_WIDTHS + kGroup;
+// LDS floats of the boxcar kernel's coefficient and step tables, rounded up so
+// the per-wave arrays after them start on a 256-byte boundary.
+constexpr int kTableFloats = (3 * kMaxWidthsPadded + 63) / 64 * 64;
+constexpr uint64_t kMaxGrid = 0x7fffffffull;   // work-groups per launch (1-D grid)
+
+// How each width's boxcar is reached from the previous one:
+//   B_{w_i}(t) = B_{w_{i-1}}(t) + sum_{m < cnt_i} D_{g}[t + off_i + m*g]
+// where D_g[k] = sum_{j<g} x'[k+j] is a presummed array held in LDS (g = the
+// array's gap) and x' = x - mean.  For a list of contiguous or evenly spaced
+// widths every cnt_i is 1, so each width costs one LDS read and one add.
+struct WidthPlan {
+    int32_t n;              // |W|
+    int32_t nmax;           // largest width
+    int32_t n_groups;       // ceil(n / kGroup); entries past n repeat the last width
+    int32_t n_arr;          // presummed arrays in use (array 0 is x' itself, gap 1)
+    int32_t arr_gap[kMaxArrays];
+    int32_t unit_counts;    // 1 when every cnt_i == 1
+    int32_t reserved;
+    uint32_t off[kMaxWidthsPadded];    // element offset of the first read: array base + w_{i-1}
+    uint32_t cg[kMaxWidthsPadded];     // cnt | (gap << 16)
+    int16_t width[kMaxWidthsPadded];   // w_i (padded entries: the last width)
+};
+
+struct PlaneArg {
+    const void* data;
+    int64_t n_rows, n_cols, stride;
+    const float* scale;     // U8 only
+    const float* zero;      // U8 only
+};
+
+// Arguments of the boxcar/SNR kernel besides the plane and the width plan.
+struct BoxcarArgs {
+    int32_t scope;
+    int32_t npw;            // floats per presummed array (>= 64X + Nmax - 1, multiple of 4)
+    int32_t wave_floats;    // LDS floats per wave: n_arr*npw + 64X zero region
+    int32_t reserved;
+    int64_t tiles_per_row;
+    int64_t nout;           // valid starts per row
+    float* snr;
+    uint8_t* widx;
+    int64_t out_stride;
+    int64_t t_offset;
+    spd_candidate* cand;
+    int64_t cand_capacity;
+    int64_t* cand_count;
+    float threshold;
+    int32_t reserved2;
+};
+
+struct SelectArgs {
+    int32_t width[SPD_MAX_WIDTHS];
+    float threshold;
+    int32_t reserved;
+    int64_t t_offset;
+    spd_candidate* cand;
+    int64_t cand_capacity;
+    int64_t* cand_count;
+};
+
+}  // namespace spd

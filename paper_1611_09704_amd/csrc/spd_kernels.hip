@@ -1,0 +1,666 @@
+// spd_kernels.hip -- gfx950 kernels of the single-pulse detection path.
+//
+//   msd_x_kernel / msd_xy_kernel   per-block (n, T, S) partials, Sec. 2.1
+//   msd_finalize_kernel            FP64 merge across blocks and sigma_N
+//                                  coefficients, Sec. 2.1-2.2
+//   boxcar_kernel                  boxcars, SNR, highest SNR and its width,
+//                                  fused threshold, Sec. 2.3 / Algorithm 1,
+//                                  Sec. 2.4
+//   select_kernel                  threshold over stored outputs, Sec. 2.4
+//
+// The path is a streaming reduction plus a sliding-window scan: no dense
+// contraction, so everything is vector ALU + LDS work.  Loads are coalesced
+// along time (the contiguous axis), one work-group per (row, time block), with
+// an XCD-aware block order so that neighbouring time blocks of a row, whose
+// halos overlap, share an L2.
+#include "spd_kernels.h"
+
+namespace spd {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+
+// The dispatcher hands work-group i to XCD (i mod 8).  Renumber so that each
+// XCD receives one contiguous range of logical blocks.
+__device__ __forceinline__ uint64_t xcd_remap(uint64_t bid, uint64_t nb)
+{
+    const uint64_t nx = 8;
+    uint64_t xcd = bid % nx, local = bid / nx;
+    uint64_t per = nb / nx, extra = nb % nx;
+    uint64_t start = xcd * per + (xcd < extra ? xcd : extra);
+    return start + local;
+}
+
+template <int DT> struct Loader;
+
+template <> struct Loader<SPD_F32> {
+    const float* row;
+    __device__ Loader(const PlaneArg& p, int64_t r) : row((const float*)p.data + r * p.stride) {}
+    __device__ __forceinline__ float at(int64_t c) const { return row[c]; }
+    __device__ __forceinline__ float4 vec(int64_t c) const { return *(const float4*)(row + c); }
+};
+
+template <> struct Loader<SPD_F16> {
+    const __half* row;
+    __device__ Loader(const PlaneArg& p, int64_t r) : row((const __half*)p.data + r * p.stride) {}
+    __device__ __forceinline__ float at(int64_t c) const { return __half2float(row[c]); }
+    __device__ __forceinline__ float4 vec(int64_t c) const {
+        uint2 u = *(const uint2*)(row + c);
+        __half2 h0 = *reinterpret_cast<__half2*>(&u.x), h1 = *reinterpret_cast<__half2*>(&u.y);
+        float2 a = __half22float2(h0), b = __half22float2(h1);
+        return make_float4(a.x, a.y, b.x, b.y);
+    }
+};
+
+template <> struct Loader<SPD_U8> {
+    const uint8_t* row;
+    float sc, z;
+    __device__ Loader(const PlaneArg& p, int64_t r)
+        : row((const uint8_t*)p.data + r * p.stride), sc(p.scale[r]), z(p.zero[r]) {}
+    __device__ __forceinline__ float deq(uint32_t q) const { return sc * ((float)q - z); }
+    __device__ __forceinline__ float at(int64_t c) const { return deq(row[c]); }
+    __device__ __forceinline__ float4 vec(int64_t c) const {
+        uint32_t u = *(const uint32_t*)(row + c);
+        return make_float4(deq(u & 255u), deq((u >> 8) & 255u), deq((u >> 16) & 255u), deq(u >> 24));
+    }
+};
+
+template <int DT, bool VEC>
+__device__ __forceinline__ float4 load4(const Loader<DT>& ld, int64_t c)
+{
+    if (VEC) return ld.vec(c);
+    return make_float4(ld.at(c), ld.at(c + 1), ld.at(c + 2), ld.at(c + 3));
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 2.1: streaming and pairwise mean / deviation in FP32 inside a block
+// ---------------------------------------------------------------------------
+
+struct Msd { float n, T, S; };
+
+// Eq. (MSD04): merge the partial of samples 1..m (a) with m+1..m+n (b).
+// m/(n(m+n)) * (n/m*T_a - T_b)^2 is evaluated as (n*T_a - m*T_b)^2/(m*n*(m+n)).
+__device__ __forceinline__ Msd msd_merge(Msd a, Msd b)
+{
+    if (a.n == 0.f) return b;
+    if (b.n == 0.f) return a;
+    float d = b.n * a.T - a.n * b.T;
+    Msd o;
+    o.n = a.n + b.n;
+    o.T = a.T + b.T;
+    o.S = a.S + b.S + d * d / (a.n * b.n * o.n);
+    return o;
+}
+
+// Eq. (MSD03) for one more sample x_j: T_j = T_{j-1} + x_j,
+// S_j = S_{j-1} + (j*x_j - T_j)^2 / (j(j-1)).
+__device__ __forceinline__ void msd_add1(Msd& s, float x)
+{
+    s.n += 1.f;
+    s.T += x;
+    if (s.n > 1.f) {
+        float d = s.n * x - s.T;
+        s.S += d * d / (s.n * (s.n - 1.f));
+    }
+}
+
+// Four consecutive samples: Eq. (MSD03) over them with j = 1..4 (constant
+// coefficients 1/2, 1/6, 1/12), then Eq. (MSD04) into the running partial.
+__device__ __forceinline__ void msd_add4(Msd& s, float a, float b, float c, float d)
+{
+    float T2 = a + b, e2 = 2.f * b - T2;
+    float T3 = T2 + c, e3 = 3.f * c - T3;
+    float T4 = T3 + d, e4 = 4.f * d - T4;
+    float S4 = e2 * e2 * 0.5f + e3 * e3 * (1.f / 6.f) + e4 * e4 * (1.f / 12.f);
+    float dd = 4.f * s.T - s.n * T4;
+    float inc = s.n > 0.f ? dd * dd * __builtin_amdgcn_rcpf(s.n * 4.f * (s.n + 4.f)) : 0.f;
+    s.S = s.S + S4 + inc;
+    s.T += T4;
+    s.n += 4.f;
+}
+
+__device__ __forceinline__ Msd wave_merge(Msd v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        Msd o{__shfl_xor(v.n, off), __shfl_xor(v.T, off), __shfl_xor(v.S, off)};
+        v = (lane & off) ? msd_merge(o, v) : msd_merge(v, o);   // lower lanes first
+    }
+    return v;
+}
+
+// Merge every thread's partial into thread 0 (fixed order: lanes, then waves).
+__device__ __forceinline__ Msd block_merge(Msd v, Msd* scratch)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    v = wave_merge(v);
+    __syncthreads();
+    if (lane == 0) scratch[wave] = v;
+    __syncthreads();
+    Msd acc{0.f, 0.f, 0.f};
+    if (threadIdx.x == 0)
+        for (int w = 0; w < nw; ++w) acc = msd_merge(acc, scratch[w]);
+    return acc;
+}
+
+// Raw-sample partials of one (row, column block).  Columns [lo, hi) with
+// lo = max(block start, new_col_begin).  Samples are shifted by the row's
+// first sample K before the FP32 reduction; T is shifted back in FP64.
+template <int DT, bool VEC>
+__global__ __launch_bounds__(256) void msd_x_kernel(PlaneArg pl, int64_t ncb, int64_t bc,
+                                                    int64_t nblk, double* part)
+{
+    __shared__ Msd scratch[16];
+    const uint64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t r = (int64_t)(wg / (uint64_t)nblk), b = (int64_t)(wg % (uint64_t)nblk);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    Loader<DT> ld(pl, r);
+    const float K = ld.at(0);
+    const int64_t lo = max(b * bc, ncb), hi = min((b + 1) * bc, pl.n_cols);
+    Msd s{0.f, 0.f, 0.f};
+    if (lo < hi) {
+        const int64_t a = min((lo + 3) & ~(int64_t)3, hi);
+        const int64_t e = max(a, hi & ~(int64_t)3);
+        if (tid < a - lo) msd_add1(s, ld.at(lo + tid) - K);
+        if (tid < hi - e) { Msd t{0.f, 0.f, 0.f}; msd_add1(t, ld.at(e + tid) - K); s = msd_merge(s, t); }
+        int64_t c = a + 4 * (int64_t)tid;
+        const int64_t step = 4 * (int64_t)nt;
+        for (; c + 3 * step < e; c += 4 * step) {
+            float4 v0 = load4<DT, VEC>(ld, c), v1 = load4<DT, VEC>(ld, c + step);
+            float4 v2 = load4<DT, VEC>(ld, c + 2 * step), v3 = load4<DT, VEC>(ld, c + 3 * step);
+            msd_add4(s, v0.x - K, v0.y - K, v0.z - K, v0.w - K);
+            msd_add4(s, v1.x - K, v1.y - K, v1.z - K, v1.w - K);
+            msd_add4(s, v2.x - K, v2.y - K, v2.z - K, v2.w - K);
+            msd_add4(s, v3.x - K, v3.y - K, v3.z - K, v3.w - K);
+        }
+        for (; c < e; c += step) {
+            float4 v = load4<DT, VEC>(ld, c);
+            msd_add4(s, v.x - K, v.y - K, v.z - K, v.w - K);
+        }
+    }
+    Msd t = block_merge(s, scratch);
+    if (tid == 0) {
+        double* o = part + wg * 6;
+        o[0] = t.n;
+        o[1] = (double)t.T + (double)t.n * (double)K;
+        o[2] = t.S;
+        o[3] = 0.0; o[4] = 0.0; o[5] = 0.0;
+    }
+}
+
+// Exclusive prefix sum of buf[0..np) in place (np a multiple of the block
+// size); each thread owns a contiguous segment.
+__device__ void block_exclusive_scan(float* buf, int np, float* wsum)
+{
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
+    const int q = np / nt;
+    float* seg = buf + tid * q;
+    float tot = 0.f;
+    for (int j = 0; j < q; ++j) tot += seg[j];
+    float inc = tot;                                    // inclusive scan over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        float o = __shfl_up(inc, off);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    float base = inc - tot;
+    for (int w = 0; w < wave; ++w) base += wsum[w];
+    float run = base;
+    for (int j = 0; j < q; ++j) { float v = seg[j]; seg[j] = run; run += v; }
+    __syncthreads();
+}
+
+// Raw-sample partials plus the partials of the widest boxcar series
+// y(t) = sum_{k<nmax} x[t+k] for starts t in [block start, min(block end, nout)),
+// which give sigma_Nmax of Eq. (sd03).  The block is walked in sub-tiles of
+// TS starts; each sub-tile (plus its nmax-1 halo) is staged in LDS, shifted by
+// K, and turned into an exclusive prefix so that y(t) = E[t+nmax] - E[t].
+template <int DT>
+__global__ __launch_bounds__(256) void msd_xy_kernel(PlaneArg pl, int64_t ncb, int64_t bc,
+                                                     int64_t nblk, int32_t nmax, int64_t nout,
+                                                     int32_t np, double* part)
+{
+    constexpr int TS = 2048;
+    extern __shared__ float buf[];                      // [np] + [16] wave sums
+    float* wsum = buf + np;
+    __shared__ Msd scratch[16];
+    const uint64_t wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t r = (int64_t)(wg / (uint64_t)nblk), b = (int64_t)(wg % (uint64_t)nblk);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    Loader<DT> ld(pl, r);
+    const float K = ld.at(0);
+    const int64_t c0 = b * bc, c1 = min(c0 + bc, pl.n_cols);
+    const int64_t xlo = max(c0, ncb), yhi = min(c1, nout);
+    Msd sx{0.f, 0.f, 0.f}, sy{0.f, 0.f, 0.f};
+    for (int64_t u0 = c0; u0 < c1; u0 += TS) {
+        const int64_t u1 = min(u0 + TS, c1);
+        const int64_t avail = pl.n_cols - u0;
+        for (int k = tid; k < np; k += nt) buf[k] = (k < avail) ? ld.at(u0 + k) - K : 0.f;
+        __syncthreads();
+        // raw samples of this sub-tile, four per mini-batch where all are new
+        for (int k0 = 4 * tid; k0 < TS; k0 += 4 * nt) {
+            const int64_t c = u0 + k0;
+            if (c >= xlo && c + 3 < u1) {
+                float4 v = *(const float4*)(buf + k0);
+                msd_add4(sx, v.x, v.y, v.z, v.w);
+            } else {
+                for (int j = 0; j < 4; ++j)
+                    if (c + j >= xlo && c + j < u1) msd_add1(sx, buf[k0 + j]);
+            }
+        }
+        __syncthreads();
+        block_exclusive_scan(buf, np, wsum);
+        for (int k0 = 4 * tid; k0 < TS; k0 += 4 * nt) {
+            const int64_t t = u0 + k0;
+            float y0 = buf[k0 + nmax] - buf[k0], y1 = buf[k0 + 1 + nmax] - buf[k0 + 1];
+            float y2 = buf[k0 + 2 + nmax] - buf[k0 + 2], y3 = buf[k0 + 3 + nmax] - buf[k0 + 3];
+            if (t + 3 < yhi) {
+                msd_add4(sy, y0, y1, y2, y3);
+            } else {
+                float yy[4] = {y0, y1, y2, y3};
+                for (int j = 0; j < 4; ++j)
+                    if (t + j < yhi) msd_add1(sy, yy[j]);
+            }
+        }
+        __syncthreads();
+    }
+    Msd tx = block_merge(sx, scratch);
+    Msd ty = block_merge(sy, scratch);
+    if (tid == 0) {
+        double* o = part + wg * 6;
+        o[0] = tx.n;
+        o[1] = (double)tx.T + (double)tx.n * (double)K;
+        o[2] = tx.S;
+        o[3] = ty.n;
+        o[4] = (double)ty.T + (double)ty.n * (double)nmax * (double)K;
+        o[5] = ty.S;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 merge across blocks (Eq. MSD04) and the sigma_N coefficients
+// ---------------------------------------------------------------------------
+
+struct Msd64 { double n, T, S; };
+
+__device__ __forceinline__ Msd64 merge64(Msd64 a, Msd64 b)
+{
+    if (a.n == 0.0) return b;
+    if (b.n == 0.0) return a;
+    double d = (b.n / a.n) * a.T - b.T;
+    return Msd64{a.n + b.n, a.T + b.T, a.S + b.S + a.n / (b.n * (a.n + b.n)) * d * d};
+}
+
+// One work-group per unit.  Thread j merges a contiguous run of partials in
+// order, then a fixed binary tree merges the 256 runs.
+__global__ __launch_bounds__(256) void msd_finalize_kernel(const double* part, int64_t per_unit,
+                                                           int32_t need_y, int32_t accumulate,
+                                                           spd_msd_state* state, spd_row_stats* stats,
+                                                           int32_t nmax, int32_t mode, double kappa)
+{
+    __shared__ Msd64 sx[256], sy[256];
+    const int64_t u = blockIdx.x;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const double* p = part + (size_t)u * per_unit * 6;
+    const int64_t q = (per_unit + nt - 1) / nt;
+    Msd64 ax{0, 0, 0}, ay{0, 0, 0};
+    for (int64_t i = tid * q; i < min((int64_t)(tid + 1) * q, per_unit); ++i) {
+        ax = merge64(ax, Msd64{p[i * 6 + 0], p[i * 6 + 1], p[i * 6 + 2]});
+        ay = merge64(ay, Msd64{p[i * 6 + 3], p[i * 6 + 4], p[i * 6 + 5]});
+    }
+    sx[tid] = ax;
+    sy[tid] = ay;
+    __syncthreads();
+    for (int h = 1; h < nt; h <<= 1) {                 // merge neighbours: runs stay in order
+        if ((tid & (2 * h - 1)) == 0 && tid + h < nt) {
+            sx[tid] = merge64(sx[tid], sx[tid + h]);
+            sy[tid] = merge64(sy[tid], sy[tid + h]);
+        }
+        __syncthreads();
+    }
+    if (tid != 0) return;
+    Msd64 X = sx[0], Y = sy[0];
+    if (state) {
+        spd_msd_state st = state[u];
+        if (accumulate) {
+            X = merge64(Msd64{st.n, st.T, st.S}, X);
+            Y = merge64(Msd64{st.n_y, st.T_y, st.S_y}, Y);
+        }
+        state[u] = spd_msd_state{X.n, X.T, X.S, Y.n, Y.T, Y.S};
+    }
+    spd_row_stats o;
+    o.mean = X.n > 0.0 ? X.T / X.n : 0.0;
+    o.sigma = X.n > 0.0 ? sqrt(X.S / X.n) : 0.0;
+    o.sigma_nmax = (need_y && Y.n > 0.0) ? sqrt(Y.S / Y.n) : 0.0;
+    o.lin_coef = 0.0;
+    o.flags = 0;
+    o.reserved0 = 0;
+    if (!(o.sigma > 0.0)) {
+        o.flags |= SPD_FLAG_ZERO_VAR;
+    } else if (nmax > 1 && mode != SPD_SIGMA_SQRTN) {
+        double base = sqrt((double)nmax) * o.sigma;
+        double anchored = (o.sigma_nmax - base) / (double)(nmax - 1);
+        if (mode == SPD_SIGMA_LINEAR) {
+            o.lin_coef = anchored; o.flags |= SPD_FLAG_LINEAR;
+        } else if (mode == SPD_SIGMA_LINEAR_LITERAL) {
+            o.lin_coef = o.sigma_nmax / (double)(nmax - 1); o.flags |= SPD_FLAG_LINEAR;
+        } else if (mode == SPD_SIGMA_AUTO && o.sigma_nmax / base > 1.0 + kappa) {
+            o.lin_coef = anchored; o.flags |= SPD_FLAG_LINEAR;
+        }
+    }
+    stats[u] = o;
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 2.3, Algorithm 1: boxcars, SNR, highest SNR and first width; Sec. 2.4
+// ---------------------------------------------------------------------------
+//
+// One wave owns 64*X consecutive output starts of one row; lane l handles
+// starts t = l + 64*i (i < X) so that every LDS read is conflict free.  The
+// wave stages x' = x - mean for its window [t_w, t_w + 64X + Nmax - 1) in LDS
+// (array 0) plus presummed arrays D_g for other gaps, then walks the width list
+// once: B_{w_i} = B_{w_{i-1}} + D_g[t + w_{i-1}], s_i = B_{w_i} * (1/sigma_{w_i}).
+// Every boxcar sum is a running sum that starts at t, as in Algorithm 1, so
+// its rounding error grows with w only.
+//
+// The highest SNR and the first width reaching it are found exactly, with the
+// bookkeeping of Algorithm 1 (compare, then keep value and width) done once
+// per group of 8 widths on the group maximum: the first group whose maximum is
+// strictly larger than everything before it holds the first maximiser.  After
+// the list is done, that one group is evaluated again from the running sum
+// saved at its start (bit-identical operations) and the first width whose SNR
+// equals the maximum is taken.
+
+template <int DT, bool VEC, int X, bool UNIT>
+__global__ __launch_bounds__(256) void boxcar_kernel(PlaneArg pl, const spd_row_stats* stats,
+                                                     BoxcarArgs ba, WidthPlan wp)
+{
+    extern __shared__ float smem[];
+    float* coef = smem;                                              // [kMaxWidthsPadded]
+    uint32_t* toff = (uint32_t*)(coef + kMaxWidthsPadded);           // [kMaxWidthsPadded]
+    uint32_t* tcg = toff + kMaxWidthsPadded;                         // [kMaxWidthsPadded]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+    float* arrs = smem + kTableFloats + (size_t)wave * ba.wave_floats;
+
+    const uint64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t r = (int64_t)(tile / (uint64_t)ba.tiles_per_row);
+    const int64_t tt = (int64_t)(tile % (uint64_t)ba.tiles_per_row);
+    const int64_t tw = tt * (int64_t)(nwaves * 64 * X) + (int64_t)wave * 64 * X;
+
+    const spd_row_stats st = stats[ba.scope == SPD_SCOPE_ROW ? r : 0];
+    const bool zero_var = (st.flags & SPD_FLAG_ZERO_VAR) != 0;
+    const int npad = wp.n_groups * kGroup;
+    for (int i = tid; i < npad; i += blockDim.x) {
+        const int w = wp.width[i];
+        const double sw = sqrt((double)w) * st.sigma + (double)(w - 1) * st.lin_coef;
+        coef[i] = (zero_var || !(sw > 0.0)) ? 0.f : (float)(1.0 / sw);   // Eq. (sd02)/(sd03)
+        toff[i] = wp.off[i];
+        tcg[i] = wp.cg[i];
+    }
+    const float mu_hi = (float)st.mean;
+    const float mu_lo = (float)(st.mean - (double)mu_hi);
+
+    // stage x' for this wave's window; zero beyond the row and in the zero region
+    Loader<DT> ld(pl, r);
+    const int np = 64 * X + wp.nmax - 1;
+    for (int k = 4 * lane; k < ba.npw; k += 256) {
+        const int64_t c = tw + k;
+        float4 v;
+        if (c + 3 < pl.n_cols) {
+            v = load4<DT, VEC>(ld, c);
+        } else {
+            v.x = c < pl.n_cols ? ld.at(c) : 0.f;
+            v.y = c + 1 < pl.n_cols ? ld.at(c + 1) : 0.f;
+            v.z = c + 2 < pl.n_cols ? ld.at(c + 2) : 0.f;
+            v.w = c + 3 < pl.n_cols ? ld.at(c + 3) : 0.f;
+        }
+        v.x = c < pl.n_cols ? (v.x - mu_hi) - mu_lo : 0.f;
+        v.y = c + 1 < pl.n_cols ? (v.y - mu_hi) - mu_lo : 0.f;
+        v.z = c + 2 < pl.n_cols ? (v.z - mu_hi) - mu_lo : 0.f;
+        v.w = c + 3 < pl.n_cols ? (v.w - mu_hi) - mu_lo : 0.f;
+        *(float4*)(arrs + k) = v;
+    }
+    float* zero_region = arrs + (size_t)wp.n_arr * ba.npw;
+    for (int k = lane; k < 64 * X; k += 64) zero_region[k] = 0.f;
+    __syncthreads();
+    for (int a = 1; a < wp.n_arr; ++a) {
+        const int g = wp.arr_gap[a];
+        float* Da = arrs + (size_t)a * ba.npw;
+        for (int k = lane; k < ba.npw; k += 64) {
+            float s = 0.f;
+            if (k + g <= np) {
+                s = arrs[k];
+                for (int j = 1; j < g; ++j) s += arrs[k + j];
+            }
+            Da[k] = s;
+        }
+    }
+    __syncthreads();
+
+    float B[X], mx[X], Bg[X];
+    int gi[X];
+#pragma unroll
+    for (int i = 0; i < X; ++i) { B[i] = 0.f; mx[i] = -INFINITY; Bg[i] = 0.f; gi[i] = 0; }
+    const float* lbase = arrs + lane;
+
+    for (int g = 0; g < wp.n_groups; ++g) {
+        const int i0 = g * kGroup;
+        const float4 a03 = *(const float4*)(coef + i0);
+        const float4 a47 = *(const float4*)(coef + i0 + 4);
+        const float a[8] = {a03.x, a03.y, a03.z, a03.w, a47.x, a47.y, a47.z, a47.w};
+        uint32_t off[8], cg[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) { off[j] = wp.off[i0 + j]; cg[j] = wp.cg[i0 + j]; }
+#pragma unroll
+        for (int i = 0; i < X; ++i) {
+            float b = B[i];
+            float s[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                if (UNIT) {
+                    b = __fadd_rn(b, lbase[off[j] + 64 * i]);
+                } else {
+                    const uint32_t cnt = cg[j] & 0xffffu, gap = cg[j] >> 16;
+                    for (uint32_t m = 0; m < cnt; ++m) b = __fadd_rn(b, lbase[off[j] + m * gap + 64 * i]);
+                }
+                s[j] = __fmul_rn(b, a[j]);
+            }
+            const float gm = fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(s[0], s[1]), s[2]), s[3]), s[4]), s[5]),
+                                         s[6]), s[7]);
+            const bool c = gm > mx[i];
+            Bg[i] = c ? B[i] : Bg[i];
+            gi[i] = c ? g : gi[i];
+            mx[i] = c ? gm : mx[i];
+            B[i] = b;
+        }
+    }
+
+    // first width inside the winning group, then outputs and the fused threshold
+#pragma unroll
+    for (int i = 0; i < X; ++i) {
+        float b = Bg[i];
+        int idx = 0;
+        bool found = false;
+        const int i0 = gi[i] * kGroup;
+        for (int j = 0; j < kGroup; ++j) {
+            const int wi = i0 + j;
+            const uint32_t o = toff[wi], cgv = tcg[wi];
+            const uint32_t cnt = cgv & 0xffffu, gap = cgv >> 16;
+            for (uint32_t m = 0; m < cnt; ++m) b = __fadd_rn(b, lbase[o + m * gap + 64 * i]);
+            const float s = __fmul_rn(b, coef[wi]);
+            if (!found && s == mx[i]) { idx = wi; found = true; }
+        }
+        const int64_t t = tw + lane + 64 * i;
+        const bool valid = t < ba.nout;
+        if (valid && ba.snr) ba.snr[r * ba.out_stride + t] = mx[i];
+        if (valid && ba.widx) ba.widx[r * ba.out_stride + t] = (uint8_t)idx;
+        if (ba.cand) {
+            const bool pred = valid && mx[i] >= ba.threshold;
+            const uint64_t mask = __ballot(pred);
+            if (mask) {
+                const int cntw = __popcll(mask);
+                const int before = __popcll(mask & ((1ull << lane) - 1ull));
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd((unsigned long long*)ba.cand_count, (unsigned long long)cntw);
+                base = __shfl(base, 0);
+                if (pred) {
+                    const unsigned long long k = base + (unsigned long long)before;
+                    if (k < (unsigned long long)ba.cand_capacity) {
+                        spd_candidate cd;
+                        cd.row = (int32_t)r;
+                        cd.width = wp.width[idx];
+                        cd.t = t + ba.t_offset;
+                        cd.snr = mx[i];
+                        cd.reserved0 = 0;
+                        ba.cand[k] = cd;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Sec. 2.4 over stored snr / width-index arrays.
+__global__ __launch_bounds__(256) void select_kernel(const float* snr, const uint8_t* widx,
+                                                     int64_t ncols, int64_t stride, int64_t chunks,
+                                                     SelectArgs sa)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t r = (int64_t)(blk / (uint64_t)chunks), ch = (int64_t)(blk % (uint64_t)chunks);
+    for (int j = 0; j < 4; ++j) {
+        const int64_t t = ch * 1024 + j * 256 + threadIdx.x;
+        const bool valid = t < ncols;
+        const float s = valid ? snr[r * stride + t] : 0.f;
+        const bool pred = valid && s >= sa.threshold;
+        const uint64_t mask = __ballot(pred);
+        if (!mask) continue;
+        const int cntw = __popcll(mask);
+        const int before = __popcll(mask & ((1ull << lane) - 1ull));
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd((unsigned long long*)sa.cand_count, (unsigned long long)cntw);
+        base = __shfl(base, 0);
+        if (pred) {
+            const unsigned long long k = base + (unsigned long long)before;
+            if (k < (unsigned long long)sa.cand_capacity) {
+                spd_candidate cd;
+                cd.row = (int32_t)r;
+                cd.width = sa.width[widx[r * stride + t]];
+                cd.t = t + sa.t_offset;
+                cd.snr = s;
+                cd.reserved0 = 0;
+                sa.cand[k] = cd;
+            }
+        }
+    }
+}
+
+__global__ void zero_count_kernel(int64_t* p) { *p = 0; }
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+template <int DT>
+static hipError_t launch_msd_dt(const PlaneArg& pl, bool vec, bool with_y, int64_t ncb, int64_t bc,
+                                int64_t nblk, int32_t nmax, int64_t nout, double* part,
+                                hipStream_t s)
+{
+    const uint64_t nwg = (uint64_t)pl.n_rows * (uint64_t)nblk;
+    if (!with_y) {
+        if (vec) hipLaunchKernelGGL((msd_x_kernel<DT, true>), dim3(nwg), dim3(256), 0, s, pl, ncb, bc, nblk, part);
+        else hipLaunchKernelGGL((msd_x_kernel<DT, false>), dim3(nwg), dim3(256), 0, s, pl, ncb, bc, nblk, part);
+    } else {
+        const int32_t np = (int32_t)(((2048 + nmax) + 255) / 256 * 256);
+        const size_t lds = (size_t)(np + 16) * sizeof(float);
+        hipLaunchKernelGGL((msd_xy_kernel<DT>), dim3(nwg), dim3(256), lds, s, pl, ncb, bc, nblk, nmax,
+                           nout, np, part);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_msd(int dtype, const PlaneArg& pl, bool vec, bool with_y, int64_t ncb, int64_t bc,
+                      int64_t nblk, int32_t nmax, int64_t nout, double* part, hipStream_t s)
+{
+    switch (dtype) {
+    case SPD_F32: return launch_msd_dt<SPD_F32>(pl, vec, with_y, ncb, bc, nblk, nmax, nout, part, s);
+    case SPD_F16: return launch_msd_dt<SPD_F16>(pl, vec, with_y, ncb, bc, nblk, nmax, nout, part, s);
+    default: return launch_msd_dt<SPD_U8>(pl, vec, with_y, ncb, bc, nblk, nmax, nout, part, s);
+    }
+}
+
+hipError_t launch_finalize(const double* part, int64_t n_units, int64_t per_unit, bool need_y,
+                           bool accumulate, spd_msd_state* state, spd_row_stats* stats, int32_t nmax,
+                           int32_t mode, double kappa, hipStream_t s)
+{
+    hipLaunchKernelGGL(msd_finalize_kernel, dim3((uint32_t)n_units), dim3(256), 0, s, part, per_unit,
+                       (int32_t)need_y, (int32_t)accumulate, state, stats, nmax, mode, kappa);
+    return hipGetLastError();
+}
+
+size_t boxcar_lds_bytes(int waves, const BoxcarArgs& ba)
+{
+    return (size_t)kTableFloats * 4 + (size_t)waves * ba.wave_floats * 4;
+}
+
+template <int DT, int X, bool UNIT>
+static hipError_t launch_boxcar_x(const PlaneArg& pl, bool vec, const spd_row_stats* stats,
+                                  const BoxcarArgs& ba, const WidthPlan& wp, int waves, uint64_t ntiles,
+                                  hipStream_t s)
+{
+    const size_t lds = boxcar_lds_bytes(waves, ba);
+    if (vec) {
+        auto k = boxcar_kernel<DT, true, X, UNIT>;
+        if (lds > 65536) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k, dim3(ntiles), dim3(64 * waves), lds, s, pl, stats, ba, wp);
+    } else {
+        auto k = boxcar_kernel<DT, false, X, UNIT>;
+        if (lds > 65536) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k, dim3(ntiles), dim3(64 * waves), lds, s, pl, stats, ba, wp);
+    }
+    return hipGetLastError();
+}
+
+template <int DT>
+static hipError_t launch_boxcar_dt(const PlaneArg& pl, bool vec, const spd_row_stats* stats,
+                                   const BoxcarArgs& ba, const WidthPlan& wp, int X, int waves,
+                                   uint64_t ntiles, hipStream_t s)
+{
+    const bool unit = wp.unit_counts != 0;
+    (void)X;
+    return unit ? launch_boxcar_x<DT, 4, true>(pl, vec, stats, ba, wp, waves, ntiles, s)
+                : launch_boxcar_x<DT, 4, false>(pl, vec, stats, ba, wp, waves, ntiles, s);
+}
+
+hipError_t launch_boxcar(int dtype, const PlaneArg& pl, bool vec, const spd_row_stats* stats,
+                         const BoxcarArgs& ba, const WidthPlan& wp, int X, int waves, uint64_t ntiles,
+                         hipStream_t s)
+{
+    switch (dtype) {
+    case SPD_F32: return launch_boxcar_dt<SPD_F32>(pl, vec, stats, ba, wp, X, waves, ntiles, s);
+    case SPD_F16: return launch_boxcar_dt<SPD_F16>(pl, vec, stats, ba, wp, X, waves, ntiles, s);
+    default: return launch_boxcar_dt<SPD_U8>(pl, vec, stats, ba, wp, X, waves, ntiles, s);
+    }
+}
+
+hipError_t launch_zero_count(int64_t* count, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_count_kernel, dim3(1), dim3(1), 0, s, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const float* snr, const uint8_t* widx, int64_t nrows, int64_t ncols,
+                         int64_t stride, const SelectArgs& sa, hipStream_t s)
+{
+    const int64_t chunks = (ncols + 1023) / 1024;
+    const uint64_t nb = (uint64_t)nrows * (uint64_t)chunks;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(select_kernel, dim3(nb), dim3(256), 0, s, snr, widx, ncols, stride, chunks, sa);
+    return hipGetLastError();
+}
+
+}  // namespace spd

@@ -1,0 +1,106 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+declared in include/spd.h, and rejects bad arguments before touching a GPU
+(validation happens before any HIP call, so these run without one)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1611_09704_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        from paper_1611_09704_amd import build
+        build.build()
+    return B.load()
+
+
+def declared_functions():
+    names = []
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if not h.endswith(".h"):
+            continue
+        src = open(os.path.join(ROOT, "include", h)).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w \*]*?\b([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M):
+            line = src[m.start():src.find("\n", m.start())]
+            if line.startswith("typedef") or line.startswith("#"):
+                continue
+            names.append(m.group(1))
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert {"msd_compute", "boxcar_snr", "select_candidates", "spd_last_error",
+            "spd_abi_version", "spd_workspace_bytes"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), "libspd.so does not export %s" % n
+    assert lib.spd_abi_version() == 1
+
+
+FAKE = 0x10000  # never dereferenced: validation rejects first
+
+
+def _plane(dtype=B.SPD_F32, rows=4, cols=1000, stride=1000, data=FAKE, scale=None, zero=None):
+    return B.SpdPlane(data, dtype, 0, rows, cols, stride, scale, zero)
+
+
+def _err(lib):
+    return lib.spd_last_error().decode()
+
+
+@pytest.mark.parametrize("widths,msg", [([], "n_widths"), ([0, 1], "widths[0]"), ([1, 3, 3], "strictly"),
+                                        ([1, 5000], "largest width"), (list(range(1, 258)), "n_widths")])
+def test_params_validation(lib, widths, msg):
+    p = B.Params(widths or [1], 5.0)
+    if not widths:
+        p.c.n_widths = 0
+    pl = _plane()
+    rc = lib.msd_compute(ctypes.byref(pl), ctypes.byref(p.c), 0, 0, None, FAKE, FAKE, 1 << 20, None)
+    assert rc == 1 and msg in _err(lib)
+
+
+def test_plane_validation(lib):
+    p = B.Params([1, 2, 4, 8], 5.0)
+    cases = [
+        (_plane(rows=0), "n_rows"),
+        (_plane(cols=1000, stride=999), "row_stride"),
+        (_plane(cols=7, stride=7), "shorter"),
+        (_plane(dtype=7), "dtype"),
+        (_plane(data=0), "data"),
+        (_plane(dtype=B.SPD_F32, data=FAKE + 2), "aligned"),
+        (_plane(dtype=B.SPD_U8), "row_scale"),
+    ]
+    for pl, msg in cases:
+        rc = lib.boxcar_snr(ctypes.byref(pl), ctypes.byref(p.c), FAKE, FAKE, FAKE, 1000, 0, None, 0, None, None)
+        assert rc == 1, msg
+        assert msg in _err(lib)
+
+
+def test_call_validation(lib):
+    p = B.Params([1, 2, 4, 8], 5.0)
+    pl = _plane()
+    assert lib.boxcar_snr(ctypes.byref(pl), ctypes.byref(p.c), FAKE, None, None, 0, 0, None, 0, None, None) == 1
+    assert "no output" in _err(lib)
+    assert lib.boxcar_snr(ctypes.byref(pl), ctypes.byref(p.c), FAKE, FAKE, None, 10, 0, None, 0, None, None) == 1
+    assert "out_stride" in _err(lib)
+    assert lib.boxcar_snr(ctypes.byref(pl), ctypes.byref(p.c), None, FAKE, None, 1000, 0, None, 0, None, None) == 1
+    assert lib.boxcar_snr(ctypes.byref(pl), ctypes.byref(p.c), FAKE, None, None, 0, 0, FAKE, 10, None, None) == 1
+    assert "cand_count" in _err(lib)
+    ws = lib.spd_workspace_bytes(ctypes.byref(pl), ctypes.byref(p.c))
+    assert ws > 0 and ws % 48 == 0
+    assert lib.msd_compute(ctypes.byref(pl), ctypes.byref(p.c), 0, 0, None, FAKE, FAKE, ws - 1, None) == 3
+    assert lib.msd_compute(ctypes.byref(pl), ctypes.byref(p.c), 0, 1, None, FAKE, FAKE, ws, None) == 1
+    assert "accumulate" in _err(lib)
+    assert lib.msd_compute(ctypes.byref(pl), ctypes.byref(p.c), 1001, 0, None, FAKE, FAKE, ws, None) == 1
+    assert lib.msd_compute(ctypes.byref(pl), ctypes.byref(p.c), 0, 0, None, FAKE, FAKE + 8, ws, None) == 1
+    assert lib.select_candidates(FAKE, FAKE, 4, 100, 50, ctypes.byref(p.c), 0, FAKE, 10, FAKE, None) == 1
+    bad = B.Params([1, 2], float("nan"))
+    assert lib.select_candidates(FAKE, FAKE, 4, 100, 100, ctypes.byref(bad.c), 0, FAKE, 10, FAKE, None) == 1
+    assert "threshold" in _err(lib)
