@@ -138,11 +138,11 @@ bool build_width_plan(const spd_params* p, int X, WidthPlan& wp, BoxcarArgs& ba,
     const size_t tables = (size_t)kTableFloats * 4;
     const size_t lds_cap = 65536;
     for (;;) {
-        const size_t per_wave = ((size_t)gaps.size() * npw + 64 * X) * 4;
+        const size_t per_wave = (size_t)gaps.size() * npw * 4;
         if (tables + per_wave <= lds_cap || gaps.size() == 1) break;
         gaps.pop_back();
     }
-    const size_t per_wave = ((size_t)gaps.size() * npw + 64 * X) * 4;
+    const size_t per_wave = (size_t)gaps.size() * npw * 4;
     if (tables + per_wave > lds_cap) return false;
     waves = (int)std::min<size_t>(4, (lds_cap - tables) / per_wave);
     wp.n_arr = (int)gaps.size();
@@ -160,14 +160,9 @@ bool build_width_plan(const spd_params* p, int X, WidthPlan& wp, BoxcarArgs& ba,
         wp.cg[i] = (uint32_t)cnt | ((uint32_t)gaps[best] << 16);
         wp.width[i] = (int16_t)W[i];
     }
-    for (int i = n; i < wp.n_groups * kGroup; ++i) {     // padding reads the zero region
-        wp.off[i] = (uint32_t)(wp.n_arr * npw);
-        wp.cg[i] = 1u | (1u << 16);
-        wp.width[i] = (int16_t)W[n - 1];
-    }
     wp.unit_counts = unit ? 1 : 0;
     ba.npw = npw;
-    ba.wave_floats = wp.n_arr * npw + 64 * X;
+    ba.wave_floats = wp.n_arr * npw;
     return true;
 }
 
@@ -238,7 +233,7 @@ spd_status boxcar_snr(const spd_plane* x, const spd_params* p, const spd_row_sta
         return fail(SPD_E_INVALID, "out_stride=%lld < %lld outputs per row", (long long)out_stride, (long long)nout);
     if (cand && (!cand_count || cand_capacity < 0))
         return fail(SPD_E_INVALID, "candidate list needs cand_count and capacity >= 0");
-    const int X = 4;
+    const int X = kOutPerLane;
     WidthPlan wp;
     BoxcarArgs ba;
     memset(&ba, 0, sizeof ba);

@@ -13,6 +13,7 @@ namespace spd {
 constexpr int kWave = 64;           // CDNA wavefront
 constexpr int kGroup = 8;           // widths evaluated between two argmax bookkeeping steps
 constexpr int kMaxArrays = 4;       // presummed LDS arrays per wave (gap sizes)
+constexpr int kOutPerLane = 8;      // boxcar outputs per lane (strided by 64)
 constexpr int kMaxWidthsPadded = SPD_MAX_WIDTHS + kGroup;
 // LDS floats of the boxcar kernel's coefficient and step tables, rounded up so
 // the per-wave arrays after them start on a 256-byte boundary.
@@ -27,14 +28,14 @@ constexpr uint64_t kMaxGrid = 0x7fffffffull;   // work-groups per launch (1-D gr
 struct WidthPlan {
     int32_t n;              // |W|
     int32_t nmax;           // largest width
-    int32_t n_groups;       // ceil(n / kGroup); entries past n repeat the last width
+    int32_t n_groups;       // ceil(n / kGroup); the last group may be partial
     int32_t n_arr;          // presummed arrays in use (array 0 is x' itself, gap 1)
     int32_t arr_gap[kMaxArrays];
     int32_t unit_counts;    // 1 when every cnt_i == 1
     int32_t reserved;
     uint32_t off[kMaxWidthsPadded];    // element offset of the first read: array base + w_{i-1}
     uint32_t cg[kMaxWidthsPadded];     // cnt | (gap << 16)
-    int16_t width[kMaxWidthsPadded];   // w_i (padded entries: the last width)
+    int16_t width[kMaxWidthsPadded];   // w_i
 };
 
 struct PlaneArg {
@@ -48,7 +49,7 @@ struct PlaneArg {
 struct BoxcarArgs {
     int32_t scope;
     int32_t npw;            // floats per presummed array (>= 64X + Nmax - 1, multiple of 4)
-    int32_t wave_floats;    // LDS floats per wave: n_arr*npw + 64X zero region
+    int32_t wave_floats;    // LDS floats per wave: n_arr*npw
     int32_t reserved;
     int64_t tiles_per_row;
     int64_t nout;           // valid starts per row

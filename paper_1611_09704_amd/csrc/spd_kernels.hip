@@ -145,9 +145,28 @@ __device__ __forceinline__ Msd block_merge(Msd v, Msd* scratch)
     return acc;
 }
 
+// Shift applied before the FP32 reduction: the mean of the row's first (up to)
+// block-size samples, so shifted samples -- and the widest-boxcar series built from
+// them -- have a mean small against their spread.  Any constant gives the same
+// statistics in exact arithmetic; T is shifted back in FP64.
+template <int DT>
+__device__ float pilot_shift(const Loader<DT>& ld, int64_t ncols, float* scratch)
+{
+    const int tid = threadIdx.x;
+    const int64_t n = ncols < (int64_t)blockDim.x ? ncols : (int64_t)blockDim.x;
+    float v = tid < n ? ld.at(tid) : 0.f;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((tid & 63) == 0) scratch[tid >> 6] = v;
+    __syncthreads();
+    float sum = 0.f;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += scratch[w];
+    return sum / (float)n;
+}
+
 // Raw-sample partials of one (row, column block).  Columns [lo, hi) with
-// lo = max(block start, new_col_begin).  Samples are shifted by the row's
-// first sample K before the FP32 reduction; T is shifted back in FP64.
+// lo = max(block start, new_col_begin).
 template <int DT, bool VEC>
 __global__ __launch_bounds__(256) void msd_x_kernel(PlaneArg pl, int64_t ncb, int64_t bc,
                                                     int64_t nblk, double* part)
@@ -156,8 +175,9 @@ __global__ __launch_bounds__(256) void msd_x_kernel(PlaneArg pl, int64_t ncb, in
     const uint64_t wg = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t r = (int64_t)(wg / (uint64_t)nblk), b = (int64_t)(wg % (uint64_t)nblk);
     const int tid = threadIdx.x, nt = blockDim.x;
+    __shared__ float pscratch[16];
     Loader<DT> ld(pl, r);
-    const float K = ld.at(0);
+    const float K = pilot_shift<DT>(ld, pl.n_cols, pscratch);
     const int64_t lo = max(b * bc, ncb), hi = min((b + 1) * bc, pl.n_cols);
     Msd s{0.f, 0.f, 0.f};
     if (lo < hi) {
@@ -190,83 +210,108 @@ __global__ __launch_bounds__(256) void msd_x_kernel(PlaneArg pl, int64_t ncb, in
     }
 }
 
-// Exclusive prefix sum of buf[0..np) in place (np a multiple of the block
-// size); each thread owns a contiguous segment.
-__device__ void block_exclusive_scan(float* buf, int np, float* wsum)
+// Inclusive prefix sum across the 64 lanes of a wave with DPP row shifts and
+// row broadcasts (Hillis-Steele inside each row of 16, then across rows).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_mov(float v)
 {
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
-    const int q = np / nt;
-    float* seg = buf + tid * q;
-    float tot = 0.f;
-    for (int j = 0; j < q; ++j) tot += seg[j];
-    float inc = tot;                                    // inclusive scan over the wave
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        float o = __shfl_up(inc, off);
-        if (lane >= off) inc += o;
-    }
-    if (lane == 63) wsum[wave] = inc;
-    __syncthreads();
-    float base = inc - tot;
-    for (int w = 0; w < wave; ++w) base += wsum[w];
-    float run = base;
-    for (int j = 0; j < q; ++j) { float v = seg[j]; seg[j] = run; run += v; }
-    __syncthreads();
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
+}
+
+__device__ __forceinline__ float wave_inclusive_scan(float x)
+{
+    x += dpp_mov<0x111, 0xf>(x);   // row_shr:1
+    x += dpp_mov<0x112, 0xf>(x);   // row_shr:2
+    x += dpp_mov<0x114, 0xf>(x);   // row_shr:4
+    x += dpp_mov<0x118, 0xf>(x);   // row_shr:8
+    x += dpp_mov<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+    x += dpp_mov<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+// Orders LDS writes and reads between lanes of one wave.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Raw-sample partials plus the partials of the widest boxcar series
 // y(t) = sum_{k<nmax} x[t+k] for starts t in [block start, min(block end, nout)),
-// which give sigma_Nmax of Eq. (sd03).  The block is walked in sub-tiles of
-// TS starts; each sub-tile (plus its nmax-1 halo) is staged in LDS, shifted by
-// K, and turned into an exclusive prefix so that y(t) = E[t+nmax] - E[t].
-template <int DT>
+// which give sigma_Nmax of Eq. (sd03).  Each wave walks its own sub-tiles of
+// TSW starts: it loads the sub-tile plus its nmax-1 halo (shifted by K),
+// forms the exclusive prefix E in its own LDS region with a wave scan, and
+// takes y(t) = E[t+nmax] - E[t].  The same loads feed the raw statistics.
+template <int DT, bool VEC>
 __global__ __launch_bounds__(256) void msd_xy_kernel(PlaneArg pl, int64_t ncb, int64_t bc,
                                                      int64_t nblk, int32_t nmax, int64_t nout,
-                                                     int32_t np, double* part)
+                                                     int32_t npw, double* part)
 {
-    constexpr int TS = 2048;
-    extern __shared__ float buf[];                      // [np] + [16] wave sums
-    float* wsum = buf + np;
+    constexpr int TSW = 512;
+    extern __shared__ float lds[];                      // [waves][npw]
     __shared__ Msd scratch[16];
+    __shared__ float pscratch[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    float* E = lds + (size_t)wave * npw;
     const uint64_t wg = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t r = (int64_t)(wg / (uint64_t)nblk), b = (int64_t)(wg % (uint64_t)nblk);
-    const int tid = threadIdx.x, nt = blockDim.x;
     Loader<DT> ld(pl, r);
-    const float K = ld.at(0);
+    const float K = pilot_shift<DT>(ld, pl.n_cols, pscratch);
     const int64_t c0 = b * bc, c1 = min(c0 + bc, pl.n_cols);
     const int64_t xlo = max(c0, ncb), yhi = min(c1, nout);
+    const int nrow = npw / 256;
     Msd sx{0.f, 0.f, 0.f}, sy{0.f, 0.f, 0.f};
-    for (int64_t u0 = c0; u0 < c1; u0 += TS) {
-        const int64_t u1 = min(u0 + TS, c1);
-        const int64_t avail = pl.n_cols - u0;
-        for (int k = tid; k < np; k += nt) buf[k] = (k < avail) ? ld.at(u0 + k) - K : 0.f;
-        __syncthreads();
-        // raw samples of this sub-tile, four per mini-batch where all are new
-        for (int k0 = 4 * tid; k0 < TS; k0 += 4 * nt) {
-            const int64_t c = u0 + k0;
-            if (c >= xlo && c + 3 < u1) {
-                float4 v = *(const float4*)(buf + k0);
-                msd_add4(sx, v.x, v.y, v.z, v.w);
+    for (int64_t u0 = c0 + (int64_t)wave * TSW; u0 < c1; u0 += (int64_t)nw * TSW) {
+        const int64_t u1 = min(u0 + TSW, c1);
+        float carry = 0.f;
+        float4 ekeep[TSW / 256];
+        for (int m = 0; m < nrow; ++m) {
+            const int p = 256 * m + 4 * lane;
+            const int64_t c = u0 + p;
+            float4 v;
+            if (c + 3 < pl.n_cols) {
+                v = load4<DT, VEC>(ld, c);
+                v.x -= K; v.y -= K; v.z -= K; v.w -= K;
             } else {
-                for (int j = 0; j < 4; ++j)
-                    if (c + j >= xlo && c + j < u1) msd_add1(sx, buf[k0 + j]);
+                v.x = c < pl.n_cols ? ld.at(c) - K : 0.f;
+                v.y = c + 1 < pl.n_cols ? ld.at(c + 1) - K : 0.f;
+                v.z = c + 2 < pl.n_cols ? ld.at(c + 2) - K : 0.f;
+                v.w = c + 3 < pl.n_cols ? ld.at(c + 3) - K : 0.f;
             }
+            if (p < TSW) {
+                if (c >= xlo && c + 3 < u1) {
+                    msd_add4(sx, v.x, v.y, v.z, v.w);
+                } else {
+                    const float vv[4] = {v.x, v.y, v.z, v.w};
+                    for (int j = 0; j < 4; ++j)
+                        if (c + j >= xlo && c + j < u1) msd_add1(sx, vv[j]);
+                }
+            }
+            const float l0 = v.x, l1 = l0 + v.y, l2 = l1 + v.z, l3 = l2 + v.w;
+            const float inc = wave_inclusive_scan(l3);
+            const float ex = (inc - l3) + carry;
+            carry += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(inc), 63));
+            const float4 e = make_float4(ex, ex + l0, ex + l1, ex + l2);
+            *(float4*)(E + p) = e;
+            if (m < TSW / 256) ekeep[m] = e;
         }
-        __syncthreads();
-        block_exclusive_scan(buf, np, wsum);
-        for (int k0 = 4 * tid; k0 < TS; k0 += 4 * nt) {
-            const int64_t t = u0 + k0;
-            float y0 = buf[k0 + nmax] - buf[k0], y1 = buf[k0 + 1 + nmax] - buf[k0 + 1];
-            float y2 = buf[k0 + 2 + nmax] - buf[k0 + 2], y3 = buf[k0 + 3 + nmax] - buf[k0 + 3];
+        wave_sync();
+#pragma unroll
+        for (int m = 0; m < TSW / 256; ++m) {
+            const int p = 256 * m + 4 * lane;
+            const int64_t t = u0 + p;
+            const float y0 = E[p + nmax] - ekeep[m].x, y1 = E[p + 1 + nmax] - ekeep[m].y;
+            const float y2 = E[p + 2 + nmax] - ekeep[m].z, y3 = E[p + 3 + nmax] - ekeep[m].w;
             if (t + 3 < yhi) {
                 msd_add4(sy, y0, y1, y2, y3);
             } else {
-                float yy[4] = {y0, y1, y2, y3};
+                const float yy[4] = {y0, y1, y2, y3};
                 for (int j = 0; j < 4; ++j)
                     if (t + j < yhi) msd_add1(sy, yy[j]);
             }
         }
-        __syncthreads();
+        wave_sync();
     }
     Msd tx = block_merge(sx, scratch);
     Msd ty = block_merge(sy, scratch);
@@ -380,9 +425,9 @@ __global__ __launch_bounds__(256) void boxcar_kernel(PlaneArg pl, const spd_row_
                                                      BoxcarArgs ba, WidthPlan wp)
 {
     extern __shared__ float smem[];
-    float* coef = smem;                                              // [kMaxWidthsPadded]
-    uint32_t* toff = (uint32_t*)(coef + kMaxWidthsPadded);           // [kMaxWidthsPadded]
-    uint32_t* tcg = toff + kMaxWidthsPadded;                         // [kMaxWidthsPadded]
+    float* coef = smem;                                              // 1/sigma_w; NaN past n
+    uint32_t* toff = (uint32_t*)(coef + kMaxWidthsPadded);           // read offsets; 0 past n
+    uint32_t* tcg = toff + kMaxWidthsPadded;                         // cnt | gap<<16; 0 past n
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
     float* arrs = smem + kTableFloats + (size_t)wave * ba.wave_floats;
 
@@ -393,18 +438,23 @@ __global__ __launch_bounds__(256) void boxcar_kernel(PlaneArg pl, const spd_row_
 
     const spd_row_stats st = stats[ba.scope == SPD_SCOPE_ROW ? r : 0];
     const bool zero_var = (st.flags & SPD_FLAG_ZERO_VAR) != 0;
-    const int npad = wp.n_groups * kGroup;
-    for (int i = tid; i < npad; i += blockDim.x) {
-        const int w = wp.width[i];
-        const double sw = sqrt((double)w) * st.sigma + (double)(w - 1) * st.lin_coef;
-        coef[i] = (zero_var || !(sw > 0.0)) ? 0.f : (float)(1.0 / sw);   // Eq. (sd02)/(sd03)
-        toff[i] = wp.off[i];
-        tcg[i] = wp.cg[i];
+    for (int i = tid; i < kMaxWidthsPadded; i += blockDim.x) {
+        if (i < wp.n) {
+            const int w = wp.width[i];
+            const double sw = sqrt((double)w) * st.sigma + (double)(w - 1) * st.lin_coef;
+            coef[i] = (zero_var || !(sw > 0.0)) ? 0.f : (float)(1.0 / sw);   // Eq. (sd02)/(sd03)
+            toff[i] = wp.off[i];
+            tcg[i] = wp.cg[i];
+        } else {
+            coef[i] = __int_as_float(0x7fc00000);
+            toff[i] = 0;
+            tcg[i] = 0;
+        }
     }
     const float mu_hi = (float)st.mean;
     const float mu_lo = (float)(st.mean - (double)mu_hi);
 
-    // stage x' for this wave's window; zero beyond the row and in the zero region
+    // stage x' = x - mean for this wave's window; zero beyond the row
     Loader<DT> ld(pl, r);
     const int np = 64 * X + wp.nmax - 1;
     for (int k = 4 * lane; k < ba.npw; k += 256) {
@@ -412,22 +462,20 @@ __global__ __launch_bounds__(256) void boxcar_kernel(PlaneArg pl, const spd_row_
         float4 v;
         if (c + 3 < pl.n_cols) {
             v = load4<DT, VEC>(ld, c);
+            v.x = (v.x - mu_hi) - mu_lo;
+            v.y = (v.y - mu_hi) - mu_lo;
+            v.z = (v.z - mu_hi) - mu_lo;
+            v.w = (v.w - mu_hi) - mu_lo;
         } else {
-            v.x = c < pl.n_cols ? ld.at(c) : 0.f;
-            v.y = c + 1 < pl.n_cols ? ld.at(c + 1) : 0.f;
-            v.z = c + 2 < pl.n_cols ? ld.at(c + 2) : 0.f;
-            v.w = c + 3 < pl.n_cols ? ld.at(c + 3) : 0.f;
+            v.x = c < pl.n_cols ? (ld.at(c) - mu_hi) - mu_lo : 0.f;
+            v.y = c + 1 < pl.n_cols ? (ld.at(c + 1) - mu_hi) - mu_lo : 0.f;
+            v.z = c + 2 < pl.n_cols ? (ld.at(c + 2) - mu_hi) - mu_lo : 0.f;
+            v.w = c + 3 < pl.n_cols ? (ld.at(c + 3) - mu_hi) - mu_lo : 0.f;
         }
-        v.x = c < pl.n_cols ? (v.x - mu_hi) - mu_lo : 0.f;
-        v.y = c + 1 < pl.n_cols ? (v.y - mu_hi) - mu_lo : 0.f;
-        v.z = c + 2 < pl.n_cols ? (v.z - mu_hi) - mu_lo : 0.f;
-        v.w = c + 3 < pl.n_cols ? (v.w - mu_hi) - mu_lo : 0.f;
         *(float4*)(arrs + k) = v;
     }
-    float* zero_region = arrs + (size_t)wp.n_arr * ba.npw;
-    for (int k = lane; k < 64 * X; k += 64) zero_region[k] = 0.f;
     __syncthreads();
-    for (int a = 1; a < wp.n_arr; ++a) {
+    for (int a = 1; a < wp.n_arr; ++a) {                // presummed arrays D_g
         const int g = wp.arr_gap[a];
         float* Da = arrs + (size_t)a * ba.npw;
         for (int k = lane; k < ba.npw; k += 64) {
@@ -447,7 +495,8 @@ __global__ __launch_bounds__(256) void boxcar_kernel(PlaneArg pl, const spd_row_
     for (int i = 0; i < X; ++i) { B[i] = 0.f; mx[i] = -INFINITY; Bg[i] = 0.f; gi[i] = 0; }
     const float* lbase = arrs + lane;
 
-    for (int g = 0; g < wp.n_groups; ++g) {
+    const int nfull = wp.n / kGroup;
+    for (int g = 0; g < nfull; ++g) {
         const int i0 = g * kGroup;
         const float4 a03 = *(const float4*)(coef + i0);
         const float4 a47 = *(const float4*)(coef + i0 + 4);
@@ -478,22 +527,56 @@ __global__ __launch_bounds__(256) void boxcar_kernel(PlaneArg pl, const spd_row_
             B[i] = b;
         }
     }
+    const int rem = wp.n - nfull * kGroup;
+    if (rem) {                                          // last, partial group
+        const int i0 = nfull * kGroup;
+#pragma unroll
+        for (int i = 0; i < X; ++i) {
+            float b = B[i], gm = -INFINITY;
+            for (int j = 0; j < rem; ++j) {
+                const uint32_t o = wp.off[i0 + j], cgv = wp.cg[i0 + j];
+                const uint32_t cnt = cgv & 0xffffu, gap = cgv >> 16;
+                for (uint32_t m = 0; m < cnt; ++m) b = __fadd_rn(b, lbase[o + m * gap + 64 * i]);
+                gm = fmaxf(gm, __fmul_rn(b, coef[i0 + j]));
+            }
+            const bool c = gm > mx[i];
+            Bg[i] = c ? B[i] : Bg[i];
+            gi[i] = c ? nfull : gi[i];
+            mx[i] = c ? gm : mx[i];
+            B[i] = b;
+        }
+    }
 
     // first width inside the winning group, then outputs and the fused threshold
 #pragma unroll
     for (int i = 0; i < X; ++i) {
-        float b = Bg[i];
-        int idx = 0;
-        bool found = false;
         const int i0 = gi[i] * kGroup;
-        for (int j = 0; j < kGroup; ++j) {
-            const int wi = i0 + j;
-            const uint32_t o = toff[wi], cgv = tcg[wi];
-            const uint32_t cnt = cgv & 0xffffu, gap = cgv >> 16;
-            for (uint32_t m = 0; m < cnt; ++m) b = __fadd_rn(b, lbase[o + m * gap + 64 * i]);
-            const float s = __fmul_rn(b, coef[wi]);
-            if (!found && s == mx[i]) { idx = wi; found = true; }
+        const float4 c03 = *(const float4*)(coef + i0);
+        const float4 c47 = *(const float4*)(coef + i0 + 4);
+        const float cf[8] = {c03.x, c03.y, c03.z, c03.w, c47.x, c47.y, c47.z, c47.w};
+        float b = Bg[i];
+        float s[8];
+        if (UNIT) {
+            const uint4 o03 = *(const uint4*)(toff + i0);
+            const uint4 o47 = *(const uint4*)(toff + i0 + 4);
+            const uint32_t o[8] = {o03.x, o03.y, o03.z, o03.w, o47.x, o47.y, o47.z, o47.w};
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                b = __fadd_rn(b, lbase[o[j] + 64 * i]);
+                s[j] = __fmul_rn(b, cf[j]);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t o = toff[i0 + j], cgv = tcg[i0 + j];
+                const uint32_t cnt = cgv & 0xffffu, gap = cgv >> 16;
+                for (uint32_t m = 0; m < cnt; ++m) b = __fadd_rn(b, lbase[o + m * gap + 64 * i]);
+                s[j] = __fmul_rn(b, cf[j]);
+            }
         }
+        int idx = wp.n - 1;                             // reached only if no SNR equals the max (NaN input)
+#pragma unroll
+        for (int j = 7; j >= 0; --j) idx = (s[j] == mx[i]) ? i0 + j : idx;
         const int64_t t = tw + lane + 64 * i;
         const bool valid = t < ba.nout;
         if (valid && ba.snr) ba.snr[r * ba.out_stride + t] = mx[i];
@@ -575,10 +658,14 @@ static hipError_t launch_msd_dt(const PlaneArg& pl, bool vec, bool with_y, int64
         if (vec) hipLaunchKernelGGL((msd_x_kernel<DT, true>), dim3(nwg), dim3(256), 0, s, pl, ncb, bc, nblk, part);
         else hipLaunchKernelGGL((msd_x_kernel<DT, false>), dim3(nwg), dim3(256), 0, s, pl, ncb, bc, nblk, part);
     } else {
-        const int32_t np = (int32_t)(((2048 + nmax) + 255) / 256 * 256);
-        const size_t lds = (size_t)(np + 16) * sizeof(float);
-        hipLaunchKernelGGL((msd_xy_kernel<DT>), dim3(nwg), dim3(256), lds, s, pl, ncb, bc, nblk, nmax,
-                           nout, np, part);
+        const int32_t npw = (int32_t)((512 + nmax + 255) / 256 * 256);
+        int waves = 4;
+        while (waves > 1 && (size_t)waves * npw * sizeof(float) > 65536 - 256) waves >>= 1;
+        const size_t lds = (size_t)waves * npw * sizeof(float);
+        if (vec) hipLaunchKernelGGL((msd_xy_kernel<DT, true>), dim3(nwg), dim3(64 * waves), lds, s, pl, ncb, bc,
+                                    nblk, nmax, nout, npw, part);
+        else hipLaunchKernelGGL((msd_xy_kernel<DT, false>), dim3(nwg), dim3(64 * waves), lds, s, pl, ncb, bc,
+                                nblk, nmax, nout, npw, part);
     }
     return hipGetLastError();
 }
@@ -612,16 +699,11 @@ static hipError_t launch_boxcar_x(const PlaneArg& pl, bool vec, const spd_row_st
                                   const BoxcarArgs& ba, const WidthPlan& wp, int waves, uint64_t ntiles,
                                   hipStream_t s)
 {
-    const size_t lds = boxcar_lds_bytes(waves, ba);
-    if (vec) {
-        auto k = boxcar_kernel<DT, true, X, UNIT>;
-        if (lds > 65536) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k, dim3(ntiles), dim3(64 * waves), lds, s, pl, stats, ba, wp);
-    } else {
-        auto k = boxcar_kernel<DT, false, X, UNIT>;
-        if (lds > 65536) hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k, dim3(ntiles), dim3(64 * waves), lds, s, pl, stats, ba, wp);
-    }
+    const size_t lds = boxcar_lds_bytes(waves, ba);      // <= 64 KiB by construction of the plan
+    if (vec) hipLaunchKernelGGL((boxcar_kernel<DT, true, X, UNIT>), dim3(ntiles), dim3(64 * waves), lds, s, pl,
+                                stats, ba, wp);
+    else hipLaunchKernelGGL((boxcar_kernel<DT, false, X, UNIT>), dim3(ntiles), dim3(64 * waves), lds, s, pl,
+                            stats, ba, wp);
     return hipGetLastError();
 }
 
@@ -632,8 +714,8 @@ static hipError_t launch_boxcar_dt(const PlaneArg& pl, bool vec, const spd_row_s
 {
     const bool unit = wp.unit_counts != 0;
     (void)X;
-    return unit ? launch_boxcar_x<DT, 4, true>(pl, vec, stats, ba, wp, waves, ntiles, s)
-                : launch_boxcar_x<DT, 4, false>(pl, vec, stats, ba, wp, waves, ntiles, s);
+    return unit ? launch_boxcar_x<DT, kOutPerLane, true>(pl, vec, stats, ba, wp, waves, ntiles, s)
+                : launch_boxcar_x<DT, kOutPerLane, false>(pl, vec, stats, ba, wp, waves, ntiles, s);
 }
 
 hipError_t launch_boxcar(int dtype, const PlaneArg& pl, bool vec, const spd_row_stats* stats,
