@@ -35,9 +35,8 @@ OPS_PER_EVAL = 3          # boxcar add, SNR multiply, running-max compare per (t
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1611_09704_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in ("spd_kernels.hip", "spd_kernels.h", "spd_internal.h"):   # device code of the path
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -64,6 +63,8 @@ def main():
     ap.add_argument("--cols", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--workload", default="ska", choices=["ska", "ska16"],
+                    help="ska: widths 1..16,18..256/2 (default); ska16: the same plane with widths 1..16 only")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -83,7 +84,7 @@ def main():
     cfg = synth.ska(device=dev, R=args.rows, L=args.cols)
     x = cfg["plane"].x
     R, L = x.shape
-    W = cfg["widths"]
+    W = cfg["widths"] if args.workload == "ska" else list(range(1, 17))
     p = B.Params(W, cfg["threshold"], "row", cfg["sigma_mode"], cfg["kappa"])
     nout = L - p.nmax + 1
     stats = torch.empty((R, B.STATS_FIELDS), dtype=torch.float64, device=dev)
@@ -138,12 +139,13 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": cfg["name"], "rows": R, "cols": L, "widths": "1..16,18..256/2",
+        "config": {"workload": cfg["name"] + ("" if args.workload == "ska" else " widths 1..16"), "rows": R,
+                   "cols": L, "widths": "1..16,18..256/2" if args.workload == "ska" else "1..16",
                    "n_widths": len(W), "threshold": cfg["threshold"], "sigma_mode": "auto", "kappa": 1.0,
                    "scope": "row", "outputs": "snr f32 + width u8 per sample, fused candidate list"},
         "roofline": {"bound": "alu", "achieved": round(box_tops, 3), "peak": round(VALU_PEAK_TOPS, 2),
                      "unit": "TFLOP/s", "frac": round(box_tops / VALU_PEAK_TOPS, 4),
-                     "traffic": load_traffic("ska"), "kernel": "boxcar_kernel",
+                     "traffic": load_traffic(args.workload), "kernel": "boxcar_kernel",
                      "work_per_launch": "%d (t,w) evaluations x %d FP32 ops" % (evals, OPS_PER_EVAL)},
         "kernels": {
             "msd_compute": {"ms": round(msd_ms, 4), "GB/s": round(msd_bytes / msd_ms / 1e6, 1),
@@ -156,7 +158,7 @@ def main():
         "kernel_sha": kernel_source_sha(),
     }
 
-    if not args.no_secondary:
+    if not args.no_secondary and args.workload == "ska":
         # the paper's own measurement setting: widths 1..16 on the same plane
         p16 = B.Params(list(range(1, 17)), cfg["threshold"], "row", "auto", 1.0)
         w16, m16, b16 = timed(p16, args.steps, args.warmup)

@@ -1,0 +1,189 @@
+"""Workload driver and summariser for rocprofv3 runs of the detection path.
+
+``python -m paper_1611_09704_amd.profiling run --workload ska``
+    Generates the SKA-like plane on cuda:0, runs one device copy of a known
+    size (the calibration kernel for the FETCH_SIZE / WRITE_SIZE counters),
+    then ``--steps`` passes of msd_compute + boxcar_snr.  Meant to be the
+    program under ``rocprofv3 --pmc ...`` or ``--kernel-trace --stats``.
+
+``python -m paper_1611_09704_amd.profiling summarize --trace DIR --fetch DIR --write DIR --out profiles``
+    Reads the CSV files rocprofv3 wrote and produces the text summaries kept
+    under profiles/ (per-kernel durations, and HBM bytes per dispatch scaled
+    by what the counters read for the calibration copy).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+COPY_BYTES = 1 << 31          # calibration copy: reads and writes 2 GiB
+WORKLOADS = {"ska": None, "ska16": list(range(1, 17))}
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1611_09704_amd", "csrc")
+    for f in ("spd_kernels.hip", "spd_kernels.h", "spd_internal.h"):   # device code of the path
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def run(args):
+    import torch
+
+    from paper_1611_09704_amd import binding as B
+    from paper_1611_09704_amd import synth
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)                       # calibration dispatch
+    torch.cuda.synchronize()
+    del src, dst
+    cfg = synth.ska(device=dev, R=args.rows, L=args.cols)
+    x = cfg["plane"].x
+    W = WORKLOADS[args.workload] or cfg["widths"]
+    p = B.Params(W, cfg["threshold"], "row", cfg["sigma_mode"], cfg["kappa"])
+    R, L = x.shape
+    nout = L - p.nmax + 1
+    stats = torch.empty((R, B.STATS_FIELDS), dtype=torch.float64, device=dev)
+    ws = torch.empty(B.workspace_bytes(x, p), dtype=torch.uint8, device=dev)
+    snr = torch.empty((R, nout), dtype=torch.float32, device=dev)
+    widx = torch.empty((R, nout), dtype=torch.uint8, device=dev)
+    cand = B.new_candidates(1 << 21, dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    for k in range(args.steps):
+        B.msd_compute(x, p, stats=stats, workspace=ws)
+        B.boxcar_snr(x, p, stats, snr=snr, widx=widx, cand=cand, cand_count=count)
+        torch.cuda.synchronize()
+        print("step %d done, %d candidates" % (k, int(count.item())), flush=True)
+
+
+def _csvs(d, suffix):
+    return sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+
+
+def _short(name: str) -> str:
+    for key in ("boxcar_kernel", "msd_xy_kernel", "msd_x_kernel", "msd_finalize_kernel", "select_kernel",
+                "zero_count_kernel"):
+        if key in name:
+            return key
+    if "copyBuffer" in name:
+        return "calibration_copy"
+    return name[:60]
+
+
+def read_counters(d):
+    """{kernel short name: {counter: [value per dispatch]}} from a --pmc run."""
+    out = defaultdict(lambda: defaultdict(dict))
+    for f in _csvs(d, "counter_collection.csv"):
+        for row in csv.DictReader(open(f)):
+            k = _short(row["Kernel_Name"])
+            disp = row.get("Dispatch_Id") or row.get("Correlation_Id")
+            c = row["Counter_Name"]
+            out[k][c][disp] = out[k][c].get(disp, 0.0) + float(row["Counter_Value"])
+    return {k: {c: list(v.values()) for c, v in cs.items()} for k, cs in out.items()}
+
+
+def summarize(args):
+    sha = kernel_source_sha()
+    lines = []
+    stats = _csvs(args.trace, "kernel_stats.csv") if args.trace else []
+    if stats:
+        lines.append("## Kernel durations (rocprofv3 --kernel-trace --stats)\n")
+        lines.append("command: `%s`\n" % args.trace_cmd)
+        lines.append("| kernel | calls | average ms | total ms | share |")
+        lines.append("|---|---|---|---|---|")
+        for row in csv.DictReader(open(stats[0])):
+            name = _short(row["Name"])
+            if not any(k in name for k in ("boxcar", "msd", "select", "zero_count")):
+                continue
+            lines.append("| %s | %s | %.4f | %.3f | %s%% |" % (
+                name, row["Calls"], float(row["AverageNs"]) / 1e6, float(row["TotalDurationNs"]) / 1e6,
+                row.get("Percentage", "")[:5]))
+        lines.append("")
+    traffic = {}
+    if args.fetch and args.write:
+        fc, wc = read_counters(args.fetch), read_counters(args.write)
+        copy_f = fc.get("calibration_copy", {}).get("FETCH_SIZE", [])
+        copy_w = wc.get("calibration_copy", {}).get("WRITE_SIZE", [])
+        cf = max(copy_f) if copy_f else None
+        cw = max(copy_w) if copy_w else None
+        ff = COPY_BYTES / (cf * 1024.0) if cf else None
+        fw = COPY_BYTES / (cw * 1024.0) if cw else None
+        lines.append("## HBM traffic per dispatch (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE)\n")
+        lines.append("commands: `%s` and `%s`\n" % (args.fetch_cmd, args.write_cmd))
+        lines.append("Calibration: a device copy of %d bytes read FETCH_SIZE = %s KiB and WRITE_SIZE = %s KiB, "
+                     "so counter KiB are scaled by %s (fetch) and %s (write) to bytes.\n" % (
+                         COPY_BYTES, cf, cw, "%.4f" % (ff * 1024) if ff else None,
+                         "%.4f" % (fw * 1024) if fw else None))
+        lines.append("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read GB | written GB |")
+        lines.append("|---|---|---|---|---|---|")
+        for k in sorted(set(fc) | set(wc)):
+            if not any(s in k for s in ("boxcar", "msd", "select")):
+                continue
+            f = fc.get(k, {}).get("FETCH_SIZE", [])
+            w = wc.get(k, {}).get("WRITE_SIZE", [])
+            fm = sum(f) / len(f) if f else 0.0
+            wm = sum(w) / len(w) if w else 0.0
+            rb = fm * ff * 1024 if ff else None
+            wb = wm * fw * 1024 if fw else None
+            lines.append("| %s | %d | %.0f | %.0f | %s | %s |" % (
+                k, len(f), fm, wm, "%.3f" % (rb / 1e9) if rb is not None else "-",
+                "%.3f" % (wb / 1e9) if wb is not None else "-"))
+            if rb is not None and wb is not None:
+                traffic[k] = {"read_bytes": rb, "write_bytes": wb, "hbm_bytes_per_launch": rb + wb}
+        lines.append("")
+    lines.append("kernel sources sha: %s\n" % sha)
+    os.makedirs(args.out, exist_ok=True)
+    path = os.path.join(args.out, args.name + ".md")
+    with open(path, "w") as fh:
+        fh.write("# %s\n\n" % args.title + "\n".join(lines))
+    print("wrote", path)
+    if traffic and args.workload:
+        tpath = os.path.join(args.out, "boxcar_traffic.json")
+        try:
+            d = json.load(open(tpath))
+        except (OSError, ValueError):
+            d = {}
+        d[args.workload] = {"kernel_sha": sha, **traffic.get("boxcar_kernel", {}),
+                            "msd": traffic.get("msd_xy_kernel") or traffic.get("msd_x_kernel")}
+        json.dump(d, open(tpath, "w"), indent=1)
+        print("wrote", tpath)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    r = sub.add_parser("run")
+    r.add_argument("--workload", default="ska", choices=sorted(WORKLOADS))
+    r.add_argument("--steps", type=int, default=2)
+    r.add_argument("--rows", type=int, default=4096)
+    r.add_argument("--cols", type=int, default=1 << 20)
+    s = sub.add_parser("summarize")
+    s.add_argument("--trace")
+    s.add_argument("--trace-cmd", default="")
+    s.add_argument("--fetch")
+    s.add_argument("--fetch-cmd", default="")
+    s.add_argument("--write")
+    s.add_argument("--write-cmd", default="")
+    s.add_argument("--workload")
+    s.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    s.add_argument("--name", required=True)
+    s.add_argument("--title", required=True)
+    a = ap.parse_args(argv)
+    (run if a.cmd == "run" else summarize)(a)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
