@@ -117,13 +117,14 @@ typedef struct {
 } spd_row_stats;
 
 /* One candidate of Sec. 2.4: DM-trial row, time (window start + t_offset),
- * highest SNR and the boxcar width that produced it.                        */
+ * highest SNR and the boxcar width that produced it.  `beam` is the beam index
+ * in batched runs and 0 otherwise.                                          */
 typedef struct {
     int32_t row;
     int32_t width;
     int64_t t;
     float snr;
-    uint32_t reserved0;
+    uint32_t beam;
 } spd_candidate;
 
 /* ABI version (SPD_ABI_VERSION of the built library). */
@@ -191,6 +192,71 @@ spd_status select_candidates(const float* snr, const uint8_t* widx, int64_t n_ro
                              int64_t n_out_cols, int64_t out_stride, const spd_params* p,
                              int64_t t_offset, spd_candidate* cand, int64_t cand_capacity,
                              int64_t* cand_count, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched form: the same path over many beams of uneven shape per step.
+ * Every beam gets per-row statistics (Sec. 2.1-2.2), then the boxcar/SNR
+ * pass with the fused threshold (Sec. 2.3-2.4); candidates carry their beam
+ * index.  One persistent launch covers all beams' MSD blocks and one all
+ * their time tiles; both pull work from an atomic queue.
+ * ------------------------------------------------------------------------ */
+typedef struct spd_batch_plan spd_batch_plan;
+
+typedef struct {
+    int32_t out_per_lane;    /* boxcar starts per lane */
+    int32_t waves_per_group; /* waves per work-group: tile = 64*waves*out_per_lane starts */
+    int32_t groups_per_cu;   /* persistent work-groups per compute unit; 0 = one ordinary
+                                launch with one work-group per tile                      */
+    int32_t tiles_per_grab;  /* tiles taken per atomic queue increment */
+    int32_t tuned;           /* 0: default schedule, 1: timed at creation, 2: from the cache */
+    int32_t reserved0;
+    int64_t msd_items;       /* (beam, row, column block) items */
+    int64_t tiles;           /* (beam, row, time tile) items */
+    int64_t rows;            /* rows over all beams */
+} spd_batch_info;
+
+/*
+ * spd_batch_plan_create -- set up a batched run over `n_beams` planes
+ *   ([host] array of spd_plane describing device memory; same dtype for all,
+ *   1..256 beams, per-row statistics only).  ALLOCATES the plan's device
+ *   buffers (descriptors, block partials, per-row statistics, queue counters)
+ *   and a capture stream; the data pointers must stay valid for the plan's
+ *   life.  autotune=1 times candidate schedules of the boxcar pass on this
+ *   device (cached in $SPD_TUNE_CACHE or ~/.cache/spd/batch_schedule.txt).
+ *   Synchronises the device.  *plan receives the plan, NULL on error.
+ */
+spd_status spd_batch_plan_create(const spd_plane* beams, int32_t n_beams, const spd_params* p,
+                                 int32_t autotune, spd_batch_plan** plan);
+
+/*
+ * spd_batch_run -- one pass over every beam; candidates only (no per-sample
+ *   outputs).  cand/cand_capacity/cand_count behave as in boxcar_snr; each
+ *   candidate's `beam` field names its beam and `row` its row in that beam.
+ *   use_graph=1: the run's launches are captured into a hipGraph on first use
+ *   (and again whenever cand, capacity or count change) and replayed on
+ *   `stream`.  Allocates nothing after the first graph capture.
+ */
+spd_status spd_batch_run(spd_batch_plan* plan, spd_candidate* cand, int64_t cand_capacity,
+                         int64_t* cand_count, int32_t use_graph, void* stream);
+
+/* Device pointer to beam `beam`'s per-row statistics (valid after a run). */
+spd_status spd_batch_stats(const spd_batch_plan* plan, int32_t beam, const spd_row_stats** stats);
+
+/* Copy beam `beam`'s per-row statistics (n_rows of that beam) into dst
+ * (device memory owned by the caller), asynchronously on `stream`.          */
+spd_status spd_batch_copy_stats(const spd_batch_plan* plan, int32_t beam, spd_row_stats* dst, void* stream);
+
+/* The schedule the plan runs with. */
+spd_status spd_batch_describe(const spd_batch_plan* plan, spd_batch_info* info);
+
+/* The autotuner's measurements: up to `cap` timed schedules (rows[i]) with the
+ * time per output start (ns_per_start[i], host arrays).  Returns how many
+ * schedules were timed (0 when the schedule came from the cache or the
+ * default).                                                                  */
+int32_t spd_batch_tune_table(const spd_batch_plan* plan, spd_batch_info* rows, float* ns_per_start, int32_t cap);
+
+/* Frees everything the plan owns (call when no run is in flight). */
+void spd_batch_plan_destroy(spd_batch_plan* plan);
 
 #ifdef __cplusplus
 }

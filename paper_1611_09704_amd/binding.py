@@ -26,7 +26,7 @@ STATUS = {0: "SPD_OK", 1: "SPD_E_INVALID", 2: "SPD_E_UNSUPPORTED", 3: "SPD_E_NOM
           4: "SPD_E_DEVICE", 5: "SPD_E_AGAIN"}
 
 CANDIDATE_DTYPE = np.dtype([("row", "<i4"), ("width", "<i4"), ("t", "<i8"), ("snr", "<f4"),
-                            ("reserved", "<u4")])
+                            ("beam", "<u4")])
 STATS_FIELDS = 5          # mean, sigma, sigma_nmax, lin_coef, flags|reserved (as doubles)
 STATE_FIELDS = 6          # n, T, S, n_y, T_y, S_y
 
@@ -47,6 +47,13 @@ class SpdParams(ctypes.Structure):
     _fields_ = [("widths", ctypes.POINTER(ctypes.c_int32)), ("n_widths", ctypes.c_int32),
                 ("threshold", ctypes.c_float), ("scope", ctypes.c_int32), ("sigma_mode", ctypes.c_int32),
                 ("auto_kappa", ctypes.c_float), ("reserved0", ctypes.c_int32)]
+
+
+class SpdBatchInfo(ctypes.Structure):
+    _fields_ = [("out_per_lane", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
+                ("groups_per_cu", ctypes.c_int32), ("tiles_per_grab", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("msd_items", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("rows", ctypes.c_int64)]
 
 
 _lock = threading.Lock()
@@ -79,6 +86,18 @@ def load():
         lib.boxcar_snr.restype = ctypes.c_int
         lib.select_candidates.argtypes = [vp, vp, i64, i64, i64, P(SpdParams), i64, vp, i64, vp, vp]
         lib.select_candidates.restype = ctypes.c_int
+        lib.spd_batch_plan_create.argtypes = [P(SpdPlane), i32, P(SpdParams), i32, P(vp)]
+        lib.spd_batch_plan_create.restype = ctypes.c_int
+        lib.spd_batch_run.argtypes = [vp, vp, i64, vp, i32, vp]
+        lib.spd_batch_run.restype = ctypes.c_int
+        lib.spd_batch_copy_stats.argtypes = [vp, i32, vp, vp]
+        lib.spd_batch_copy_stats.restype = ctypes.c_int
+        lib.spd_batch_describe.argtypes = [vp, P(SpdBatchInfo)]
+        lib.spd_batch_describe.restype = ctypes.c_int
+        lib.spd_batch_tune_table.argtypes = [vp, P(SpdBatchInfo), P(ctypes.c_float), i32]
+        lib.spd_batch_tune_table.restype = i32
+        lib.spd_batch_plan_destroy.argtypes = [vp]
+        lib.spd_batch_plan_destroy.restype = None
         _lib = lib
         return lib
 
@@ -242,3 +261,54 @@ def detect(x: torch.Tensor, widths: Sequence[int], threshold: float, *, scope: s
         capacity = n
     return {"params": params, "stats": stats, "snr": snr, "widx": widx,
             "cands": candidates_to_numpy(cand, n), "n_cands": n}
+
+
+class BatchPlan:
+    """Batched form (spd_batch_*): many beams of uneven shape, one persistent
+    launch per pass, optional hipGraph replay.  ``beams`` is a list of 2-D
+    device tensors of one dtype (or (tensor, scale, zero) tuples for uint8);
+    they must stay alive while the plan exists."""
+
+    def __init__(self, beams, params: Params, autotune: bool = True):
+        lib = load()
+        self.params = params
+        self._beams = [b if isinstance(b, tuple) else (b, None, None) for b in beams]
+        arr = (SpdPlane * len(self._beams))(*[plane_struct(x, s, z) for x, s, z in self._beams])
+        h = ctypes.c_void_p()
+        _check(lib.spd_batch_plan_create(arr, len(self._beams), ctypes.byref(params.c), int(bool(autotune)),
+                                         ctypes.byref(h)))
+        self._h = h
+
+    def run(self, cand: torch.Tensor, cand_count: torch.Tensor, use_graph: bool = False, stream=None) -> None:
+        _check(load().spd_batch_run(self._h, cand.data_ptr(), cand.shape[0], cand_count.data_ptr(),
+                                    int(bool(use_graph)), _stream(stream)))
+
+    def stats(self, beam: int, stream=None) -> torch.Tensor:
+        x = self._beams[beam][0]
+        out = torch.empty((x.shape[0], STATS_FIELDS), dtype=torch.float64, device=x.device)
+        _check(load().spd_batch_copy_stats(self._h, int(beam), out.data_ptr(), _stream(stream)))
+        return out
+
+    def describe(self) -> dict:
+        info = SpdBatchInfo()
+        _check(load().spd_batch_describe(self._h, ctypes.byref(info)))
+        return {f: getattr(info, f) for f, _ in SpdBatchInfo._fields_ if f != "reserved0"}
+
+    def tune_table(self) -> list:
+        rows = (SpdBatchInfo * 64)()
+        ns = (ctypes.c_float * 64)()
+        n = load().spd_batch_tune_table(self._h, rows, ns, 64)
+        return [{"out_per_lane": rows[i].out_per_lane, "waves_per_group": rows[i].waves_per_group,
+                 "groups_per_cu": rows[i].groups_per_cu, "tiles_per_grab": rows[i].tiles_per_grab,
+                 "ns_per_start": round(float(ns[i]), 5)} for i in range(min(n, 64))]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().spd_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -112,7 +112,7 @@ MsdLayout msd_layout(const spd_plane* x)
 }
 
 // Presummed LDS arrays and per-width steps for the boxcar kernel.
-bool build_width_plan(const spd_params* p, int X, WidthPlan& wp, BoxcarArgs& ba, int& waves)
+bool build_width_plan(const spd_params* p, int X, WidthPlan& wp, BoxcarArgs& ba, int& waves, size_t lds_reserve)
 {
     const int n = p->n_widths;
     const int* W = p->widths;
@@ -136,7 +136,7 @@ bool build_width_plan(const spd_params* p, int X, WidthPlan& wp, BoxcarArgs& ba,
     const int np = 64 * X + wp.nmax - 1;
     const int npw = (np + 3) & ~3;
     const size_t tables = (size_t)kTableFloats * 4;
-    const size_t lds_cap = 65536;
+    const size_t lds_cap = 65536 - lds_reserve;
     for (;;) {
         const size_t per_wave = (size_t)gaps.size() * npw * 4;
         if (tables + per_wave <= lds_cap || gaps.size() == 1) break;
@@ -202,7 +202,7 @@ spd_status msd_compute(const spd_plane* x, const spd_params* p, int64_t new_col_
     const int nmax = p->widths[p->n_widths - 1];
     const int64_t nout = x->n_cols - nmax + 1;
     const bool need_y = p->sigma_mode != SPD_SIGMA_SQRTN;
-    if ((uint64_t)x->n_rows * (uint64_t)m.nblk > kMaxGrid)
+    if ((uint64_t)x->n_rows * (uint64_t)m.nblk * 256u > kMaxGridItems)
         return fail(SPD_E_UNSUPPORTED, "plane too large for one launch (%lld blocks)",
                     (long long)(x->n_rows * m.nblk));
     hipStream_t s = (hipStream_t)stream;
@@ -256,7 +256,7 @@ spd_status boxcar_snr(const spd_plane* x, const spd_params* p, const spd_row_sta
         if (e != hipSuccess) return device_status(e, "count reset launch");
     }
     const uint64_t ntiles = (uint64_t)x->n_rows * (uint64_t)ba.tiles_per_row;
-    if (ntiles > kMaxGrid) return fail(SPD_E_UNSUPPORTED, "plane too large for one launch");
+    if (ntiles * 64u * (uint64_t)waves > kMaxGridItems) return fail(SPD_E_UNSUPPORTED, "plane too large for one launch");
     hipError_t e = launch_boxcar(x->dtype, plane_arg(x), plane_vec_ok(x), stats, ba, wp, X, waves, ntiles, s);
     return device_status(e, "boxcar launch");
 }
@@ -273,7 +273,7 @@ spd_status select_candidates(const float* snr, const uint8_t* widx, int64_t n_ro
     if (out_stride < n_out_cols) return fail(SPD_E_INVALID, "out_stride < n_out_cols");
     if (!cand || !cand_count || cand_capacity < 0)
         return fail(SPD_E_INVALID, "candidate list needs cand, cand_count and capacity >= 0");
-    if ((uint64_t)n_rows * (uint64_t)((n_out_cols + 1023) / 1024) > kMaxGrid)
+    if ((uint64_t)n_rows * (uint64_t)((n_out_cols + 1023) / 1024) * 256u > kMaxGridItems)
         return fail(SPD_E_UNSUPPORTED, "output too large for one launch");
     SelectArgs sa;
     memset(&sa, 0, sizeof sa);

@@ -22,6 +22,7 @@ spd_status check_plane(const spd_plane* x, const spd_params* p);
 PlaneArg plane_arg(const spd_plane* x);
 bool plane_vec_ok(const spd_plane* x);
 MsdLayout msd_layout(const spd_plane* x);
-bool build_width_plan(const spd_params* p, int X, WidthPlan& wp, BoxcarArgs& ba, int& waves);
+bool build_width_plan(const spd_params* p, int X, WidthPlan& wp, BoxcarArgs& ba, int& waves,
+                      size_t lds_reserve = 0);
 
 }  // namespace spd

@@ -18,7 +18,7 @@ constexpr int kMaxWidthsPadded = SPD_MAX_WIDTHS + kGroup;
 // LDS floats of the boxcar kernel's coefficient and step tables, rounded up so
 // the per-wave arrays after them start on a 256-byte boundary.
 constexpr int kTableFloats = (3 * kMaxWidthsPadded + 63) / 64 * 64;
-constexpr uint64_t kMaxGrid = 0x7fffffffull;   // work-groups per launch (1-D grid)
+constexpr uint64_t kMaxGridItems = 0xffffffffull;   // work-items per launch (1-D grid)
 
 // How each width's boxcar is reached from the previous one:
 //   B_{w_i}(t) = B_{w_{i-1}}(t) + sum_{m < cnt_i} D_{g}[t + off_i + m*g]
@@ -61,7 +61,7 @@ struct BoxcarArgs {
     int64_t cand_capacity;
     int64_t* cand_count;
     float threshold;
-    int32_t reserved2;
+    uint32_t beam;          // stored in each candidate (batched runs)
 };
 
 struct SelectArgs {

@@ -1,4 +1,4 @@
-// spd_kernels.hip -- gfx950 kernels of the single-pulse detection path.
+// spd_kernels.hip -- one-plane launches of the detection path on gfx950.
 //
 //   msd_x_kernel / msd_xy_kernel   per-block (n, T, S) partials, Sec. 2.1
 //   msd_finalize_kernel            FP64 merge across blocks and sigma_N
@@ -8,603 +8,56 @@
 //                                  Sec. 2.4
 //   select_kernel                  threshold over stored outputs, Sec. 2.4
 //
-// The path is a streaming reduction plus a sliding-window scan: no dense
-// contraction, so everything is vector ALU + LDS work.  Loads are coalesced
-// along time (the contiguous axis), one work-group per (row, time block), with
-// an XCD-aware block order so that neighbouring time blocks of a row, whose
-// halos overlap, share an L2.
+// One work-group per (row, column block) or (row, time tile), numbered so that
+// each XCD gets a contiguous range.  The arithmetic lives in spd_device.h.
+#include "spd_device.h"
 #include "spd_kernels.h"
 
 namespace spd {
 
-// ---------------------------------------------------------------------------
-// small helpers
-// ---------------------------------------------------------------------------
-
-// The dispatcher hands work-group i to XCD (i mod 8).  Renumber so that each
-// XCD receives one contiguous range of logical blocks.
-__device__ __forceinline__ uint64_t xcd_remap(uint64_t bid, uint64_t nb)
-{
-    const uint64_t nx = 8;
-    uint64_t xcd = bid % nx, local = bid / nx;
-    uint64_t per = nb / nx, extra = nb % nx;
-    uint64_t start = xcd * per + (xcd < extra ? xcd : extra);
-    return start + local;
-}
-
-template <int DT> struct Loader;
-
-template <> struct Loader<SPD_F32> {
-    const float* row;
-    __device__ Loader(const PlaneArg& p, int64_t r) : row((const float*)p.data + r * p.stride) {}
-    __device__ __forceinline__ float at(int64_t c) const { return row[c]; }
-    __device__ __forceinline__ float4 vec(int64_t c) const { return *(const float4*)(row + c); }
-};
-
-template <> struct Loader<SPD_F16> {
-    const __half* row;
-    __device__ Loader(const PlaneArg& p, int64_t r) : row((const __half*)p.data + r * p.stride) {}
-    __device__ __forceinline__ float at(int64_t c) const { return __half2float(row[c]); }
-    __device__ __forceinline__ float4 vec(int64_t c) const {
-        uint2 u = *(const uint2*)(row + c);
-        __half2 h0 = *reinterpret_cast<__half2*>(&u.x), h1 = *reinterpret_cast<__half2*>(&u.y);
-        float2 a = __half22float2(h0), b = __half22float2(h1);
-        return make_float4(a.x, a.y, b.x, b.y);
-    }
-};
-
-template <> struct Loader<SPD_U8> {
-    const uint8_t* row;
-    float sc, z;
-    __device__ Loader(const PlaneArg& p, int64_t r)
-        : row((const uint8_t*)p.data + r * p.stride), sc(p.scale[r]), z(p.zero[r]) {}
-    __device__ __forceinline__ float deq(uint32_t q) const { return sc * ((float)q - z); }
-    __device__ __forceinline__ float at(int64_t c) const { return deq(row[c]); }
-    __device__ __forceinline__ float4 vec(int64_t c) const {
-        uint32_t u = *(const uint32_t*)(row + c);
-        return make_float4(deq(u & 255u), deq((u >> 8) & 255u), deq((u >> 16) & 255u), deq(u >> 24));
-    }
-};
-
-template <int DT, bool VEC>
-__device__ __forceinline__ float4 load4(const Loader<DT>& ld, int64_t c)
-{
-    if (VEC) return ld.vec(c);
-    return make_float4(ld.at(c), ld.at(c + 1), ld.at(c + 2), ld.at(c + 3));
-}
-
-// ---------------------------------------------------------------------------
-// Sec. 2.1: streaming and pairwise mean / deviation in FP32 inside a block
-// ---------------------------------------------------------------------------
-
-struct Msd { float n, T, S; };
-
-// Eq. (MSD04): merge the partial of samples 1..m (a) with m+1..m+n (b).
-// m/(n(m+n)) * (n/m*T_a - T_b)^2 is evaluated as (n*T_a - m*T_b)^2/(m*n*(m+n)).
-__device__ __forceinline__ Msd msd_merge(Msd a, Msd b)
-{
-    if (a.n == 0.f) return b;
-    if (b.n == 0.f) return a;
-    float d = b.n * a.T - a.n * b.T;
-    Msd o;
-    o.n = a.n + b.n;
-    o.T = a.T + b.T;
-    o.S = a.S + b.S + d * d / (a.n * b.n * o.n);
-    return o;
-}
-
-// Eq. (MSD03) for one more sample x_j: T_j = T_{j-1} + x_j,
-// S_j = S_{j-1} + (j*x_j - T_j)^2 / (j(j-1)).
-__device__ __forceinline__ void msd_add1(Msd& s, float x)
-{
-    s.n += 1.f;
-    s.T += x;
-    if (s.n > 1.f) {
-        float d = s.n * x - s.T;
-        s.S += d * d / (s.n * (s.n - 1.f));
-    }
-}
-
-// Four consecutive samples: Eq. (MSD03) over them with j = 1..4 (constant
-// coefficients 1/2, 1/6, 1/12), then Eq. (MSD04) into the running partial.
-__device__ __forceinline__ void msd_add4(Msd& s, float a, float b, float c, float d)
-{
-    float T2 = a + b, e2 = 2.f * b - T2;
-    float T3 = T2 + c, e3 = 3.f * c - T3;
-    float T4 = T3 + d, e4 = 4.f * d - T4;
-    float S4 = e2 * e2 * 0.5f + e3 * e3 * (1.f / 6.f) + e4 * e4 * (1.f / 12.f);
-    float dd = 4.f * s.T - s.n * T4;
-    float inc = s.n > 0.f ? dd * dd * __builtin_amdgcn_rcpf(s.n * 4.f * (s.n + 4.f)) : 0.f;
-    s.S = s.S + S4 + inc;
-    s.T += T4;
-    s.n += 4.f;
-}
-
-__device__ __forceinline__ Msd wave_merge(Msd v)
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        Msd o{__shfl_xor(v.n, off), __shfl_xor(v.T, off), __shfl_xor(v.S, off)};
-        v = (lane & off) ? msd_merge(o, v) : msd_merge(v, o);   // lower lanes first
-    }
-    return v;
-}
-
-// Merge every thread's partial into thread 0 (fixed order: lanes, then waves).
-__device__ __forceinline__ Msd block_merge(Msd v, Msd* scratch)
-{
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    v = wave_merge(v);
-    __syncthreads();
-    if (lane == 0) scratch[wave] = v;
-    __syncthreads();
-    Msd acc{0.f, 0.f, 0.f};
-    if (threadIdx.x == 0)
-        for (int w = 0; w < nw; ++w) acc = msd_merge(acc, scratch[w]);
-    return acc;
-}
-
-// Shift applied before the FP32 reduction: the mean of the row's first (up to)
-// block-size samples, so shifted samples -- and the widest-boxcar series built from
-// them -- have a mean small against their spread.  Any constant gives the same
-// statistics in exact arithmetic; T is shifted back in FP64.
 template <int DT>
-__device__ float pilot_shift(const Loader<DT>& ld, int64_t ncols, float* scratch)
-{
-    const int tid = threadIdx.x;
-    const int64_t n = ncols < (int64_t)blockDim.x ? ncols : (int64_t)blockDim.x;
-    float v = tid < n ? ld.at(tid) : 0.f;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    __syncthreads();
-    if ((tid & 63) == 0) scratch[tid >> 6] = v;
-    __syncthreads();
-    float sum = 0.f;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += scratch[w];
-    return sum / (float)n;
-}
-
-// Raw-sample partials of one (row, column block).  Columns [lo, hi) with
-// lo = max(block start, new_col_begin).
-template <int DT, bool VEC>
-__global__ __launch_bounds__(256) void msd_x_kernel(PlaneArg pl, int64_t ncb, int64_t bc,
+__global__ __launch_bounds__(256) void msd_x_kernel(PlaneArg pl, bool vec, int64_t ncb, int64_t bc,
                                                     int64_t nblk, double* part)
 {
-    __shared__ Msd scratch[16];
+    __shared__ MsdScratch sh;
     const uint64_t wg = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t r = (int64_t)(wg / (uint64_t)nblk), b = (int64_t)(wg % (uint64_t)nblk);
-    const int tid = threadIdx.x, nt = blockDim.x;
-    __shared__ float pscratch[16];
-    Loader<DT> ld(pl, r);
-    const float K = pilot_shift<DT>(ld, pl.n_cols, pscratch);
-    const int64_t lo = max(b * bc, ncb), hi = min((b + 1) * bc, pl.n_cols);
-    Msd s{0.f, 0.f, 0.f};
-    if (lo < hi) {
-        const int64_t a = min((lo + 3) & ~(int64_t)3, hi);
-        const int64_t e = max(a, hi & ~(int64_t)3);
-        if (tid < a - lo) msd_add1(s, ld.at(lo + tid) - K);
-        if (tid < hi - e) { Msd t{0.f, 0.f, 0.f}; msd_add1(t, ld.at(e + tid) - K); s = msd_merge(s, t); }
-        int64_t c = a + 4 * (int64_t)tid;
-        const int64_t step = 4 * (int64_t)nt;
-        for (; c + 3 * step < e; c += 4 * step) {
-            float4 v0 = load4<DT, VEC>(ld, c), v1 = load4<DT, VEC>(ld, c + step);
-            float4 v2 = load4<DT, VEC>(ld, c + 2 * step), v3 = load4<DT, VEC>(ld, c + 3 * step);
-            msd_add4(s, v0.x - K, v0.y - K, v0.z - K, v0.w - K);
-            msd_add4(s, v1.x - K, v1.y - K, v1.z - K, v1.w - K);
-            msd_add4(s, v2.x - K, v2.y - K, v2.z - K, v2.w - K);
-            msd_add4(s, v3.x - K, v3.y - K, v3.z - K, v3.w - K);
-        }
-        for (; c < e; c += step) {
-            float4 v = load4<DT, VEC>(ld, c);
-            msd_add4(s, v.x - K, v.y - K, v.z - K, v.w - K);
-        }
-    }
-    Msd t = block_merge(s, scratch);
-    if (tid == 0) {
-        double* o = part + wg * 6;
-        o[0] = t.n;
-        o[1] = (double)t.T + (double)t.n * (double)K;
-        o[2] = t.S;
-        o[3] = 0.0; o[4] = 0.0; o[5] = 0.0;
-    }
+    msd_block_x<DT>(pl, vec, r, b, ncb, bc, part + wg * 6, sh);
 }
 
-// Inclusive prefix sum across the 64 lanes of a wave with DPP row shifts and
-// row broadcasts (Hillis-Steele inside each row of 16, then across rows).
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_mov(float v)
-{
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, 0xf, true));
-}
-
-__device__ __forceinline__ float wave_inclusive_scan(float x)
-{
-    x += dpp_mov<0x111, 0xf>(x);   // row_shr:1
-    x += dpp_mov<0x112, 0xf>(x);   // row_shr:2
-    x += dpp_mov<0x114, 0xf>(x);   // row_shr:4
-    x += dpp_mov<0x118, 0xf>(x);   // row_shr:8
-    x += dpp_mov<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
-    x += dpp_mov<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
-    return x;
-}
-
-// Orders LDS writes and reads between lanes of one wave.
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Raw-sample partials plus the partials of the widest boxcar series
-// y(t) = sum_{k<nmax} x[t+k] for starts t in [block start, min(block end, nout)),
-// which give sigma_Nmax of Eq. (sd03).  Each wave walks its own sub-tiles of
-// TSW starts: it loads the sub-tile plus its nmax-1 halo (shifted by K),
-// forms the exclusive prefix E in its own LDS region with a wave scan, and
-// takes y(t) = E[t+nmax] - E[t].  The same loads feed the raw statistics.
-template <int DT, bool VEC>
-__global__ __launch_bounds__(256) void msd_xy_kernel(PlaneArg pl, int64_t ncb, int64_t bc,
+template <int DT>
+__global__ __launch_bounds__(256) void msd_xy_kernel(PlaneArg pl, bool vec, int64_t ncb, int64_t bc,
                                                      int64_t nblk, int32_t nmax, int64_t nout,
                                                      int32_t npw, double* part)
 {
-    constexpr int TSW = 512;
-    extern __shared__ float lds[];                      // [waves][npw]
-    __shared__ Msd scratch[16];
-    __shared__ float pscratch[16];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    float* E = lds + (size_t)wave * npw;
+    extern __shared__ float lds[];
+    __shared__ MsdScratch sh;
     const uint64_t wg = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t r = (int64_t)(wg / (uint64_t)nblk), b = (int64_t)(wg % (uint64_t)nblk);
-    Loader<DT> ld(pl, r);
-    const float K = pilot_shift<DT>(ld, pl.n_cols, pscratch);
-    const int64_t c0 = b * bc, c1 = min(c0 + bc, pl.n_cols);
-    const int64_t xlo = max(c0, ncb), yhi = min(c1, nout);
-    const int nrow = npw / 256;
-    Msd sx{0.f, 0.f, 0.f}, sy{0.f, 0.f, 0.f};
-    for (int64_t u0 = c0 + (int64_t)wave * TSW; u0 < c1; u0 += (int64_t)nw * TSW) {
-        const int64_t u1 = min(u0 + TSW, c1);
-        float carry = 0.f;
-        float4 ekeep[TSW / 256];
-        for (int m = 0; m < nrow; ++m) {
-            const int p = 256 * m + 4 * lane;
-            const int64_t c = u0 + p;
-            float4 v;
-            if (c + 3 < pl.n_cols) {
-                v = load4<DT, VEC>(ld, c);
-                v.x -= K; v.y -= K; v.z -= K; v.w -= K;
-            } else {
-                v.x = c < pl.n_cols ? ld.at(c) - K : 0.f;
-                v.y = c + 1 < pl.n_cols ? ld.at(c + 1) - K : 0.f;
-                v.z = c + 2 < pl.n_cols ? ld.at(c + 2) - K : 0.f;
-                v.w = c + 3 < pl.n_cols ? ld.at(c + 3) - K : 0.f;
-            }
-            if (p < TSW) {
-                if (c >= xlo && c + 3 < u1) {
-                    msd_add4(sx, v.x, v.y, v.z, v.w);
-                } else {
-                    const float vv[4] = {v.x, v.y, v.z, v.w};
-                    for (int j = 0; j < 4; ++j)
-                        if (c + j >= xlo && c + j < u1) msd_add1(sx, vv[j]);
-                }
-            }
-            const float l0 = v.x, l1 = l0 + v.y, l2 = l1 + v.z, l3 = l2 + v.w;
-            const float inc = wave_inclusive_scan(l3);
-            const float ex = (inc - l3) + carry;
-            carry += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(inc), 63));
-            const float4 e = make_float4(ex, ex + l0, ex + l1, ex + l2);
-            *(float4*)(E + p) = e;
-            if (m < TSW / 256) ekeep[m] = e;
-        }
-        wave_sync();
-#pragma unroll
-        for (int m = 0; m < TSW / 256; ++m) {
-            const int p = 256 * m + 4 * lane;
-            const int64_t t = u0 + p;
-            const float y0 = E[p + nmax] - ekeep[m].x, y1 = E[p + 1 + nmax] - ekeep[m].y;
-            const float y2 = E[p + 2 + nmax] - ekeep[m].z, y3 = E[p + 3 + nmax] - ekeep[m].w;
-            if (t + 3 < yhi) {
-                msd_add4(sy, y0, y1, y2, y3);
-            } else {
-                const float yy[4] = {y0, y1, y2, y3};
-                for (int j = 0; j < 4; ++j)
-                    if (t + j < yhi) msd_add1(sy, yy[j]);
-            }
-        }
-        wave_sync();
-    }
-    Msd tx = block_merge(sx, scratch);
-    Msd ty = block_merge(sy, scratch);
-    if (tid == 0) {
-        double* o = part + wg * 6;
-        o[0] = tx.n;
-        o[1] = (double)tx.T + (double)tx.n * (double)K;
-        o[2] = tx.S;
-        o[3] = ty.n;
-        o[4] = (double)ty.T + (double)ty.n * (double)nmax * (double)K;
-        o[5] = ty.S;
-    }
+    msd_block_xy<DT>(pl, vec, r, b, ncb, bc, nmax, nout, npw, lds, part + wg * 6, sh);
 }
 
-// ---------------------------------------------------------------------------
-// FP64 merge across blocks (Eq. MSD04) and the sigma_N coefficients
-// ---------------------------------------------------------------------------
-
-struct Msd64 { double n, T, S; };
-
-__device__ __forceinline__ Msd64 merge64(Msd64 a, Msd64 b)
-{
-    if (a.n == 0.0) return b;
-    if (b.n == 0.0) return a;
-    double d = (b.n / a.n) * a.T - b.T;
-    return Msd64{a.n + b.n, a.T + b.T, a.S + b.S + a.n / (b.n * (a.n + b.n)) * d * d};
-}
-
-// One work-group per unit.  Thread j merges a contiguous run of partials in
-// order, then a fixed binary tree merges the 256 runs.
 __global__ __launch_bounds__(256) void msd_finalize_kernel(const double* part, int64_t per_unit,
                                                            int32_t need_y, int32_t accumulate,
                                                            spd_msd_state* state, spd_row_stats* stats,
                                                            int32_t nmax, int32_t mode, double kappa)
 {
-    __shared__ Msd64 sx[256], sy[256];
+    __shared__ FinalizeScratch sh;
     const int64_t u = blockIdx.x;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const double* p = part + (size_t)u * per_unit * 6;
-    const int64_t q = (per_unit + nt - 1) / nt;
-    Msd64 ax{0, 0, 0}, ay{0, 0, 0};
-    for (int64_t i = tid * q; i < min((int64_t)(tid + 1) * q, per_unit); ++i) {
-        ax = merge64(ax, Msd64{p[i * 6 + 0], p[i * 6 + 1], p[i * 6 + 2]});
-        ay = merge64(ay, Msd64{p[i * 6 + 3], p[i * 6 + 4], p[i * 6 + 5]});
-    }
-    sx[tid] = ax;
-    sy[tid] = ay;
-    __syncthreads();
-    for (int h = 1; h < nt; h <<= 1) {                 // merge neighbours: runs stay in order
-        if ((tid & (2 * h - 1)) == 0 && tid + h < nt) {
-            sx[tid] = merge64(sx[tid], sx[tid + h]);
-            sy[tid] = merge64(sy[tid], sy[tid + h]);
-        }
-        __syncthreads();
-    }
-    if (tid != 0) return;
-    Msd64 X = sx[0], Y = sy[0];
-    if (state) {
-        spd_msd_state st = state[u];
-        if (accumulate) {
-            X = merge64(Msd64{st.n, st.T, st.S}, X);
-            Y = merge64(Msd64{st.n_y, st.T_y, st.S_y}, Y);
-        }
-        state[u] = spd_msd_state{X.n, X.T, X.S, Y.n, Y.T, Y.S};
-    }
-    spd_row_stats o;
-    o.mean = X.n > 0.0 ? X.T / X.n : 0.0;
-    o.sigma = X.n > 0.0 ? sqrt(X.S / X.n) : 0.0;
-    o.sigma_nmax = (need_y && Y.n > 0.0) ? sqrt(Y.S / Y.n) : 0.0;
-    o.lin_coef = 0.0;
-    o.flags = 0;
-    o.reserved0 = 0;
-    if (!(o.sigma > 0.0)) {
-        o.flags |= SPD_FLAG_ZERO_VAR;
-    } else if (nmax > 1 && mode != SPD_SIGMA_SQRTN) {
-        double base = sqrt((double)nmax) * o.sigma;
-        double anchored = (o.sigma_nmax - base) / (double)(nmax - 1);
-        if (mode == SPD_SIGMA_LINEAR) {
-            o.lin_coef = anchored; o.flags |= SPD_FLAG_LINEAR;
-        } else if (mode == SPD_SIGMA_LINEAR_LITERAL) {
-            o.lin_coef = o.sigma_nmax / (double)(nmax - 1); o.flags |= SPD_FLAG_LINEAR;
-        } else if (mode == SPD_SIGMA_AUTO && o.sigma_nmax / base > 1.0 + kappa) {
-            o.lin_coef = anchored; o.flags |= SPD_FLAG_LINEAR;
-        }
-    }
-    stats[u] = o;
+    finalize_unit(part + (size_t)u * per_unit * 6, per_unit, need_y != 0, accumulate != 0,
+                  state ? state + u : nullptr, stats + u, nmax, mode, kappa, sh);
 }
 
-// ---------------------------------------------------------------------------
-// Sec. 2.3, Algorithm 1: boxcars, SNR, highest SNR and first width; Sec. 2.4
-// ---------------------------------------------------------------------------
-//
-// One wave owns 64*X consecutive output starts of one row; lane l handles
-// starts t = l + 64*i (i < X) so that every LDS read is conflict free.  The
-// wave stages x' = x - mean for its window [t_w, t_w + 64X + Nmax - 1) in LDS
-// (array 0) plus presummed arrays D_g for other gaps, then walks the width list
-// once: B_{w_i} = B_{w_{i-1}} + D_g[t + w_{i-1}], s_i = B_{w_i} * (1/sigma_{w_i}).
-// Every boxcar sum is a running sum that starts at t, as in Algorithm 1, so
-// its rounding error grows with w only.
-//
-// The highest SNR and the first width reaching it are found exactly, with the
-// bookkeeping of Algorithm 1 (compare, then keep value and width) done once
-// per group of 8 widths on the group maximum: the first group whose maximum is
-// strictly larger than everything before it holds the first maximiser.  After
-// the list is done, that one group is evaluated again from the running sum
-// saved at its start (bit-identical operations) and the first width whose SNR
-// equals the maximum is taken.
-
-template <int DT, bool VEC, int X, bool UNIT>
-__global__ __launch_bounds__(256) void boxcar_kernel(PlaneArg pl, const spd_row_stats* stats,
+template <int DT, int X, bool UNIT>
+__global__ __launch_bounds__(256) void boxcar_kernel(PlaneArg pl, bool vec, const spd_row_stats* stats,
                                                      BoxcarArgs ba, WidthPlan wp)
 {
     extern __shared__ float smem[];
-    float* coef = smem;                                              // 1/sigma_w; NaN past n
-    uint32_t* toff = (uint32_t*)(coef + kMaxWidthsPadded);           // read offsets; 0 past n
-    uint32_t* tcg = toff + kMaxWidthsPadded;                         // cnt | gap<<16; 0 past n
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
-    float* arrs = smem + kTableFloats + (size_t)wave * ba.wave_floats;
-
     const uint64_t tile = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t r = (int64_t)(tile / (uint64_t)ba.tiles_per_row);
     const int64_t tt = (int64_t)(tile % (uint64_t)ba.tiles_per_row);
-    const int64_t tw = tt * (int64_t)(nwaves * 64 * X) + (int64_t)wave * 64 * X;
-
     const spd_row_stats st = stats[ba.scope == SPD_SCOPE_ROW ? r : 0];
-    const bool zero_var = (st.flags & SPD_FLAG_ZERO_VAR) != 0;
-    for (int i = tid; i < kMaxWidthsPadded; i += blockDim.x) {
-        if (i < wp.n) {
-            const int w = wp.width[i];
-            const double sw = sqrt((double)w) * st.sigma + (double)(w - 1) * st.lin_coef;
-            coef[i] = (zero_var || !(sw > 0.0)) ? 0.f : (float)(1.0 / sw);   // Eq. (sd02)/(sd03)
-            toff[i] = wp.off[i];
-            tcg[i] = wp.cg[i];
-        } else {
-            coef[i] = __int_as_float(0x7fc00000);
-            toff[i] = 0;
-            tcg[i] = 0;
-        }
-    }
-    const float mu_hi = (float)st.mean;
-    const float mu_lo = (float)(st.mean - (double)mu_hi);
-
-    // stage x' = x - mean for this wave's window; zero beyond the row
-    Loader<DT> ld(pl, r);
-    const int np = 64 * X + wp.nmax - 1;
-    for (int k = 4 * lane; k < ba.npw; k += 256) {
-        const int64_t c = tw + k;
-        float4 v;
-        if (c + 3 < pl.n_cols) {
-            v = load4<DT, VEC>(ld, c);
-            v.x = (v.x - mu_hi) - mu_lo;
-            v.y = (v.y - mu_hi) - mu_lo;
-            v.z = (v.z - mu_hi) - mu_lo;
-            v.w = (v.w - mu_hi) - mu_lo;
-        } else {
-            v.x = c < pl.n_cols ? (ld.at(c) - mu_hi) - mu_lo : 0.f;
-            v.y = c + 1 < pl.n_cols ? (ld.at(c + 1) - mu_hi) - mu_lo : 0.f;
-            v.z = c + 2 < pl.n_cols ? (ld.at(c + 2) - mu_hi) - mu_lo : 0.f;
-            v.w = c + 3 < pl.n_cols ? (ld.at(c + 3) - mu_hi) - mu_lo : 0.f;
-        }
-        *(float4*)(arrs + k) = v;
-    }
-    __syncthreads();
-    for (int a = 1; a < wp.n_arr; ++a) {                // presummed arrays D_g
-        const int g = wp.arr_gap[a];
-        float* Da = arrs + (size_t)a * ba.npw;
-        for (int k = lane; k < ba.npw; k += 64) {
-            float s = 0.f;
-            if (k + g <= np) {
-                s = arrs[k];
-                for (int j = 1; j < g; ++j) s += arrs[k + j];
-            }
-            Da[k] = s;
-        }
-    }
-    __syncthreads();
-
-    float B[X], mx[X], Bg[X];
-    int gi[X];
-#pragma unroll
-    for (int i = 0; i < X; ++i) { B[i] = 0.f; mx[i] = -INFINITY; Bg[i] = 0.f; gi[i] = 0; }
-    const float* lbase = arrs + lane;
-
-    const int nfull = wp.n / kGroup;
-    for (int g = 0; g < nfull; ++g) {
-        const int i0 = g * kGroup;
-        const float4 a03 = *(const float4*)(coef + i0);
-        const float4 a47 = *(const float4*)(coef + i0 + 4);
-        const float a[8] = {a03.x, a03.y, a03.z, a03.w, a47.x, a47.y, a47.z, a47.w};
-        uint32_t off[8], cg[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) { off[j] = wp.off[i0 + j]; cg[j] = wp.cg[i0 + j]; }
-#pragma unroll
-        for (int i = 0; i < X; ++i) {
-            float b = B[i];
-            float s[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (UNIT) {
-                    b = __fadd_rn(b, lbase[off[j] + 64 * i]);
-                } else {
-                    const uint32_t cnt = cg[j] & 0xffffu, gap = cg[j] >> 16;
-                    for (uint32_t m = 0; m < cnt; ++m) b = __fadd_rn(b, lbase[off[j] + m * gap + 64 * i]);
-                }
-                s[j] = __fmul_rn(b, a[j]);
-            }
-            const float gm = fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(s[0], s[1]), s[2]), s[3]), s[4]), s[5]),
-                                         s[6]), s[7]);
-            const bool c = gm > mx[i];
-            Bg[i] = c ? B[i] : Bg[i];
-            gi[i] = c ? g : gi[i];
-            mx[i] = c ? gm : mx[i];
-            B[i] = b;
-        }
-    }
-    const int rem = wp.n - nfull * kGroup;
-    if (rem) {                                          // last, partial group
-        const int i0 = nfull * kGroup;
-#pragma unroll
-        for (int i = 0; i < X; ++i) {
-            float b = B[i], gm = -INFINITY;
-            for (int j = 0; j < rem; ++j) {
-                const uint32_t o = wp.off[i0 + j], cgv = wp.cg[i0 + j];
-                const uint32_t cnt = cgv & 0xffffu, gap = cgv >> 16;
-                for (uint32_t m = 0; m < cnt; ++m) b = __fadd_rn(b, lbase[o + m * gap + 64 * i]);
-                gm = fmaxf(gm, __fmul_rn(b, coef[i0 + j]));
-            }
-            const bool c = gm > mx[i];
-            Bg[i] = c ? B[i] : Bg[i];
-            gi[i] = c ? nfull : gi[i];
-            mx[i] = c ? gm : mx[i];
-            B[i] = b;
-        }
-    }
-
-    // first width inside the winning group, then outputs and the fused threshold
-#pragma unroll
-    for (int i = 0; i < X; ++i) {
-        const int i0 = gi[i] * kGroup;
-        const float4 c03 = *(const float4*)(coef + i0);
-        const float4 c47 = *(const float4*)(coef + i0 + 4);
-        const float cf[8] = {c03.x, c03.y, c03.z, c03.w, c47.x, c47.y, c47.z, c47.w};
-        float b = Bg[i];
-        float s[8];
-        if (UNIT) {
-            const uint4 o03 = *(const uint4*)(toff + i0);
-            const uint4 o47 = *(const uint4*)(toff + i0 + 4);
-            const uint32_t o[8] = {o03.x, o03.y, o03.z, o03.w, o47.x, o47.y, o47.z, o47.w};
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                b = __fadd_rn(b, lbase[o[j] + 64 * i]);
-                s[j] = __fmul_rn(b, cf[j]);
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const uint32_t o = toff[i0 + j], cgv = tcg[i0 + j];
-                const uint32_t cnt = cgv & 0xffffu, gap = cgv >> 16;
-                for (uint32_t m = 0; m < cnt; ++m) b = __fadd_rn(b, lbase[o + m * gap + 64 * i]);
-                s[j] = __fmul_rn(b, cf[j]);
-            }
-        }
-        int idx = wp.n - 1;                             // reached only if no SNR equals the max (NaN input)
-#pragma unroll
-        for (int j = 7; j >= 0; --j) idx = (s[j] == mx[i]) ? i0 + j : idx;
-        const int64_t t = tw + lane + 64 * i;
-        const bool valid = t < ba.nout;
-        if (valid && ba.snr) ba.snr[r * ba.out_stride + t] = mx[i];
-        if (valid && ba.widx) ba.widx[r * ba.out_stride + t] = (uint8_t)idx;
-        if (ba.cand) {
-            const bool pred = valid && mx[i] >= ba.threshold;
-            const uint64_t mask = __ballot(pred);
-            if (mask) {
-                const int cntw = __popcll(mask);
-                const int before = __popcll(mask & ((1ull << lane) - 1ull));
-                unsigned long long base = 0;
-                if (lane == 0) base = atomicAdd((unsigned long long*)ba.cand_count, (unsigned long long)cntw);
-                base = __shfl(base, 0);
-                if (pred) {
-                    const unsigned long long k = base + (unsigned long long)before;
-                    if (k < (unsigned long long)ba.cand_capacity) {
-                        spd_candidate cd;
-                        cd.row = (int32_t)r;
-                        cd.width = wp.width[idx];
-                        cd.t = t + ba.t_offset;
-                        cd.snr = mx[i];
-                        cd.reserved0 = 0;
-                        ba.cand[k] = cd;
-                    }
-                }
-            }
-        }
-    }
+    boxcar_tile<DT, X, UNIT>(pl, vec, r, tt, st, ba, wp, smem, true);
 }
 
 // Sec. 2.4 over stored snr / width-index arrays.
@@ -635,37 +88,43 @@ __global__ __launch_bounds__(256) void select_kernel(const float* snr, const uin
                 cd.width = sa.width[widx[r * stride + t]];
                 cd.t = t + sa.t_offset;
                 cd.snr = s;
-                cd.reserved0 = 0;
+                cd.beam = 0;
                 sa.cand[k] = cd;
             }
         }
     }
 }
 
-__global__ void zero_count_kernel(int64_t* p) { *p = 0; }
+__global__ void fill_i64_kernel(int64_t* p, int64_t n, int64_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 
+int msd_xy_waves(int nmax)
+{
+    int waves = 4;
+    while (waves > 1 && (size_t)waves * msd_xy_npw(nmax) * sizeof(float) > 65536 - 4096) waves >>= 1;
+    return waves;
+}
+
 template <int DT>
 static hipError_t launch_msd_dt(const PlaneArg& pl, bool vec, bool with_y, int64_t ncb, int64_t bc,
-                                int64_t nblk, int32_t nmax, int64_t nout, double* part,
-                                hipStream_t s)
+                                int64_t nblk, int32_t nmax, int64_t nout, double* part, hipStream_t s)
 {
     const uint64_t nwg = (uint64_t)pl.n_rows * (uint64_t)nblk;
     if (!with_y) {
-        if (vec) hipLaunchKernelGGL((msd_x_kernel<DT, true>), dim3(nwg), dim3(256), 0, s, pl, ncb, bc, nblk, part);
-        else hipLaunchKernelGGL((msd_x_kernel<DT, false>), dim3(nwg), dim3(256), 0, s, pl, ncb, bc, nblk, part);
+        hipLaunchKernelGGL((msd_x_kernel<DT>), dim3(nwg), dim3(256), 0, s, pl, vec, ncb, bc, nblk, part);
     } else {
-        const int32_t npw = (int32_t)((512 + nmax + 255) / 256 * 256);
-        int waves = 4;
-        while (waves > 1 && (size_t)waves * npw * sizeof(float) > 65536 - 256) waves >>= 1;
+        const int32_t npw = msd_xy_npw(nmax);
+        const int waves = msd_xy_waves(nmax);
         const size_t lds = (size_t)waves * npw * sizeof(float);
-        if (vec) hipLaunchKernelGGL((msd_xy_kernel<DT, true>), dim3(nwg), dim3(64 * waves), lds, s, pl, ncb, bc,
-                                    nblk, nmax, nout, npw, part);
-        else hipLaunchKernelGGL((msd_xy_kernel<DT, false>), dim3(nwg), dim3(64 * waves), lds, s, pl, ncb, bc,
-                                nblk, nmax, nout, npw, part);
+        hipLaunchKernelGGL((msd_xy_kernel<DT>), dim3(nwg), dim3(64 * waves), lds, s, pl, vec, ncb, bc, nblk,
+                           nmax, nout, npw, part);
     }
     return hipGetLastError();
 }
@@ -694,46 +153,40 @@ size_t boxcar_lds_bytes(int waves, const BoxcarArgs& ba)
     return (size_t)kTableFloats * 4 + (size_t)waves * ba.wave_floats * 4;
 }
 
-template <int DT, int X, bool UNIT>
-static hipError_t launch_boxcar_x(const PlaneArg& pl, bool vec, const spd_row_stats* stats,
-                                  const BoxcarArgs& ba, const WidthPlan& wp, int waves, uint64_t ntiles,
-                                  hipStream_t s)
-{
-    const size_t lds = boxcar_lds_bytes(waves, ba);      // <= 64 KiB by construction of the plan
-    if (vec) hipLaunchKernelGGL((boxcar_kernel<DT, true, X, UNIT>), dim3(ntiles), dim3(64 * waves), lds, s, pl,
-                                stats, ba, wp);
-    else hipLaunchKernelGGL((boxcar_kernel<DT, false, X, UNIT>), dim3(ntiles), dim3(64 * waves), lds, s, pl,
-                            stats, ba, wp);
-    return hipGetLastError();
-}
-
 template <int DT>
 static hipError_t launch_boxcar_dt(const PlaneArg& pl, bool vec, const spd_row_stats* stats,
-                                   const BoxcarArgs& ba, const WidthPlan& wp, int X, int waves,
-                                   uint64_t ntiles, hipStream_t s)
+                                   const BoxcarArgs& ba, const WidthPlan& wp, int waves, uint64_t ntiles,
+                                   hipStream_t s)
 {
-    const bool unit = wp.unit_counts != 0;
-    (void)X;
-    return unit ? launch_boxcar_x<DT, kOutPerLane, true>(pl, vec, stats, ba, wp, waves, ntiles, s)
-                : launch_boxcar_x<DT, kOutPerLane, false>(pl, vec, stats, ba, wp, waves, ntiles, s);
+    const size_t lds = boxcar_lds_bytes(waves, ba);      // <= 64 KiB by construction of the plan
+    if (wp.unit_counts)
+        hipLaunchKernelGGL((boxcar_kernel<DT, kOutPerLane, true>), dim3(ntiles), dim3(64 * waves), lds, s, pl,
+                           vec, stats, ba, wp);
+    else
+        hipLaunchKernelGGL((boxcar_kernel<DT, kOutPerLane, false>), dim3(ntiles), dim3(64 * waves), lds, s, pl,
+                           vec, stats, ba, wp);
+    return hipGetLastError();
 }
 
 hipError_t launch_boxcar(int dtype, const PlaneArg& pl, bool vec, const spd_row_stats* stats,
                          const BoxcarArgs& ba, const WidthPlan& wp, int X, int waves, uint64_t ntiles,
                          hipStream_t s)
 {
+    (void)X;
     switch (dtype) {
-    case SPD_F32: return launch_boxcar_dt<SPD_F32>(pl, vec, stats, ba, wp, X, waves, ntiles, s);
-    case SPD_F16: return launch_boxcar_dt<SPD_F16>(pl, vec, stats, ba, wp, X, waves, ntiles, s);
-    default: return launch_boxcar_dt<SPD_U8>(pl, vec, stats, ba, wp, X, waves, ntiles, s);
+    case SPD_F32: return launch_boxcar_dt<SPD_F32>(pl, vec, stats, ba, wp, waves, ntiles, s);
+    case SPD_F16: return launch_boxcar_dt<SPD_F16>(pl, vec, stats, ba, wp, waves, ntiles, s);
+    default: return launch_boxcar_dt<SPD_U8>(pl, vec, stats, ba, wp, waves, ntiles, s);
     }
 }
 
-hipError_t launch_zero_count(int64_t* count, hipStream_t s)
+hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s)
 {
-    hipLaunchKernelGGL(zero_count_kernel, dim3(1), dim3(1), 0, s, count);
+    hipLaunchKernelGGL(fill_i64_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
+
+hipError_t launch_zero_count(int64_t* count, hipStream_t s) { return launch_fill_i64(count, 1, 0, s); }
 
 hipError_t launch_select(const float* snr, const uint8_t* widx, int64_t nrows, int64_t ncols,
                          int64_t stride, const SelectArgs& sa, hipStream_t s)

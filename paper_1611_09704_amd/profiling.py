@@ -32,7 +32,7 @@ WORKLOADS = {"ska": None, "ska16": list(range(1, 17))}
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1611_09704_amd", "csrc")
-    for f in ("spd_kernels.hip", "spd_kernels.h", "spd_internal.h"):   # device code of the path
+    for f in ("spd_device.h", "spd_kernels.hip", "spd_kernels.h", "spd_internal.h"):   # device code
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 

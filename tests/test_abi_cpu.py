@@ -104,3 +104,20 @@ def test_call_validation(lib):
     bad = B.Params([1, 2], float("nan"))
     assert lib.select_candidates(FAKE, FAKE, 4, 100, 100, ctypes.byref(bad.c), 0, FAKE, 10, FAKE, None) == 1
     assert "threshold" in _err(lib)
+
+
+def test_batch_validation(lib):
+    p = B.Params([1, 2, 4, 8], 5.0)
+    out = ctypes.c_void_p(123)
+    arr = (B.SpdPlane * 2)(_plane(), _plane(dtype=B.SPD_F16))
+    assert lib.spd_batch_plan_create(arr, 0, ctypes.byref(p.c), 0, ctypes.byref(out)) == 1
+    assert out.value is None and "n_beams" in _err(lib)
+    assert lib.spd_batch_plan_create(arr, 2, ctypes.byref(p.c), 0, ctypes.byref(out)) == 1
+    assert "dtype differs" in _err(lib)
+    bad = (B.SpdPlane * 1)(_plane(cols=5, stride=5))
+    assert lib.spd_batch_plan_create(bad, 1, ctypes.byref(p.c), 0, ctypes.byref(out)) == 1
+    assert "beam 0" in _err(lib)
+    pp = B.Params([1, 2], 5.0, scope="plane")
+    assert lib.spd_batch_plan_create(arr, 1, ctypes.byref(pp.c), 0, ctypes.byref(out)) == 2
+    assert lib.spd_batch_run(None, FAKE, 1, FAKE, 0, None) == 1
+    lib.spd_batch_plan_destroy(None)
