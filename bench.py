@@ -65,7 +65,7 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--workload", default="ska", choices=["ska", "ska16"],
                     help="ska: widths 1..16,18..256/2 (default); ska16: the same plane with widths 1..16 only")
-    ap.add_argument("--form", default="plain", choices=["plain", "batch"],
+    ap.add_argument("--form", default="plain", choices=["plain", "batch", "serve", "precision"],
                     help="plain: the SKA-like plane (default); batch: 48 uneven beams in one persistent, "
                          "graph-replayed launch per step, against per-beam plain launches")
     ap.add_argument("--batch-samples", type=float, default=40e9,
@@ -88,6 +88,12 @@ def main():
     torch.cuda.set_device(dev)
     if args.form == "batch":
         print(json.dumps(run_batch(args, dev)), flush=True)
+        return
+    if args.form == "serve":
+        print(json.dumps(run_serve(args, dev)), flush=True)
+        return
+    if args.form == "precision":
+        print(json.dumps(run_precision(args, dev)), flush=True)
         return
     cfg = synth.ska(device=dev, R=args.rows, L=args.cols)
     x = cfg["plane"].x
@@ -267,6 +273,201 @@ def run_batch(args, dev):
         "speedup_vs_plain": round(t_plain / t_batch, 4),
         "schedule": info, "autotune_table": table, "plan_create_s": round(t_create, 3), "n_candidates": n_cand,
     }
+
+
+def run_precision(args, dev):
+    """Precision form.  (1) Error: the tiny plane (64 x 65,536, widths 1..32,
+    threshold 6) stored as FP16 and as U8 (s_r = sigma_r/20, z = 64), each run
+    on the GPU and compared with the FP64 oracle on the ORIGINAL FP32 values
+    (max |dSNR|, candidate-set differences), next to the FP32 path's own
+    numbers; kernel parity on the dequantised values is checked too.  (2) Speed:
+    the SKA-like plane as FP32, FP16 and U8 (per-row zero at the row mean)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1611_09704_amd import binding as B
+    from paper_1611_09704_amd import synth
+    cfg = synth.tiny(device=dev)
+    x32 = cfg["plane"].x
+    W, thr = cfg["widths"], cfg["threshold"]
+    ref = oracle.detect(x32.cpu().double().numpy(), W, thr)
+    ref_set = set(zip(ref["cands"]["row"].tolist(), ref["cands"]["t"].tolist()))
+    q8, s8, z8 = synth.quantize_u8(x32, cfg["plane"].row_sigma)
+    forms = {"f32": (x32, None, None), "f16": (synth.quantize_f16(x32), None, None), "u8": (q8, s8, z8)}
+    errors = {}
+    for name, (x, sc, zr) in forms.items():
+        g = B.detect(x, W, thr, scale=sc, zero=zr)
+        snr = g["snr"].cpu().double().numpy()
+        gset = {(int(c["row"]), int(c["t"])) for c in g["cands"]}
+        if x.dtype == torch.uint8:
+            deq = oracle.dequantize_u8(x.cpu().numpy(), sc.cpu().numpy(), zr.cpu().numpy())
+        else:
+            deq = x.cpu().double().numpy()
+        own = oracle.detect(deq, W, thr)
+        errors[name] = {
+            "max_abs_dSNR_vs_fp32_oracle": float(np.abs(snr - ref["snr"]).max()),
+            "rms_dSNR_vs_fp32_oracle": float(np.sqrt(((snr - ref["snr"]) ** 2).mean())),
+            "width_differs_frac": float((g["widx"].cpu().numpy() != ref["widx"]).mean()),
+            "candidates": len(gset), "missing_vs_fp32_oracle": len(ref_set - gset),
+            "extra_vs_fp32_oracle": len(gset - ref_set),
+            "kernel_parity_max_abs_dSNR_on_stored_values": float(np.abs(snr - own["snr"]).max()),
+            "bytes_per_sample": x.element_size(),
+        }
+    # speed on the SKA-like plane
+    sk = synth.ska(device=dev, R=args.rows, L=args.cols)
+    xs = sk["plane"].x
+    R, L = xs.shape
+    q, sc, zr = synth.quantize_u8(xs, sk["plane"].row_sigma, row_mu=sk["plane"].row_mu)
+    planes = {"f32": (xs, None, None), "f16": (synth.quantize_f16(xs), None, None), "u8": (q, sc, zr)}
+    speed = {}
+    for wname, Wl in (("ska136", sk["widths"]), ("w16", list(range(1, 17)))):
+        p = B.Params(Wl, sk["threshold"], "row", "auto", 1.0)
+        nout = L - p.nmax + 1
+        snr = torch.empty((R, nout), dtype=torch.float32, device=dev)
+        widx = torch.empty((R, nout), dtype=torch.uint8, device=dev)
+        cand = B.new_candidates(1 << 21, dev)
+        count = torch.zeros(1, dtype=torch.int64, device=dev)
+        for name, (x, s_, z_) in planes.items():
+            stats = torch.empty((R, B.STATS_FIELDS), dtype=torch.float64, device=dev)
+            ws = torch.empty(B.workspace_bytes(x, p, s_, z_), dtype=torch.uint8, device=dev)
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            for rep in range(args.warmup + args.steps):
+                if rep == args.warmup:
+                    ev[0].record()
+                B.msd_compute(x, p, scale=s_, zero=z_, stats=stats, workspace=ws)
+                if rep == args.warmup:
+                    ev[1].record()
+                B.boxcar_snr(x, p, stats, scale=s_, zero=z_, snr=snr, widx=widx, cand=cand, cand_count=count)
+            ev[2].record()
+            torch.cuda.synchronize()
+            t_msd = ev[0].elapsed_time(ev[1])
+            t_all = ev[0].elapsed_time(ev[2]) / args.steps
+            speed["%s/%s" % (wname, name)] = {"msd_ms": round(t_msd, 4), "step_ms": round(t_all, 3),
+                                              "GSamples_per_s": round(R * L / t_all / 1e6, 3),
+                                              "msd_GB_per_s": round(R * L * x.element_size() / t_msd / 1e6, 1)}
+        del snr, widx
+    return {"metric": METRIC, "value": speed["ska136/f16"]["GSamples_per_s"], "unit": "GSamples/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+            "dtype": "f16/u8 storage, f32 accumulation, f64 merge", "data": "synthetic",
+            "config": {"workload": "precision forms: tiny 64x65536 error, ska 4096x2^20 speed"},
+            "errors": errors, "speed": speed}
+
+
+SAMPLE_S = 64e-6                  # sampling time of the serving workload
+
+
+def serve_run(B, srv, payloads, n_beams, rate_x, window_s, chunk_sky_s, seed, max_per_beam):
+    """Poisson arrivals for `window_s` seconds (each beam at rate_x /
+    chunk_sky_s chunks per second, at most max_per_beam chunks), every result
+    polled; returns latencies, wall time, the chunks sent and per-beam counts."""
+    import threading
+
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    events, per_beam = [], []
+    for b in range(n_beams):
+        t, k = 0.0, 0
+        while k < max_per_beam:
+            t += rng.exponential(chunk_sky_s / rate_x)
+            if t > window_s:
+                break
+            events.append((t, b, k))
+            k += 1
+        per_beam.append(k)
+    events.sort()
+    t0 = B.steady_now() + 0.05
+    err = []
+
+    def submitter():
+        try:
+            for t, b, k in events:
+                dt = t0 + t - B.steady_now()
+                if dt > 0:
+                    time.sleep(dt)
+                srv.submit(b, k, payloads[b][k % len(payloads[b])], arrival_s=t0 + t)
+        except Exception as e:          # surfaced after the run
+            err.append(e)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat, n = [], 0
+    while n < len(events):
+        r = srv.poll(wait_ms=200)
+        if r is None:
+            if err:
+                break
+            continue
+        res, _ = r
+        lat.append(res["done_s"] - res["submit_s"])
+        n += 1
+    th.join()
+    if err:
+        raise err[0]
+    wall = B.steady_now() - t0
+    return np.array(lat), wall, len(events), per_beam
+
+
+def run_serve(args, dev):
+    """Serving workload: 16 beams of 1,024 DM x 131,072 FP16 chunks (64 us
+    sampling, 8.39 s of sky each), widths 1..256, threshold 7, carried halo
+    and running statistics; Poisson arrivals at 1.5x aggregate real time, then
+    accelerated replays."""
+    import numpy as np
+    import torch
+
+    from paper_1611_09704_amd import binding as B
+    from paper_1611_09704_amd import synth
+    n_beams, R, C = 16, 1024, 131072
+    W = list(range(1, 257))
+    chunk_sky = C * SAMPLE_S
+    payloads = []
+    for b in range(n_beams):
+        chunks, _ = synth.stream_chunks(2, R, C, seed=4000 + b, device=dev, wmax=256, dtype=torch.float16)
+        payloads.append([c.cpu().pin_memory() for c in chunks])
+    srv = B.Server(n_beams, R, C, B.Params(W, 7.0), dtype=torch.float16, cand_capacity=1 << 16, slots_per_beam=2)
+    out_runs = []
+    window = float(os.environ.get("SPD_SERVE_PACED_S", "20"))
+    base = [0] * n_beams
+    for label, rate_x, win, cap in [("paced 1.5x real time", 1.5, window, 1000), ("replay 10x", 15.0, 4.0, 1000),
+                                    ("replay 100x", 150.0, 1.0, 16), ("replay 1000x", 1500.0, 0.1, 16)]:
+        lat, wall, n, per_beam = serve_run(B, _Offset(srv, list(base)), payloads, n_beams, rate_x, win, chunk_sky,
+                                           seed=len(out_runs), max_per_beam=cap)
+        base = [a + b for a, b in zip(base, per_beam)]
+        samples = n * R * C
+        out_runs.append({"run": label, "input_rate_x_real_time": rate_x, "chunks": n,
+                         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                         "max_ms": round(float(lat.max()) * 1e3, 3), "wall_s": round(wall, 3),
+                         "GSamples_per_s": round(samples / wall / 1e9, 3),
+                         "achieved_x_real_time": round(n * chunk_sky / n_beams / wall, 3)})
+    cnt = srv.counters()
+    srv.close()
+    fastest = out_runs[-1]
+    return {
+        "metric": METRIC, "value": fastest["GSamples_per_s"], "unit": "GSamples/s", "n_gpus": 1,
+        "steps": sum(r["chunks"] for r in out_runs), "warmup": 0, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f16 in, f32 compute",
+        "data": "synthetic",
+        "config": {"workload": "serve-16beams-1024x131072-f16", "widths": "1..256", "threshold": 7.0,
+                   "sigma_mode": "sqrtn", "halo": 255, "slots_per_beam": 2, "chunk_sky_s": round(chunk_sky, 6)},
+        "p50_chunk_latency_ms": out_runs[0]["p50_ms"], "p99_chunk_latency_ms": out_runs[0]["p99_ms"],
+        "max_real_time_factor": fastest["achieved_x_real_time"], "runs": out_runs, "counters": cnt,
+    }
+
+
+class _Offset:
+    """Server view whose chunk numbers continue, per beam, where the previous
+    run stopped."""
+
+    def __init__(self, srv, base):
+        self.srv, self.base = srv, base
+
+    def submit(self, beam, seq, chunk, arrival_s=0.0):
+        self.srv.submit(beam, self.base[beam] + seq, chunk, arrival_s)
+
+    def poll(self, wait_ms=0):
+        return self.srv.poll(wait_ms)
 
 
 if __name__ == "__main__":

@@ -258,6 +258,72 @@ int32_t spd_batch_tune_table(const spd_batch_plan* plan, spd_batch_info* rows, f
 /* Frees everything the plan owns (call when no run is in flight). */
 void spd_batch_plan_destroy(spd_batch_plan* plan);
 
+/* ------------------------------------------------------------------------
+ * Serving form: real-time streams of chunks from several beams.
+ * Each beam sends consecutive chunks of [n_rows][chunk_cols] new samples
+ * (time contiguous).  Per beam the server keeps on the device the running
+ * FP64 statistics of everything received so far (Eq. MSD04 merges, Sec. 2.1)
+ * and the last Nmax-1 columns of the previous chunk, which it puts in front
+ * of the next chunk: every boxcar window that ends inside chunk k is
+ * evaluated with chunk k, exactly once, and its SNR uses the statistics after
+ * chunk k (Sec. 2.2-2.4).  Candidate times are global sample indices.
+ * Requests are admitted as soon as the beam has a free chunk buffer and every
+ * earlier chunk of the beam was admitted; chunks of different beams run
+ * concurrently on the device (one stream per beam), copies overlap work.
+ * ------------------------------------------------------------------------ */
+typedef struct spd_server spd_server;
+
+typedef struct {
+    int32_t n_beams;           /* 1 .. 1024 */
+    int32_t dtype;             /* SPD_F32 or SPD_F16 */
+    int64_t n_rows;            /* DM trials per chunk */
+    int64_t chunk_cols;        /* new samples per chunk, >= the widest boxcar */
+    int64_t cand_capacity;     /* candidates kept per chunk (more are counted, not kept) */
+    int32_t slots_per_beam;    /* device chunk buffers per beam, 1..8 (2: the next copy overlaps work) */
+    int32_t reserved0;
+    int64_t hbm_budget_bytes;  /* 0, or the most device memory the server may take */
+} spd_server_config;
+
+typedef struct {
+    int32_t beam;
+    int32_t status;            /* SPD_OK, SPD_E_NOMEM (candidates beyond capacity), SPD_E_DEVICE */
+    int64_t seq;               /* chunk number within the beam */
+    int64_t t_offset;          /* global sample index of this chunk's first window start */
+    int64_t n_cands;           /* candidates found in the chunk */
+    int64_t n_copied;          /* candidates copied to the caller's buffer */
+    double submit_s;           /* arrival time given at submit (steady clock, seconds) */
+    double start_s;            /* when the chunk was admitted */
+    double done_s;             /* when its results reached the host */
+} spd_server_result;
+
+/* Device bytes a server with this configuration allocates (0 if invalid). */
+size_t spd_server_device_bytes(const spd_server_config* cfg, const spd_params* p);
+
+/* Create a server (ALLOCATES all device buffers, pinned result buffers,
+ * streams and a worker thread).  Per-row statistics only; p->sigma_mode may
+ * be any mode (the widest-boxcar statistics are streamed as well).         */
+spd_status spd_server_create(const spd_server_config* cfg, const spd_params* p, spd_server** server);
+
+/* Queue chunk `seq` of `beam` ([host] n_rows x chunk_cols elements of the
+ * configured dtype, pinned memory recommended).  seq must be the beam's next
+ * chunk number (0, 1, 2, ...).  The buffer must stay valid and unchanged
+ * until the chunk's result has been returned by spd_server_poll.
+ * arrival_s: the chunk's arrival time on the steady clock in seconds (<= 0:
+ * now); latency is measured from it.  Never blocks on the device.          */
+spd_status spd_server_submit(spd_server* server, int32_t beam, int64_t seq, const void* host_chunk,
+                             double arrival_s);
+
+/* Take one finished chunk: its result and up to `cap` candidates ([host]
+ * buffer).  Waits up to wait_ms for one; SPD_E_AGAIN if none finished.    */
+spd_status spd_server_poll(spd_server* server, spd_server_result* result, spd_candidate* cands, int64_t cap,
+                           int32_t wait_ms);
+
+/* Chunks submitted, admitted to the device, and completed so far. */
+spd_status spd_server_counters(spd_server* server, int64_t* submitted, int64_t* admitted, int64_t* completed);
+
+/* Finish the chunks in flight, stop the worker and free everything. */
+void spd_server_destroy(spd_server* server);
+
 #ifdef __cplusplus
 }
 #endif

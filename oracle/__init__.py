@@ -28,7 +28,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "spd_oracle.c")
-_LIB = os.path.join(_HERE, "libspd_oracle.so")
+_LIB = os.environ.get("SPD_ORACLE_LIB") or os.path.join(_HERE, "libspd_oracle.so")   # override: pin checks
 _lock = threading.Lock()
 _lib = None
 
@@ -52,7 +52,8 @@ def _load():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            if not os.environ.get("SPD_ORACLE_LIB") and (
+                    not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC)):
                 build(force=True)
             lib = ctypes.CDLL(_LIB)
             d, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32

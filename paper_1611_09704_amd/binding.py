@@ -10,6 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 import threading
+import time
 from typing import Optional, Sequence
 
 import numpy as np
@@ -56,6 +57,19 @@ class SpdBatchInfo(ctypes.Structure):
                 ("rows", ctypes.c_int64)]
 
 
+class SpdServerConfig(ctypes.Structure):
+    _fields_ = [("n_beams", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n_rows", ctypes.c_int64),
+                ("chunk_cols", ctypes.c_int64), ("cand_capacity", ctypes.c_int64),
+                ("slots_per_beam", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_int64)]
+
+
+class SpdServerResult(ctypes.Structure):
+    _fields_ = [("beam", ctypes.c_int32), ("status", ctypes.c_int32), ("seq", ctypes.c_int64),
+                ("t_offset", ctypes.c_int64), ("n_cands", ctypes.c_int64), ("n_copied", ctypes.c_int64),
+                ("submit_s", ctypes.c_double), ("start_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -96,6 +110,18 @@ def load():
         lib.spd_batch_describe.restype = ctypes.c_int
         lib.spd_batch_tune_table.argtypes = [vp, P(SpdBatchInfo), P(ctypes.c_float), i32]
         lib.spd_batch_tune_table.restype = i32
+        lib.spd_server_device_bytes.argtypes = [P(SpdServerConfig), P(SpdParams)]
+        lib.spd_server_device_bytes.restype = ctypes.c_size_t
+        lib.spd_server_create.argtypes = [P(SpdServerConfig), P(SpdParams), P(vp)]
+        lib.spd_server_create.restype = ctypes.c_int
+        lib.spd_server_submit.argtypes = [vp, i32, i64, vp, ctypes.c_double]
+        lib.spd_server_submit.restype = ctypes.c_int
+        lib.spd_server_poll.argtypes = [vp, P(SpdServerResult), vp, i64, i32]
+        lib.spd_server_poll.restype = ctypes.c_int
+        lib.spd_server_counters.argtypes = [vp, P(i64), P(i64), P(i64)]
+        lib.spd_server_counters.restype = ctypes.c_int
+        lib.spd_server_destroy.argtypes = [vp]
+        lib.spd_server_destroy.restype = None
         lib.spd_batch_plan_destroy.argtypes = [vp]
         lib.spd_batch_plan_destroy.restype = None
         _lib = lib
@@ -306,6 +332,69 @@ class BatchPlan:
         if getattr(self, "_h", None):
             load().spd_batch_plan_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def steady_now() -> float:
+    """The steady clock the server stamps results with (seconds)."""
+    return time.monotonic()
+
+
+class Server:
+    """Serving form (spd_server_*): chunk streams from several beams with
+    carried halo and running statistics; results are polled as they finish."""
+
+    def __init__(self, n_beams: int, n_rows: int, chunk_cols: int, params: Params, dtype=torch.float16,
+                 cand_capacity: int = 1 << 16, slots_per_beam: int = 2, hbm_budget_bytes: int = 0):
+        lib = load()
+        dt = {torch.float32: SPD_F32, torch.float16: SPD_F16}[dtype]
+        self.params = params
+        self.cfg = SpdServerConfig(n_beams, dt, n_rows, chunk_cols, cand_capacity, slots_per_beam, 0,
+                                   hbm_budget_bytes)
+        self.cap = cand_capacity
+        self._buf = np.empty(cand_capacity, dtype=CANDIDATE_DTYPE)
+        self._keep = {}
+        h = ctypes.c_void_p()
+        _check(lib.spd_server_create(ctypes.byref(self.cfg), ctypes.byref(params.c), ctypes.byref(h)))
+        self._h = h
+
+    def device_bytes(self) -> int:
+        return load().spd_server_device_bytes(ctypes.byref(self.cfg), ctypes.byref(self.params.c))
+
+    def submit(self, beam: int, seq: int, chunk: torch.Tensor, arrival_s: float = 0.0) -> None:
+        """chunk: a host tensor [n_rows, chunk_cols], kept alive until its result is polled."""
+        if chunk.is_cuda or not chunk.is_contiguous():
+            raise ValueError("chunk must be a contiguous host tensor (pinned for speed)")
+        self._keep[(beam, seq)] = chunk
+        _check(load().spd_server_submit(self._h, int(beam), int(seq), chunk.data_ptr(), float(arrival_s)))
+
+    def poll(self, wait_ms: int = 0):
+        """(result dict, candidates array) of one finished chunk, or None."""
+        res = SpdServerResult()
+        st = load().spd_server_poll(self._h, ctypes.byref(res), self._buf.ctypes.data_as(ctypes.c_void_p),
+                                    self.cap, int(wait_ms))
+        if st == 5:
+            return None
+        _check(st)
+        self._keep.pop((res.beam, res.seq), None)
+        out = {f: getattr(res, f) for f, _ in SpdServerResult._fields_}
+        return out, self._buf[:res.n_copied].copy()
+
+    def counters(self) -> dict:
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(load().spd_server_counters(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return {"submitted": a.value, "admitted": b.value, "completed": c.value}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().spd_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

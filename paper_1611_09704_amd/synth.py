@@ -155,14 +155,19 @@ def quantize_f16(x: torch.Tensor) -> torch.Tensor:
     return x.to(torch.float16)
 
 
-def quantize_u8(x: torch.Tensor, row_sigma, counts_per_sigma: float = 20.0, zero: float = 64.0):
-    """Per-row uint8 storage q = clamp(rint(x / s_r) + z, 0, 255) with
-    s_r = sigma_r / counts_per_sigma and z = 64 (noise at ~20 counts, range
-    -3.2 to +9.6 sigma).  Returns (q, scale[R] f32, zero[R] f32)."""
+def quantize_u8(x: torch.Tensor, row_sigma, counts_per_sigma: float = 20.0, zero: float = 64.0,
+                row_mu=None):
+    """Per-row uint8 storage q = clamp(rint(x / s_r) + z_r, 0, 255) with
+    s_r = sigma_r / counts_per_sigma and z_r = 64 (noise at ~20 counts, range
+    -3.2 to +9.6 sigma); with ``row_mu`` given, z_r = 64 - rint(mu_r / s_r) so
+    each row's mean sits at 64 counts.  Returns (q, scale[R] f32, zero[R] f32)."""
     R = x.shape[0]
-    scale = torch.as_tensor(np.asarray(row_sigma, dtype=np.float64) / counts_per_sigma,
-                            dtype=torch.float32, device=x.device)
-    z = torch.full((R,), zero, dtype=torch.float32, device=x.device)
+    s64 = np.asarray(row_sigma, dtype=np.float64) / counts_per_sigma
+    scale = torch.as_tensor(s64, dtype=torch.float32, device=x.device)
+    z64 = np.full(R, zero)
+    if row_mu is not None:
+        z64 = zero - np.rint(np.asarray(row_mu, dtype=np.float64) / scale.cpu().double().numpy())
+    z = torch.as_tensor(z64, dtype=torch.float32, device=x.device)
     q = torch.round(x / scale.view(R, 1)) + z.view(R, 1)
     q = q.clamp_(0, 255).to(torch.uint8)
     return q, scale, z

@@ -121,3 +121,26 @@ def test_batch_validation(lib):
     assert lib.spd_batch_plan_create(arr, 1, ctypes.byref(pp.c), 0, ctypes.byref(out)) == 2
     assert lib.spd_batch_run(None, FAKE, 1, FAKE, 0, None) == 1
     lib.spd_batch_plan_destroy(None)
+
+
+def test_server_validation(lib):
+    p = B.Params(list(range(1, 17)), 7.0)
+    out = ctypes.c_void_p(7)
+
+    def cfg(**kw):
+        c = dict(n_beams=2, dtype=B.SPD_F16, n_rows=8, chunk_cols=4096, cand_capacity=100, slots_per_beam=2,
+                 reserved0=0, hbm_budget_bytes=0)
+        c.update(kw)
+        return B.SpdServerConfig(**c)
+
+    for c, code, msg in [(cfg(n_beams=0), 1, "n_beams"), (cfg(dtype=B.SPD_U8), 2, "F32 or F16"),
+                         (cfg(chunk_cols=8), 1, "chunk_cols"), (cfg(slots_per_beam=0), 1, "slots_per_beam"),
+                         (cfg(cand_capacity=0), 1, "cand_capacity"), (cfg(hbm_budget_bytes=1000), 3, "budget")]:
+        assert lib.spd_server_create(ctypes.byref(c), ctypes.byref(p.c), ctypes.byref(out)) == code
+        assert out.value is None and msg in _err(lib)
+    pp = B.Params([1, 2], 5.0, scope="plane")
+    assert lib.spd_server_create(ctypes.byref(cfg()), ctypes.byref(pp.c), ctypes.byref(out)) == 2
+    need = lib.spd_server_device_bytes(ctypes.byref(cfg()), ctypes.byref(p.c))
+    assert need > 2 * 2 * 8 * (4096 + 15) * 2
+    assert lib.spd_server_submit(None, 0, 0, FAKE, 0.0) == 1
+    lib.spd_server_destroy(None)

@@ -1,0 +1,145 @@
+"""Serving form: chunk streams from several beams with a carried halo and
+running per-beam statistics, checked against the streaming oracle; the same
+beam gives the same results alone and in a mix of beams."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1611_09704_amd import binding as B
+from paper_1611_09704_amd import synth
+import spd_check as C
+
+pytestmark = pytest.mark.gpu
+
+
+def _streams(n_beams, K, R, Lc, wmax, dtype, seed=77):
+    out = []
+    for b in range(n_beams):
+        chunks, pulses = synth.stream_chunks(K, R, Lc, seed=seed + b, device="cuda", wmax=wmax, dtype=dtype)
+        out.append(([c.cpu().pin_memory() for c in chunks], pulses))
+    return out
+
+
+def _drain(srv, n, timeout_ms=20000):
+    got = []
+    while len(got) < n:
+        r = srv.poll(wait_ms=timeout_ms)
+        assert r is not None, "server produced %d of %d results" % (len(got), n)
+        got.append(r)
+    return got
+
+
+def _oracle_stream(chunks, W, thr, mode="sqrtn"):
+    """Per chunk: oracle candidates of the view [halo | chunk] with the running state."""
+    nmax = W[-1]
+    state, prev, res = None, None, []
+    for k, c in enumerate(chunks):
+        x = c.double().numpy()
+        if k == 0:
+            view, ncb, toff = x, 0, 0
+        else:
+            view, ncb, toff = np.concatenate([prev[:, -(nmax - 1):], x], axis=1), nmax - 1, k * x.shape[1] - (nmax - 1)
+        state, st, snr, widx = oracle.stream_step(view, W, new_col_begin=ncb, state=state, sigma_mode=mode)
+        res.append((oracle.select(snr, widx, W, thr, t_offset=toff), snr, toff))
+        prev = x
+    return res
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
+def test_server_matches_streaming_oracle(dtype):
+    R, Lc, K, nb = 6, 4096, 4, 3
+    W = list(range(1, 65))
+    thr = 6.0
+    streams = _streams(nb, K, R, Lc, 64, dtype)
+    srv = B.Server(nb, R, Lc, B.Params(W, thr), dtype=dtype, cand_capacity=4096)
+    for k in range(K):                       # interleave beams chunk by chunk
+        for b in range(nb):
+            srv.submit(b, k, streams[b][0][k])
+    results = _drain(srv, nb * K)
+    srv.close()
+    by = {(r["beam"], r["seq"]): (r, c) for r, c in results}
+    for b in range(nb):
+        orc = _oracle_stream(streams[b][0], W, thr)
+        seqs = [r["seq"] for r, _ in results if r["beam"] == b]
+        assert seqs == sorted(seqs), "beam %d completed out of order" % b
+        found = set()
+        for k in range(K):
+            r, c = by[(b, k)]
+            oc, snr, toff = orc[k]
+            assert r["status"] == 0 and r["t_offset"] == toff
+            C.check_candidates(c, oc, thr, lambda row, t: snr[row, t - toff])
+            found |= {(int(x["row"]), int(x["t"])) for x in c}
+        for p in streams[b][1]:             # every bright boundary-straddling pulse is seen
+            if p.snr >= 10.0:
+                assert any(row == p.row and abs(t - p.t0) <= p.width for row, t in found), p
+
+
+def test_server_same_result_alone_and_in_a_mix():
+    R, Lc, K = 8, 8192, 3
+    W = list(range(1, 33))
+    streams = _streams(4, K, R, Lc, 32, torch.float16, seed=91)
+    p = B.Params(W, 5.5)
+    alone = B.Server(1, R, Lc, p, cand_capacity=8192)
+    for k in range(K):
+        alone.submit(0, k, streams[0][0][k])
+    ra = sorted(_drain(alone, K), key=lambda r: r[0]["seq"])
+    alone.close()
+    mix = B.Server(4, R, Lc, p, cand_capacity=8192, slots_per_beam=3)
+    for k in range(K):
+        for b in (3, 1, 0, 2):
+            mix.submit(b, k, streams[b][0][k])
+    rm = sorted([r for r in _drain(mix, 4 * K) if r[0]["beam"] == 0], key=lambda r: r[0]["seq"])
+    mix.close()
+    for (a, ca), (m, cm) in zip(ra, rm):
+        assert a["n_cands"] == m["n_cands"]
+        ka = sorted((int(x["row"]), int(x["t"]), float(x["snr"]), int(x["width"])) for x in ca)
+        km = sorted((int(x["row"]), int(x["t"]), float(x["snr"]), int(x["width"])) for x in cm)
+        assert ka == km                      # bitwise: a beam's work never depends on the others
+
+
+def test_server_backpressure_and_order():
+    R, Lc, K = 4, 2048, 12
+    W = [1, 2, 4, 8]
+    streams = _streams(2, K, R, Lc, 8, torch.float32, seed=5)
+    srv = B.Server(2, R, Lc, B.Params(W, 5.0), dtype=torch.float32, cand_capacity=64, slots_per_beam=1)
+    for k in range(K):
+        srv.submit(0, k, streams[0][0][k])
+        srv.submit(1, k, streams[1][0][k])
+    with pytest.raises(B.SpdError):
+        srv.submit(0, K + 3, streams[0][0][0])   # sequence gap
+    res = _drain(srv, 2 * K)
+    cnt = srv.counters()
+    srv.close()
+    assert cnt == {"submitted": 2 * K, "admitted": 2 * K, "completed": 2 * K}
+    for b in (0, 1):
+        assert [r["seq"] for r, _ in res if r["beam"] == b] == list(range(K))
+    assert all(r["done_s"] >= r["start_s"] >= r["submit_s"] for r, _ in res)
+
+
+def test_server_full_size_chunks_sampled_rows():
+    """Serving chunk shape at full size: 1,024 DM x 131,072 FP16 samples,
+    widths 1..256, threshold 7; 4 beams x 2 chunks; sampled rows checked
+    against the streaming oracle."""
+    R, Lc, K, nb = 1024, 131072, 2, 4
+    W = list(range(1, 257))
+    streams = _streams(nb, K, R, Lc, 256, torch.float16, seed=2024)
+    srv = B.Server(nb, R, Lc, B.Params(W, 7.0), cand_capacity=1 << 18)
+    for k in range(K):
+        for b in range(nb):
+            srv.submit(b, k, streams[b][0][k])
+    res = _drain(srv, nb * K)
+    srv.close()
+    rng = np.random.default_rng(3)
+    for b in range(nb):
+        rows = sorted(set([p.row for p in streams[b][1]] + rng.choice(R, 3, replace=False).tolist()))
+        sub = [c[rows] for c in streams[b][0]]
+        orc = _oracle_stream(sub, W, 7.0)
+        for k in range(K):
+            r, c = next(x for x in res if x[0]["beam"] == b and x[0]["seq"] == k)
+            oc, snr, toff = orc[k]
+            oc = dict(oc)
+            oc["row"] = np.asarray(rows)[oc["row"]]
+            cs = c[np.isin(c["row"], rows)]
+            C.check_candidates(cs, oc, 7.0, lambda row, t: snr[rows.index(row), t - toff])
+        print("beam %d rows %s ok" % (b, rows), flush=True)

@@ -1,0 +1,54 @@
+"""The pins have teeth: each plausible slip, planted in a copy of the oracle
+(compiled on the CPU into a temporary library), makes the pin suite fail.
+
+Mutations: the unsquared Eq. (MSD03) update; mu instead of w*mu in the SNR;
+'>=' instead of '>' in the running maximum; the sign of the anchored Eq. (sd03)
+coefficient; the Eq. (MSD04) weights swapped; a shifted boxcar window; a
+strict threshold; sample instead of population sigma; the MSD04 ratio
+inverted; a widest-boxcar series one sample short; w instead of sqrt(w) in
+Eq. (sd02); the AUTO switch at rho > kappa.
+"""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "spd_oracle.c")
+
+MUTATIONS = {
+    "no_square": ("S += d * d / (j * (j - 1.0));", "S += d / (j * (j - 1.0));"),
+    "mu_not_wmu": ("(B - (double)W[i] * mu) / sig_w[i]", "(B - mu) / sig_w[i]"),
+    "ge_ties": ("if (s > best) { best = s; bi = i; }", "if (s >= best) { best = s; bi = i; }"),
+    "anchored_sign": ("coef = (sig_nmax - base) / (double)(nmax - 1);\n            flags |= FLAG_LINEAR;\n"
+                      "        } else if (sigma_mode == SIG_LINEAR_LITERAL)",
+                      "coef = (base - sig_nmax) / (double)(nmax - 1);\n            flags |= FLAG_LINEAR;\n"
+                      "        } else if (sigma_mode == SIG_LINEAR_LITERAL)"),
+    "merge_weights": ("m / (n * (m + n)) * d * d", "n / (m * (m + n)) * d * d"),
+    "window_shift": ("while (k < W[i]) { B += row[t + k]; ++k; }", "while (k < W[i]) { B += row[t + k + 1]; ++k; }"),
+    "threshold_strict": ("if (s >= f_T) {", "if (s > f_T) {"),
+    "sample_sigma": ("double sigma = n > 0.0 ? sqrt(S / n) : 0.0;",
+                     "double sigma = n > 1.0 ? sqrt(S / (n - 1.0)) : 0.0;"),
+    "merge_ratio": ("double d = (n / m) * a3[1] - b3[1];", "double d = (m / n) * a3[1] - b3[1];"),
+    "nmax_series_short": ("for (int k = 0; k < nmax; ++k) b += row[t + k];",
+                          "for (int k = 0; k < nmax - 1; ++k) b += row[t + k];"),
+    "w_not_sqrt_w": ("sig_w[i] = sqrt((double)W[i]) * sigma", "sig_w[i] = (double)W[i] * sigma"),
+    "auto_at_kappa": ("if (rho > 1.0 + kappa) {", "if (rho > kappa) {"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(name, tmp_path):
+    a, b = MUTATIONS[name]
+    src = open(SRC).read()
+    assert src.count(a) == 1, "mutation site not found"
+    c = tmp_path / ("%s.c" % name)
+    c.write_text(src.replace(a, b))
+    so = tmp_path / ("%s.so" % name)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", str(so), str(c), "-lm"])
+    env = dict(os.environ, SPD_ORACLE_LIB=str(so), OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py")], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0, "planted mistake %s passed every pin:\n%s" % (name, r.stdout[-500:])

@@ -264,3 +264,20 @@ def test_stream_equals_one_shot_on_prefix(mode):
         np.testing.assert_allclose(st[:, :4], st1[:, :4], rtol=1e-11, atol=1e-12)
         np.testing.assert_allclose(snr, snr1[:, toff:toff + snr.shape[1]], rtol=0, atol=1e-10)
         np.testing.assert_array_equal(widx, widx1[:, toff:toff + snr.shape[1]])
+
+
+def test_auto_switches_exactly_at_one_plus_kappa():
+    """AUTO applies the linear form iff rho = sigma_Nmax / (sqrt(Nmax) sigma)
+    exceeds 1 + kappa; rho recomputed here by numpy from the definitions."""
+    rng = np.random.default_rng(14)
+    L, nmax = 40000, 32
+    x = rng.standard_normal((2, L))
+    x[1, 5000:5000 + int(0.3 * L)] += 1.0
+    for r in range(2):
+        y = np.convolve(x[r], np.ones(nmax), mode="valid")
+        rho = y.std() / (np.sqrt(nmax) * x[r].std())
+        for kappa in (0.0, 0.5, rho - 1.0 - 1e-3, rho - 1.0 + 1e-3, 2.0):
+            if kappa < 0:
+                continue
+            _, st, _, _ = oracle.stream_step(x[r:r + 1], list(range(1, nmax + 1)), sigma_mode="auto", kappa=kappa)
+            assert bool(int(st[0, 4]) & oracle.FLAG_LINEAR) == (rho > 1.0 + kappa), (r, rho, kappa)
