@@ -441,7 +441,7 @@ __device__ void finalize_unit(const double* p, int64_t per_unit, bool need_y, bo
 
 // LDS layout of a work-group: [kTableFloats] tables, then per wave
 // ba.wave_floats floats of presummed arrays.
-template <int DT, int X, bool UNIT>
+template <int DT, int X, bool UNIT, int SMALL = 0>
 __device__ void boxcar_tile(const PlaneArg& pl, bool vec, int64_t r, int64_t tt, const spd_row_stats& st,
                             const BoxcarArgs& ba, const WidthPlan& wp, float* smem, bool setup_tables)
 {
@@ -494,100 +494,15 @@ __device__ void boxcar_tile(const PlaneArg& pl, bool vec, int64_t r, int64_t tt,
     }
     __syncthreads();
 
-    float B[X], mx[X], Bg[X];
-    int gi[X];
-#pragma unroll
-    for (int i = 0; i < X; ++i) { B[i] = 0.f; mx[i] = -INFINITY; Bg[i] = 0.f; gi[i] = 0; }
     const float* lbase = arrs + lane;
-
-    const int nfull = wp.n / kGroup;
-    for (int g = 0; g < nfull; ++g) {
-        const int i0 = g * kGroup;
-        const float4 a03 = *(const float4*)(coef + i0);
-        const float4 a47 = *(const float4*)(coef + i0 + 4);
-        const float a[8] = {a03.x, a03.y, a03.z, a03.w, a47.x, a47.y, a47.z, a47.w};
-        uint32_t off[8], cg[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) { off[j] = wp.off[i0 + j]; cg[j] = wp.cg[i0 + j]; }
-#pragma unroll
-        for (int i = 0; i < X; ++i) {
-            float b = B[i];
-            float s[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (UNIT) {
-                    b = __fadd_rn(b, lbase[off[j] + 64 * i]);
-                } else {
-                    const uint32_t cnt = cg[j] & 0xffffu, gap = cg[j] >> 16;
-                    for (uint32_t m = 0; m < cnt; ++m) b = __fadd_rn(b, lbase[off[j] + m * gap + 64 * i]);
-                }
-                s[j] = __fmul_rn(b, a[j]);
-            }
-            const float gm = fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(s[0], s[1]), s[2]), s[3]), s[4]), s[5]),
-                                         s[6]), s[7]);
-            const bool c = gm > mx[i];
-            Bg[i] = c ? B[i] : Bg[i];
-            gi[i] = c ? g : gi[i];
-            mx[i] = c ? gm : mx[i];
-            B[i] = b;
-        }
-    }
-    const int rem = wp.n - nfull * kGroup;
-    if (rem) {                                          // last, partial group
-        const int i0 = nfull * kGroup;
-#pragma unroll
-        for (int i = 0; i < X; ++i) {
-            float b = B[i], gm = -INFINITY;
-            for (int j = 0; j < rem; ++j) {
-                const uint32_t o = wp.off[i0 + j], cgv = wp.cg[i0 + j];
-                const uint32_t cnt = cgv & 0xffffu, gap = cgv >> 16;
-                for (uint32_t m = 0; m < cnt; ++m) b = __fadd_rn(b, lbase[o + m * gap + 64 * i]);
-                gm = fmaxf(gm, __fmul_rn(b, coef[i0 + j]));
-            }
-            const bool c = gm > mx[i];
-            Bg[i] = c ? B[i] : Bg[i];
-            gi[i] = c ? nfull : gi[i];
-            mx[i] = c ? gm : mx[i];
-            B[i] = b;
-        }
-    }
-
-    // first width inside the winning group, then outputs and the fused threshold
-#pragma unroll
-    for (int i = 0; i < X; ++i) {
-        const int i0 = gi[i] * kGroup;
-        const float4 c03 = *(const float4*)(coef + i0);
-        const float4 c47 = *(const float4*)(coef + i0 + 4);
-        const float cf[8] = {c03.x, c03.y, c03.z, c03.w, c47.x, c47.y, c47.z, c47.w};
-        float b = Bg[i];
-        float s[8];
-        if (UNIT) {
-            const uint4 o03 = *(const uint4*)(toff + i0);
-            const uint4 o47 = *(const uint4*)(toff + i0 + 4);
-            const uint32_t o[8] = {o03.x, o03.y, o03.z, o03.w, o47.x, o47.y, o47.z, o47.w};
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                b = __fadd_rn(b, lbase[o[j] + 64 * i]);
-                s[j] = __fmul_rn(b, cf[j]);
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const uint32_t o = toff[i0 + j], cgv = tcg[i0 + j];
-                const uint32_t cnt = cgv & 0xffffu, gap = cgv >> 16;
-                for (uint32_t m = 0; m < cnt; ++m) b = __fadd_rn(b, lbase[o + m * gap + 64 * i]);
-                s[j] = __fmul_rn(b, cf[j]);
-            }
-        }
-        int idx = wp.n - 1;                             // reached only if no SNR equals the max (NaN input)
-#pragma unroll
-        for (int j = 7; j >= 0; --j) idx = (s[j] == mx[i]) ? i0 + j : idx;
+    // output start t = tw + lane + 64 i: per-sample outputs and the fused threshold
+    auto emit = [&](int i, float m, int idx) {
         const int64_t t = tw + lane + 64 * i;
         const bool valid = t < ba.nout;
-        if (valid && ba.snr) ba.snr[r * ba.out_stride + t] = mx[i];
+        if (valid && ba.snr) ba.snr[r * ba.out_stride + t] = m;
         if (valid && ba.widx) ba.widx[r * ba.out_stride + t] = (uint8_t)idx;
         if (ba.cand) {
-            const bool pred = valid && mx[i] >= ba.threshold;
+            const bool pred = valid && m >= ba.threshold;
             const uint64_t mask = __ballot(pred);
             if (mask) {
                 const int cntw = __popcll(mask);
@@ -602,12 +517,140 @@ __device__ void boxcar_tile(const PlaneArg& pl, bool vec, int64_t r, int64_t tt,
                         cd.row = (int32_t)r;
                         cd.width = wp.width[idx];
                         cd.t = t + ba.t_offset;
-                        cd.snr = mx[i];
+                        cd.snr = m;
                         cd.beam = ba.beam;
                         ba.cand[k] = cd;
                     }
                 }
             }
+        }
+    };
+    if constexpr (SMALL > 0) {
+        // Short lists (n <= SMALL, one step per width): every SNR of a start
+        // stays in registers; the maximum is a max tree and the first width
+        // reaching it a reverse select chain.  Entries past n have a NaN
+        // coefficient: max ignores them and they never compare equal.
+        constexpr int NS = SMALL > 0 ? SMALL : 1;
+        float a[NS];
+        uint32_t off[NS];
+#pragma unroll
+        for (int j = 0; j < SMALL; j += 4) {
+            const float4 c = *(const float4*)(coef + j);
+            a[j] = c.x; a[j + 1] = c.y; a[j + 2] = c.z; a[j + 3] = c.w;
+        }
+#pragma unroll
+        for (int j = 0; j < SMALL; ++j) off[j] = wp.off[j];
+#pragma unroll
+        for (int i = 0; i < X; ++i) {
+            float b = 0.f, sv[NS];
+#pragma unroll
+            for (int j = 0; j < SMALL; ++j) {
+                b = __fadd_rn(b, lbase[off[j] + 64 * i]);
+                sv[j] = __fmul_rn(b, a[j]);
+            }
+            float m = sv[0];
+#pragma unroll
+            for (int j = 1; j < SMALL; ++j) m = fmaxf(m, sv[j]);
+            int idx = wp.n - 1;
+#pragma unroll
+            for (int j = SMALL - 1; j >= 0; --j) idx = (sv[j] == m) ? j : idx;
+            emit(i, m, idx);
+        }
+    } else {
+        float B[X], mx[X], Bg[X];
+        int gi[X];
+#pragma unroll
+        for (int i = 0; i < X; ++i) { B[i] = 0.f; mx[i] = -INFINITY; Bg[i] = 0.f; gi[i] = 0; }
+
+        const int nfull = wp.n / kGroup;
+        // Two groups per trip let the carried sums and maxima alternate
+        // registers instead of being copied; the general-count form is
+        // already register-heavy and stays rolled.
+        constexpr int kGroupUnroll = UNIT ? 2 : 1;
+#pragma unroll kGroupUnroll
+        for (int g = 0; g < nfull; ++g) {
+            const int i0 = g * kGroup;
+            const float4 a03 = *(const float4*)(coef + i0);
+            const float4 a47 = *(const float4*)(coef + i0 + 4);
+            const float a[8] = {a03.x, a03.y, a03.z, a03.w, a47.x, a47.y, a47.z, a47.w};
+            uint32_t off[8], cg[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) { off[j] = wp.off[i0 + j]; cg[j] = wp.cg[i0 + j]; }
+#pragma unroll
+            for (int i = 0; i < X; ++i) {
+                float b = B[i];
+                float s[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (UNIT) {
+                        b = __fadd_rn(b, lbase[off[j] + 64 * i]);
+                    } else {
+                        const uint32_t cnt = cg[j] & 0xffffu, gap = cg[j] >> 16;
+                        for (uint32_t m = 0; m < cnt; ++m) b = __fadd_rn(b, lbase[off[j] + m * gap + 64 * i]);
+                    }
+                    s[j] = __fmul_rn(b, a[j]);
+                }
+                // running maximum folded into the group's max3 tree; c: this group beats all before it
+                const float mnew = fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(s[0], s[1]), s[2]), s[3]), s[4]),
+                                                           s[5]), s[6]), s[7]), mx[i]);
+                const bool c = mnew > mx[i];
+                Bg[i] = c ? B[i] : Bg[i];
+                gi[i] = c ? g : gi[i];
+                mx[i] = mnew;
+                B[i] = b;
+            }
+        }
+        const int rem = wp.n - nfull * kGroup;
+        if (rem) {                                          // last, partial group
+            const int i0 = nfull * kGroup;
+#pragma unroll
+            for (int i = 0; i < X; ++i) {
+                float b = B[i], gm = -INFINITY;
+                for (int j = 0; j < rem; ++j) {
+                    const uint32_t o = wp.off[i0 + j], cgv = wp.cg[i0 + j];
+                    const uint32_t cnt = cgv & 0xffffu, gap = cgv >> 16;
+                    for (uint32_t m = 0; m < cnt; ++m) b = __fadd_rn(b, lbase[o + m * gap + 64 * i]);
+                    gm = fmaxf(gm, __fmul_rn(b, coef[i0 + j]));
+                }
+                const bool c = gm > mx[i];
+                Bg[i] = c ? B[i] : Bg[i];
+                gi[i] = c ? nfull : gi[i];
+                mx[i] = c ? gm : mx[i];
+                B[i] = b;
+            }
+        }
+
+        // first width inside the winning group, then outputs and the fused threshold
+#pragma unroll
+        for (int i = 0; i < X; ++i) {
+            const int i0 = gi[i] * kGroup;
+            const float4 c03 = *(const float4*)(coef + i0);
+            const float4 c47 = *(const float4*)(coef + i0 + 4);
+            const float cf[8] = {c03.x, c03.y, c03.z, c03.w, c47.x, c47.y, c47.z, c47.w};
+            float b = Bg[i];
+            float s[8];
+            if (UNIT) {
+                const uint4 o03 = *(const uint4*)(toff + i0);
+                const uint4 o47 = *(const uint4*)(toff + i0 + 4);
+                const uint32_t o[8] = {o03.x, o03.y, o03.z, o03.w, o47.x, o47.y, o47.z, o47.w};
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    b = __fadd_rn(b, lbase[o[j] + 64 * i]);
+                    s[j] = __fmul_rn(b, cf[j]);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const uint32_t o = toff[i0 + j], cgv = tcg[i0 + j];
+                    const uint32_t cnt = cgv & 0xffffu, gap = cgv >> 16;
+                    for (uint32_t m = 0; m < cnt; ++m) b = __fadd_rn(b, lbase[o + m * gap + 64 * i]);
+                    s[j] = __fmul_rn(b, cf[j]);
+                }
+            }
+            int idx = wp.n - 1;                             // reached only if no SNR equals the max (NaN input)
+#pragma unroll
+            for (int j = 7; j >= 0; --j) idx = (s[j] == mx[i]) ? i0 + j : idx;
+            emit(i, mx[i], idx);
         }
     }
 }

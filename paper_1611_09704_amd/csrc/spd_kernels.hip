@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void msd_finalize_kernel(const double* part, i
                   state ? state + u : nullptr, stats + u, nmax, mode, kappa, sh);
 }
 
-template <int DT, int X, bool UNIT>
+template <int DT, int X, bool UNIT, int SMALL>
 __global__ __launch_bounds__(256) void boxcar_kernel(PlaneArg pl, bool vec, const spd_row_stats* stats,
                                                      BoxcarArgs ba, WidthPlan wp)
 {
@@ -57,7 +57,7 @@ __global__ __launch_bounds__(256) void boxcar_kernel(PlaneArg pl, bool vec, cons
     const int64_t r = (int64_t)(tile / (uint64_t)ba.tiles_per_row);
     const int64_t tt = (int64_t)(tile % (uint64_t)ba.tiles_per_row);
     const spd_row_stats st = stats[ba.scope == SPD_SCOPE_ROW ? r : 0];
-    boxcar_tile<DT, X, UNIT>(pl, vec, r, tt, st, ba, wp, smem, true);
+    boxcar_tile<DT, X, UNIT, SMALL>(pl, vec, r, tt, st, ba, wp, smem, true);
 }
 
 // Sec. 2.4 over stored snr / width-index arrays.
@@ -159,12 +159,19 @@ static hipError_t launch_boxcar_dt(const PlaneArg& pl, bool vec, const spd_row_s
                                    hipStream_t s)
 {
     const size_t lds = boxcar_lds_bytes(waves, ba);      // <= 64 KiB by construction of the plan
-    if (wp.unit_counts)
-        hipLaunchKernelGGL((boxcar_kernel<DT, kOutPerLane, true>), dim3(ntiles), dim3(64 * waves), lds, s, pl,
-                           vec, stats, ba, wp);
+    constexpr int X = kOutPerLane;
+    if (wp.unit_counts && wp.n <= 8)
+        hipLaunchKernelGGL((boxcar_kernel<DT, X, true, 8>), dim3(ntiles), dim3(64 * waves), lds, s, pl, vec, stats,
+                           ba, wp);
+    else if (wp.unit_counts && wp.n <= 16)
+        hipLaunchKernelGGL((boxcar_kernel<DT, X, true, 16>), dim3(ntiles), dim3(64 * waves), lds, s, pl, vec, stats,
+                           ba, wp);
+    else if (wp.unit_counts)
+        hipLaunchKernelGGL((boxcar_kernel<DT, X, true, 0>), dim3(ntiles), dim3(64 * waves), lds, s, pl, vec, stats,
+                           ba, wp);
     else
-        hipLaunchKernelGGL((boxcar_kernel<DT, kOutPerLane, false>), dim3(ntiles), dim3(64 * waves), lds, s, pl,
-                           vec, stats, ba, wp);
+        hipLaunchKernelGGL((boxcar_kernel<DT, X, false, 0>), dim3(ntiles), dim3(64 * waves), lds, s, pl, vec, stats,
+                           ba, wp);
     return hipGetLastError();
 }
 
