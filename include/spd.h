@@ -193,6 +193,45 @@ spd_status select_candidates(const float* snr, const uint8_t* widx, int64_t n_ro
                              int64_t t_offset, spd_candidate* cand, int64_t cand_capacity,
                              int64_t* cand_count, void* stream);
 
+/*
+ * spd_detect -- the whole path (Sec. 2.1-2.4) over one plane in one call:
+ *   the result of msd_compute(x, p, 0, 0, NULL, stats, workspace, ...)
+ *   followed by boxcar_snr(x, p, stats, ...) on `stream`, with identical
+ *   statistics, SNRs and width indices and the same candidate set (its
+ *   order may differ).
+ *   In ROW scope the rows are cut into row_chunks consecutive chunks.  Each
+ *   chunk's statistics (Sec. 2.1-2.2) are computed on aux_stream and its
+ *   boxcars (Sec. 2.3-2.4) on stream as soon as they are ready, so the
+ *   bandwidth-bound statistics pass of later chunks overlaps the
+ *   arithmetic-bound boxcar pass of earlier ones.  The overlap shortens the
+ *   call only where neither pass fills the device by itself; each launch of
+ *   the 4096 x 2^20 plane does, and there the two passes share the compute
+ *   units rather than overlap.  aux_stream waits for
+ *   the work enqueued on `stream` before this call, and `stream` waits for
+ *   every chunk's statistics before the call's last boxcar: work enqueued on
+ *   `stream` afterwards sees all outputs.  The call enqueues work on both
+ *   streams, so the two must not be the same.
+ *   With aux_stream == NULL, row_chunks <= 1, or SPD_SCOPE_PLANE (whose
+ *   statistics span every row) the two steps run one after the other on
+ *   `stream`.
+ *   stats       [n_units] output.
+ *   snr_out, widx_out, out_stride, t_offset, cand, cand_capacity,
+ *   cand_count  as in boxcar_snr (*cand_count is reset once by the call).
+ *   workspace   >= spd_workspace_bytes(x, p) bytes, 256-byte aligned; the
+ *               chunks reuse it one after another on aux_stream.
+ *   row_chunks  1..SPD_MAX_ROW_CHUNKS (larger values are clamped, and so is
+ *               a value above n_rows).
+ *   The library keeps one set of HIP events per thread and device for the
+ *   stream dependencies, created on the first pipelined call; no device
+ *   memory is allocated.
+ */
+#define SPD_MAX_ROW_CHUNKS 64
+spd_status spd_detect(const spd_plane* x, const spd_params* p, spd_row_stats* stats,
+                      float* snr_out, uint8_t* widx_out, int64_t out_stride, int64_t t_offset,
+                      spd_candidate* cand, int64_t cand_capacity, int64_t* cand_count,
+                      void* workspace, size_t workspace_bytes, int32_t row_chunks,
+                      void* stream, void* aux_stream);
+
 /* ------------------------------------------------------------------------
  * Batched form: the same path over many beams of uneven shape per step.
  * Every beam gets per-row statistics (Sec. 2.1-2.2), then the boxcar/SNR

@@ -100,6 +100,9 @@ def load():
         lib.boxcar_snr.restype = ctypes.c_int
         lib.select_candidates.argtypes = [vp, vp, i64, i64, i64, P(SpdParams), i64, vp, i64, vp, vp]
         lib.select_candidates.restype = ctypes.c_int
+        lib.spd_detect.argtypes = [P(SpdPlane), P(SpdParams), vp, vp, vp, i64, i64, vp, i64, vp, vp,
+                                   ctypes.c_size_t, i32, vp, vp]
+        lib.spd_detect.restype = ctypes.c_int
         lib.spd_batch_plan_create.argtypes = [P(SpdPlane), i32, P(SpdParams), i32, P(vp)]
         lib.spd_batch_plan_create.restype = ctypes.c_int
         lib.spd_batch_run.argtypes = [vp, vp, i64, vp, i32, vp]
@@ -244,6 +247,55 @@ def select_candidates(snr: torch.Tensor, widx: torch.Tensor, params: Params, *, 
     _check(lib.select_candidates(snr.data_ptr(), widx.data_ptr(), n_rows, ncols, snr.stride(0),
                                  ctypes.byref(params.c), int(t_offset), cand.data_ptr(), cand.shape[0],
                                  cand_count.data_ptr(), _stream(stream)))
+
+
+_aux_streams = {}
+
+
+def aux_stream_for(device) -> torch.cuda.Stream:
+    """A side stream per device (default priority) for spd_detect's statistics pass."""
+    idx = torch.device(device).index
+    idx = torch.cuda.current_device() if idx is None else idx
+    st = _aux_streams.get(idx)
+    if st is None:
+        st = _aux_streams[idx] = torch.cuda.Stream(device=idx)
+    return st
+
+
+def spd_detect(x: torch.Tensor, params: Params, *, scale=None, zero=None, stats: Optional[torch.Tensor] = None,
+               snr: Optional[torch.Tensor] = None, widx: Optional[torch.Tensor] = None,
+               out_stride: Optional[int] = None, t_offset: int = 0, cand: Optional[torch.Tensor] = None,
+               cand_count: Optional[torch.Tensor] = None, workspace: Optional[torch.Tensor] = None,
+               row_chunks: int = 1, stream=None, aux_stream=None) -> torch.Tensor:
+    """The whole path in one call (statistics, boxcars, fused threshold).
+    With ``row_chunks`` > 1 and an ``aux_stream`` ("auto": a cached side
+    stream of the plane's device) the statistics of later row chunks run
+    beside the boxcars of earlier ones; by default both steps run on
+    ``stream``.  Returns stats."""
+    lib = load()
+    pl = plane_struct(x, scale, zero)
+    units = params.n_units(x.shape[0])
+    if stats is None:
+        stats = torch.empty((units, STATS_FIELDS), dtype=torch.float64, device=x.device)
+    if workspace is None:
+        need = lib.spd_workspace_bytes(ctypes.byref(pl), ctypes.byref(params.c))
+        if need == 0:
+            _check(1)
+        workspace = torch.empty(need, dtype=torch.uint8, device=x.device)
+    if out_stride is None:
+        out_stride = snr.stride(0) if snr is not None else (widx.stride(0) if widx is not None else 0)
+    if isinstance(aux_stream, str):
+        aux_stream = aux_stream_for(x.device)
+    aux = _stream(aux_stream) if aux_stream is not None else None
+    cap = cand.shape[0] if cand is not None else 0
+    _check(lib.spd_detect(ctypes.byref(pl), ctypes.byref(params.c), stats.data_ptr(),
+                          snr.data_ptr() if snr is not None else None,
+                          widx.data_ptr() if widx is not None else None, int(out_stride), int(t_offset),
+                          cand.data_ptr() if cand is not None else None, int(cap),
+                          cand_count.data_ptr() if cand_count is not None else None,
+                          workspace.data_ptr(), workspace.numel() * workspace.element_size(), int(row_chunks),
+                          _stream(stream), aux))
+    return stats
 
 
 def new_candidates(capacity: int, device) -> torch.Tensor:

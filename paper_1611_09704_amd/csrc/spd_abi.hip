@@ -166,6 +166,126 @@ bool build_width_plan(const spd_params* p, int X, WidthPlan& wp, BoxcarArgs& ba,
     return true;
 }
 
+spd_status check_msd_workspace(const spd_plane* x, const MsdLayout& m, const void* workspace, size_t bytes)
+{
+    if (!workspace) return fail(SPD_E_INVALID, "workspace is NULL");
+    if (((uintptr_t)workspace) % 256) return fail(SPD_E_INVALID, "workspace not 256-byte aligned");
+    if (bytes < m.ws_bytes) return fail(SPD_E_NOMEM, "workspace %zu bytes < %zu needed", bytes, m.ws_bytes);
+    if ((uint64_t)x->n_rows * (uint64_t)m.nblk * 256u > kMaxGridItems)
+        return fail(SPD_E_UNSUPPORTED, "plane too large for one launch (%lld blocks)",
+                    (long long)(x->n_rows * m.nblk));
+    return SPD_OK;
+}
+
+// Block partials (Sec. 2.1) then the FP64 merge and sigma_N coefficients
+// (Sec. 2.1-2.2) of every unit of x, on s.  Arguments already validated.
+spd_status enqueue_msd(const spd_plane* x, const spd_params* p, int64_t new_col_begin, bool accumulate,
+                       spd_msd_state* state, spd_row_stats* stats, double* part, const MsdLayout& m, hipStream_t s)
+{
+    const int nmax = p->widths[p->n_widths - 1];
+    const int64_t nout = x->n_cols - nmax + 1;
+    const bool need_y = p->sigma_mode != SPD_SIGMA_SQRTN;
+    hipError_t e = launch_msd(x->dtype, plane_arg(x), plane_vec_ok(x), need_y, new_col_begin, m.bc, m.nblk,
+                              nmax, nout, part, s);
+    if (e != hipSuccess) return device_status(e, "msd partial launch");
+    const bool plane = p->scope == SPD_SCOPE_PLANE;
+    const int64_t units = plane ? 1 : x->n_rows;
+    const int64_t per_unit = plane ? x->n_rows * m.nblk : m.nblk;
+    e = launch_finalize(part, units, per_unit, need_y, accumulate, state, stats, nmax, p->sigma_mode,
+                        (double)p->auto_kappa, s);
+    return device_status(e, "msd finalize launch");
+}
+
+// Validates the boxcar outputs and fills the launch plan for the whole plane.
+spd_status plan_boxcar(const spd_plane* x, const spd_params* p, const spd_row_stats* stats, float* snr_out,
+                       uint8_t* widx_out, int64_t out_stride, int64_t t_offset, spd_candidate* cand,
+                       int64_t cand_capacity, int64_t* cand_count, BoxcarPlan& bp)
+{
+    if (!stats) return fail(SPD_E_INVALID, "stats is NULL");
+    if (!snr_out && !widx_out && !cand) return fail(SPD_E_INVALID, "no output requested");
+    const int nmax = p->widths[p->n_widths - 1];
+    const int64_t nout = x->n_cols - nmax + 1;
+    if ((snr_out || widx_out) && out_stride < nout)
+        return fail(SPD_E_INVALID, "out_stride=%lld < %lld outputs per row", (long long)out_stride, (long long)nout);
+    if (cand && (!cand_count || cand_capacity < 0))
+        return fail(SPD_E_INVALID, "candidate list needs cand_count and capacity >= 0");
+    const int X = kOutPerLane;
+    memset(&bp.ba, 0, sizeof bp.ba);
+    bp.waves = 4;
+    if (!build_width_plan(p, X, bp.wp, bp.ba, bp.waves)) return fail(SPD_E_UNSUPPORTED, "width list does not fit in LDS");
+    BoxcarArgs& ba = bp.ba;
+    ba.scope = p->scope;
+    ba.nout = nout;
+    ba.tiles_per_row = (nout + (int64_t)bp.waves * 64 * X - 1) / ((int64_t)bp.waves * 64 * X);
+    ba.snr = snr_out;
+    ba.widx = widx_out;
+    ba.out_stride = out_stride;
+    ba.t_offset = t_offset;
+    ba.cand = cand;
+    ba.cand_capacity = cand_capacity;
+    ba.cand_count = cand_count;
+    ba.threshold = p->threshold;
+    const uint64_t ntiles = (uint64_t)x->n_rows * (uint64_t)ba.tiles_per_row;
+    if (ntiles * 64u * (uint64_t)bp.waves > kMaxGridItems) return fail(SPD_E_UNSUPPORTED, "plane too large for one launch");
+    return SPD_OK;
+}
+
+// Boxcar launch over rows [r0, r0 + rows) of the plan's plane; x is that row
+// range as its own plane and stats its first unit.
+spd_status enqueue_boxcar(const spd_plane* x, const spd_row_stats* stats, const BoxcarPlan& bp, int64_t r0,
+                          int64_t rows, hipStream_t s)
+{
+    BoxcarArgs ba = bp.ba;
+    ba.row0 = (int32_t)r0;
+    if (ba.snr) ba.snr += r0 * ba.out_stride;
+    if (ba.widx) ba.widx += r0 * ba.out_stride;
+    const uint64_t ntiles = (uint64_t)rows * (uint64_t)ba.tiles_per_row;
+    hipError_t e = launch_boxcar(x->dtype, plane_arg(x), plane_vec_ok(x), stats, ba, bp.wp, kOutPerLane, bp.waves,
+                                 ntiles, s);
+    return device_status(e, "boxcar launch");
+}
+
+// Rows [r0, r0 + rows) of x as a plane of their own.
+spd_plane row_slice(const spd_plane* x, int64_t r0, int64_t rows)
+{
+    spd_plane sub = *x;
+    sub.data = (const char*)x->data + (size_t)(r0 * x->row_stride) * (size_t)elem_size(x->dtype);
+    sub.n_rows = rows;
+    if (x->row_scale) sub.row_scale = x->row_scale + r0;
+    if (x->row_zero) sub.row_zero = x->row_zero + r0;
+    return sub;
+}
+
+// One fork event and one event per chunk, per thread and device, created on
+// first use and kept for the life of the thread.  A stream wait binds to the
+// record that precedes it, so the events can be recorded again by the next call.
+spd_status detect_events(hipEvent_t** out)
+{
+    struct Events {
+        int device = -1;
+        std::vector<hipEvent_t> ev;
+    };
+    static thread_local std::vector<Events> cache;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_status(e, "hipGetDevice");
+    for (auto& c : cache)
+        if (c.device == dev) { *out = c.ev.data(); return SPD_OK; }
+    Events c;
+    c.device = dev;
+    c.ev.assign(SPD_MAX_ROW_CHUNKS + 1, nullptr);
+    for (auto& h : c.ev) {
+        if ((e = hipEventCreateWithFlags(&h, hipEventDisableTiming)) != hipSuccess) {
+            for (auto& g : c.ev)
+                if (g) hipEventDestroy(g);
+            return device_status(e, "event create");
+        }
+    }
+    cache.push_back(std::move(c));
+    *out = cache.back().ev.data();
+    return SPD_OK;
+}
+
 }  // namespace spd
 
 using namespace spd;
@@ -195,27 +315,9 @@ spd_status msd_compute(const spd_plane* x, const spd_params* p, int64_t new_col_
     if (new_col_begin < 0 || new_col_begin > x->n_cols)
         return fail(SPD_E_INVALID, "new_col_begin=%lld outside [0, n_cols]", (long long)new_col_begin);
     const MsdLayout m = msd_layout(x);
-    if (!workspace) return fail(SPD_E_INVALID, "workspace is NULL");
-    if (((uintptr_t)workspace) % 256) return fail(SPD_E_INVALID, "workspace not 256-byte aligned");
-    if (workspace_bytes < m.ws_bytes)
-        return fail(SPD_E_NOMEM, "workspace %zu bytes < %zu needed", workspace_bytes, m.ws_bytes);
-    const int nmax = p->widths[p->n_widths - 1];
-    const int64_t nout = x->n_cols - nmax + 1;
-    const bool need_y = p->sigma_mode != SPD_SIGMA_SQRTN;
-    if ((uint64_t)x->n_rows * (uint64_t)m.nblk * 256u > kMaxGridItems)
-        return fail(SPD_E_UNSUPPORTED, "plane too large for one launch (%lld blocks)",
-                    (long long)(x->n_rows * m.nblk));
-    hipStream_t s = (hipStream_t)stream;
-    double* part = (double*)workspace;
-    hipError_t e = launch_msd(x->dtype, plane_arg(x), plane_vec_ok(x), need_y, new_col_begin, m.bc, m.nblk,
-                              nmax, nout, part, s);
-    if (e != hipSuccess) return device_status(e, "msd partial launch");
-    const bool plane = p->scope == SPD_SCOPE_PLANE;
-    const int64_t units = plane ? 1 : x->n_rows;
-    const int64_t per_unit = plane ? x->n_rows * m.nblk : m.nblk;
-    e = launch_finalize(part, units, per_unit, need_y, accumulate != 0, state, stats, nmax, p->sigma_mode,
-                        (double)p->auto_kappa, s);
-    return device_status(e, "msd finalize launch");
+    if ((st = check_msd_workspace(x, m, workspace, workspace_bytes))) return st;
+    return enqueue_msd(x, p, new_col_begin, accumulate != 0, state, stats, (double*)workspace, m,
+                       (hipStream_t)stream);
 }
 
 spd_status boxcar_snr(const spd_plane* x, const spd_params* p, const spd_row_stats* stats, float* snr_out,
@@ -225,40 +327,63 @@ spd_status boxcar_snr(const spd_plane* x, const spd_params* p, const spd_row_sta
     clear_error();
     spd_status st;
     if ((st = check_params(p)) || (st = check_plane(x, p))) return st;
-    if (!stats) return fail(SPD_E_INVALID, "stats is NULL");
-    if (!snr_out && !widx_out && !cand) return fail(SPD_E_INVALID, "no output requested");
-    const int nmax = p->widths[p->n_widths - 1];
-    const int64_t nout = x->n_cols - nmax + 1;
-    if ((snr_out || widx_out) && out_stride < nout)
-        return fail(SPD_E_INVALID, "out_stride=%lld < %lld outputs per row", (long long)out_stride, (long long)nout);
-    if (cand && (!cand_count || cand_capacity < 0))
-        return fail(SPD_E_INVALID, "candidate list needs cand_count and capacity >= 0");
-    const int X = kOutPerLane;
-    WidthPlan wp;
-    BoxcarArgs ba;
-    memset(&ba, 0, sizeof ba);
-    int waves = 4;
-    if (!build_width_plan(p, X, wp, ba, waves)) return fail(SPD_E_UNSUPPORTED, "width list does not fit in LDS");
-    ba.scope = p->scope;
-    ba.nout = nout;
-    ba.tiles_per_row = (nout + (int64_t)waves * 64 * X - 1) / ((int64_t)waves * 64 * X);
-    ba.snr = snr_out;
-    ba.widx = widx_out;
-    ba.out_stride = out_stride;
-    ba.t_offset = t_offset;
-    ba.cand = cand;
-    ba.cand_capacity = cand_capacity;
-    ba.cand_count = cand_count;
-    ba.threshold = p->threshold;
+    BoxcarPlan bp;
+    if ((st = plan_boxcar(x, p, stats, snr_out, widx_out, out_stride, t_offset, cand, cand_capacity, cand_count,
+                          bp)))
+        return st;
     hipStream_t s = (hipStream_t)stream;
     if (cand) {
         hipError_t e = launch_zero_count(cand_count, s);
         if (e != hipSuccess) return device_status(e, "count reset launch");
     }
-    const uint64_t ntiles = (uint64_t)x->n_rows * (uint64_t)ba.tiles_per_row;
-    if (ntiles * 64u * (uint64_t)waves > kMaxGridItems) return fail(SPD_E_UNSUPPORTED, "plane too large for one launch");
-    hipError_t e = launch_boxcar(x->dtype, plane_arg(x), plane_vec_ok(x), stats, ba, wp, X, waves, ntiles, s);
-    return device_status(e, "boxcar launch");
+    return enqueue_boxcar(x, stats, bp, 0, x->n_rows, s);
+}
+
+spd_status spd_detect(const spd_plane* x, const spd_params* p, spd_row_stats* stats, float* snr_out,
+                      uint8_t* widx_out, int64_t out_stride, int64_t t_offset, spd_candidate* cand,
+                      int64_t cand_capacity, int64_t* cand_count, void* workspace, size_t workspace_bytes,
+                      int32_t row_chunks, void* stream, void* aux_stream)
+{
+    clear_error();
+    spd_status st;
+    if ((st = check_params(p)) || (st = check_plane(x, p))) return st;
+    if (!stats) return fail(SPD_E_INVALID, "stats is NULL");
+    if (row_chunks < 1) return fail(SPD_E_INVALID, "row_chunks=%d < 1", row_chunks);
+    if (aux_stream && aux_stream == stream) return fail(SPD_E_INVALID, "aux_stream must differ from stream");
+    const MsdLayout m = msd_layout(x);
+    if ((st = check_msd_workspace(x, m, workspace, workspace_bytes))) return st;
+    BoxcarPlan bp;
+    if ((st = plan_boxcar(x, p, stats, snr_out, widx_out, out_stride, t_offset, cand, cand_capacity, cand_count,
+                          bp)))
+        return st;
+    hipStream_t s = (hipStream_t)stream, a = (hipStream_t)aux_stream;
+    double* part = (double*)workspace;
+    const int64_t chunks = std::min<int64_t>(std::min<int64_t>(row_chunks, SPD_MAX_ROW_CHUNKS), x->n_rows);
+    const bool pipelined = a && chunks > 1 && p->scope == SPD_SCOPE_ROW;
+    hipEvent_t* ev = nullptr;
+    if (pipelined && (st = detect_events(&ev))) return st;
+
+    hipError_t e;
+    if (cand && (e = launch_zero_count(cand_count, s)) != hipSuccess) return device_status(e, "count reset launch");
+    if (!pipelined) {
+        if ((st = enqueue_msd(x, p, 0, false, nullptr, stats, part, m, s))) return st;
+        return enqueue_boxcar(x, stats, bp, 0, x->n_rows, s);
+    }
+    // fork: the statistics stream starts after everything already on `stream`
+    if ((e = hipEventRecord(ev[0], s)) != hipSuccess) return device_status(e, "event record");
+    if ((e = hipStreamWaitEvent(a, ev[0], 0)) != hipSuccess) return device_status(e, "stream wait");
+    const int64_t per = (x->n_rows + chunks - 1) / chunks;
+    int k = 0;
+    for (int64_t r0 = 0; r0 < x->n_rows; r0 += per, ++k) {
+        const int64_t rc = std::min<int64_t>(per, x->n_rows - r0);
+        const spd_plane sub = row_slice(x, r0, rc);
+        // the chunk's partials use the whole plane's block layout, so they fit the workspace
+        if ((st = enqueue_msd(&sub, p, 0, false, nullptr, stats + r0, part, m, a))) return st;
+        if ((e = hipEventRecord(ev[k + 1], a)) != hipSuccess) return device_status(e, "event record");
+        if ((e = hipStreamWaitEvent(s, ev[k + 1], 0)) != hipSuccess) return device_status(e, "stream wait");
+        if ((st = enqueue_boxcar(&sub, stats + r0, bp, r0, rc, s))) return st;
+    }
+    return SPD_OK;
 }
 
 spd_status select_candidates(const float* snr, const uint8_t* widx, int64_t n_rows, int64_t n_out_cols,

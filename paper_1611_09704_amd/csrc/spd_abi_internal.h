@@ -25,4 +25,21 @@ MsdLayout msd_layout(const spd_plane* x);
 bool build_width_plan(const spd_params* p, int X, WidthPlan& wp, BoxcarArgs& ba, int& waves,
                       size_t lds_reserve = 0);
 
+struct BoxcarPlan {
+    WidthPlan wp;
+    BoxcarArgs ba;
+    int waves;
+};
+
+spd_status check_msd_workspace(const spd_plane* x, const MsdLayout& m, const void* workspace, size_t bytes);
+spd_status enqueue_msd(const spd_plane* x, const spd_params* p, int64_t new_col_begin, bool accumulate,
+                       spd_msd_state* state, spd_row_stats* stats, double* part, const MsdLayout& m, hipStream_t s);
+spd_status plan_boxcar(const spd_plane* x, const spd_params* p, const spd_row_stats* stats, float* snr_out,
+                       uint8_t* widx_out, int64_t out_stride, int64_t t_offset, spd_candidate* cand,
+                       int64_t cand_capacity, int64_t* cand_count, BoxcarPlan& bp);
+spd_status enqueue_boxcar(const spd_plane* x, const spd_row_stats* stats, const BoxcarPlan& bp, int64_t r0,
+                          int64_t rows, hipStream_t s);
+spd_plane row_slice(const spd_plane* x, int64_t r0, int64_t rows);
+spd_status detect_events(hipEvent_t** out);
+
 }  // namespace spd

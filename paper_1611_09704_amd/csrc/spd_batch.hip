@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void batch_finalize_kernel(const BeamDesc* bea
 }
 
 template <int DT, int X, bool UNIT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void batch_boxcar_kernel(const BeamDesc* beams, int n_beams, int64_t total,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(X == 4 ? 5 : (UNIT ? 4 : 3)))) void batch_boxcar_kernel(const BeamDesc* beams, int n_beams, int64_t total,
                                                            int64_t* queue, int grab, const spd_row_stats* stats,
                                                            BoxcarArgs ba, WidthPlan wp)
 {
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void b
 // All tiles of all beams in one ordinary launch: work-group i takes tile i
 // (XCD-aware numbering), finds its beam and row, and runs the same tile code.
 template <int DT, int X, bool UNIT>
-__global__ __launch_bounds__(256) void batch_boxcar_grid_kernel(const BeamDesc* beams, int n_beams,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UNIT ? 5 : 1))) void batch_boxcar_grid_kernel(const BeamDesc* beams, int n_beams,
                                                                 const spd_row_stats* stats, BoxcarArgs ba,
                                                                 WidthPlan wp)
 {

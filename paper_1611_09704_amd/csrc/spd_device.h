@@ -276,7 +276,7 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int kMsdSubTile = 512;   // window starts per wave sub-tile in msd_block_xy
+constexpr int kMsdSubTile = 1024;  // window starts per wave sub-tile in msd_block_xy
 
 // LDS floats per wave of msd_block_xy for a given widest boxcar.
 __host__ __device__ inline int msd_xy_npw(int nmax) { return (kMsdSubTile + nmax + 255) / 256 * 256; }
@@ -304,7 +304,6 @@ __device__ void msd_block_xy(const PlaneArg& pl, bool vec, int64_t r, int64_t b,
     for (int64_t u0 = c0 + (int64_t)wave * TSW; u0 < c1; u0 += (int64_t)nw * TSW) {
         const int64_t u1 = min(u0 + TSW, c1);
         float carry = 0.f;
-        float4 ekeep[TSW / 256];
         for (int m = 0; m < nrow; ++m) {
             const int p = 256 * m + 4 * lane;
             const int64_t c = u0 + p;
@@ -316,15 +315,15 @@ __device__ void msd_block_xy(const PlaneArg& pl, bool vec, int64_t r, int64_t b,
             carry += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(inc), 63));
             const float4 e = make_float4(ex, ex + l0, ex + l1, ex + l2);
             *(float4*)(E + p) = e;
-            if (m < TSW / 256) ekeep[m] = e;
         }
         wave_sync();
 #pragma unroll
         for (int m = 0; m < TSW / 256; ++m) {
             const int p = 256 * m + 4 * lane;
             const int64_t t = u0 + p;
-            const float4 y = make_float4(E[p + nmax] - ekeep[m].x, E[p + 1 + nmax] - ekeep[m].y,
-                                         E[p + 2 + nmax] - ekeep[m].z, E[p + 3 + nmax] - ekeep[m].w);
+            const float4 e = *(const float4*)(E + p);
+            const float4 y = make_float4(E[p + nmax] - e.x, E[p + 1 + nmax] - e.y, E[p + 2 + nmax] - e.z,
+                                         E[p + 3 + nmax] - e.w);
             msd_add4_clipped(sy, y, t, u0, yhi);
         }
         wave_sync();
@@ -514,7 +513,7 @@ __device__ void boxcar_tile(const PlaneArg& pl, bool vec, int64_t r, int64_t tt,
                     const unsigned long long k = base + (unsigned long long)before;
                     if (k < (unsigned long long)ba.cand_capacity) {
                         spd_candidate cd;
-                        cd.row = (int32_t)r;
+                        cd.row = (int32_t)r + ba.row0;
                         cd.width = wp.width[idx];
                         cd.t = t + ba.t_offset;
                         cd.snr = m;

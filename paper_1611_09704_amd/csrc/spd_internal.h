@@ -50,7 +50,7 @@ struct BoxcarArgs {
     int32_t scope;
     int32_t npw;            // floats per presummed array (>= 64X + Nmax - 1, multiple of 4)
     int32_t wave_floats;    // LDS floats per wave: n_arr*npw
-    int32_t reserved;
+    int32_t row0;           // added to the row stored in each candidate (row-chunked launches)
     int64_t tiles_per_row;
     int64_t nout;           // valid starts per row
     float* snr;

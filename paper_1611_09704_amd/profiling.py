@@ -73,11 +73,17 @@ def _csvs(d, suffix):
     return sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
 
 
-def _short(name: str) -> str:
-    for key in ("boxcar_kernel", "msd_xy_kernel", "msd_x_kernel", "msd_finalize_kernel", "select_kernel",
-                "zero_count_kernel"):
+def _short(name: str, with_args: bool = False) -> str:
+    """Kernel name without namespace and signature; ``with_args`` keeps the
+    template arguments (dtype, outputs per lane, unit steps, small path)."""
+    targs = ""
+    if with_args and "<" in name.split("(")[0]:
+        targs = "<" + name.split("(")[0].split("<", 1)[1]
+    for key in ("batch_boxcar_grid_kernel", "batch_boxcar_kernel", "batch_msd_kernel", "batch_finalize_kernel",
+                "boxcar_kernel", "msd_xy_kernel", "msd_x_kernel", "msd_finalize_kernel", "select_kernel",
+                "fill_i64_kernel"):
         if key in name:
-            return key
+            return key + targs
     if "copyBuffer" in name:
         return "calibration_copy"
     return name[:60]
@@ -104,13 +110,34 @@ def summarize(args):
         lines.append("command: `%s`\n" % args.trace_cmd)
         lines.append("| kernel | calls | average ms | total ms | share |")
         lines.append("|---|---|---|---|---|")
-        for row in csv.DictReader(open(stats[0])):
-            name = _short(row["Name"])
-            if not any(k in name for k in ("boxcar", "msd", "select", "zero_count")):
+        rows = list(csv.DictReader(open(stats[0])))
+        total = sum(float(r["TotalDurationNs"]) for r in rows) or 1.0
+        for row in rows:
+            name = _short(row["Name"], with_args=True)
+            if not any(k in name for k in ("boxcar", "msd", "select", "finalize", "fill_i64")):
                 continue
-            lines.append("| %s | %s | %.4f | %.3f | %s%% |" % (
+            lines.append("| %s | %s | %.4f | %.3f | %.2f%% |" % (
                 name, row["Calls"], float(row["AverageNs"]) / 1e6, float(row["TotalDurationNs"]) / 1e6,
-                row.get("Percentage", "")[:5]))
+                100.0 * float(row["TotalDurationNs"]) / total))
+        lines.append("")
+    traces = _csvs(args.trace, "kernel_trace.csv") if args.trace else []
+    if traces:
+        groups = defaultdict(list)
+        meta = {}
+        for row in csv.DictReader(open(traces[0])):
+            name = _short(row["Kernel_Name"], with_args=True)
+            if not any(k in name for k in ("boxcar", "msd", "select", "finalize", "fill_i64")):
+                continue
+            key = (name, int(row["Grid_Size_X"]))
+            groups[key].append((int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e6)
+            meta[key] = row.get("Workgroup_Size_X", "")
+        lines.append("## Launches by kernel and grid size (rocprofv3 --kernel-trace, same run)\n")
+        lines.append("| kernel | grid work-items | work-group | calls | average ms | min ms | max ms |")
+        lines.append("|---|---|---|---|---|---|---|")
+        for key in sorted(groups, key=lambda k: -sum(groups[k])):
+            d = groups[key]
+            lines.append("| %s | %d | %s | %d | %.4f | %.4f | %.4f |" % (
+                key[0], key[1], meta[key], len(d), sum(d) / len(d), min(d), max(d)))
         lines.append("")
     traffic = {}
     if args.fetch and args.write:
@@ -162,6 +189,56 @@ def summarize(args):
         print("wrote", tpath)
 
 
+N_CU, N_XCD, N_SIMD = 256, 8, 1024
+
+
+def counter_summary(args):
+    """Clock, LDS and VALU use of each path kernel from --pmc runs of SQ and
+    GRBM counters (rocprofv3 reports each counter summed over XCDs and shader
+    engines: GRBM_GUI_ACTIVE / 8 is the clock count of one XCD)."""
+    lines = ["# %s\n" % args.title]
+    for d, cmd in zip(args.dirs, args.cmds or [""] * len(args.dirs)):
+        vals = defaultdict(lambda: defaultdict(float))
+        span = {}
+        for f in _csvs(d, "counter_collection.csv"):
+            for row in csv.DictReader(open(f)):
+                name = _short(row["Kernel_Name"], with_args=True)
+                if not any(k in name for k in ("boxcar", "msd")):
+                    continue
+                key = (name, row.get("Dispatch_Id"))
+                vals[key][row["Counter_Name"]] += float(row["Counter_Value"])
+                span[key] = (int(row["Start_Timestamp"]), int(row["End_Timestamp"]))
+        lines.append("command: `%s`\n" % cmd)
+        lines.append("| kernel | ms | counter | total | derived |")
+        lines.append("|---|---|---|---|---|")
+        for key in sorted(vals):
+            c = vals[key]
+            ms = (span[key][1] - span[key][0]) / 1e6
+            cyc = c.get("GRBM_GUI_ACTIVE", 0.0) / N_XCD
+            for n in sorted(c):
+                der = ""
+                if n == "GRBM_GUI_ACTIVE":
+                    der = "clock %.2f GHz" % (cyc / (ms * 1e-3) / 1e9)
+                elif cyc and n == "SQ_INSTS_VALU":
+                    der = "%.2f VALU instructions per SIMD per 4 clocks (2 = dual-issue peak)" % (
+                        c[n] / (N_SIMD * cyc / 4))
+                elif cyc and n == "SQ_ACTIVE_INST_VALU2":
+                    der = "two VALU issued in %.0f%% of SIMD quad-cycles" % (100 * c[n] / (N_SIMD * cyc / 4))
+                elif cyc and n == "SQ_LDS_IDX_ACTIVE":
+                    der = "LDS busy %.0f%% of CU clocks" % (100 * c[n] / (N_CU * cyc))
+                elif cyc and n == "SQ_LDS_BANK_CONFLICT":
+                    der = "bank-conflict stall %.1f%% of CU clocks" % (100 * c[n] / (N_CU * cyc))
+                elif cyc and n == "SQ_INSTS_LDS_LOAD_BANDWIDTH":
+                    der = "%.0f bytes read from LDS per CU clock" % (c[n] * 64 / (N_CU * cyc))
+                lines.append("| %s | %.3f | %s | %.4g | %s |" % (key[0], ms, n, c[n], der))
+        lines.append("")
+    lines.append("kernel sources sha: %s\n" % kernel_source_sha())
+    path = os.path.join(args.out, args.name + ".md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines))
+    print("wrote", path)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -181,8 +258,14 @@ def main(argv=None):
     s.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     s.add_argument("--name", required=True)
     s.add_argument("--title", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("--dirs", nargs="+", required=True)
+    c.add_argument("--cmds", nargs="*")
+    c.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    c.add_argument("--name", required=True)
+    c.add_argument("--title", required=True)
     a = ap.parse_args(argv)
-    (run if a.cmd == "run" else summarize)(a)
+    {"run": run, "summarize": summarize, "counters": counter_summary}[a.cmd](a)
 
 
 if __name__ == "__main__":

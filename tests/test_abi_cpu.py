@@ -106,6 +106,27 @@ def test_call_validation(lib):
     assert "threshold" in _err(lib)
 
 
+def test_detect_validation(lib):
+    p = B.Params([1, 2, 4, 8], 5.0)
+    pl = _plane()
+    ws = lib.spd_workspace_bytes(ctypes.byref(pl), ctypes.byref(p.c))
+
+    def call(stats=FAKE, snr=FAKE, stride=1000, cand=None, cap=0, count=None, work=FAKE * 16, nbytes=ws, chunks=4,
+             stream=FAKE, aux=FAKE + 64, params=p, plane=pl):
+        return lib.spd_detect(ctypes.byref(plane), ctypes.byref(params.c), stats, snr, None, stride, 0, cand, cap,
+                              count, work, nbytes, chunks, stream, aux)
+
+    for kw, code, msg in [(dict(stats=None), 1, "stats"), (dict(chunks=0), 1, "row_chunks"),
+                          (dict(aux=FAKE), 1, "aux_stream"), (dict(nbytes=ws - 1), 3, "workspace"),
+                          (dict(work=FAKE + 8), 1, "aligned"), (dict(work=None), 1, "workspace"),
+                          (dict(snr=None), 1, "no output"), (dict(stride=10), 1, "out_stride"),
+                          (dict(snr=None, cand=FAKE, cap=5), 1, "cand_count"),
+                          (dict(plane=_plane(cols=1000, stride=999)), 1, "row_stride"),
+                          (dict(params=B.Params([1, 3, 2], 5.0)), 1, "strictly")]:
+        assert call(**kw) == code, kw
+        assert msg in _err(lib), (kw, _err(lib))
+
+
 def test_batch_validation(lib):
     p = B.Params([1, 2, 4, 8], 5.0)
     out = ctypes.c_void_p(123)
