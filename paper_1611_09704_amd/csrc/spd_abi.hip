@@ -3,6 +3,7 @@
 // the thread-local error string.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -111,8 +112,62 @@ MsdLayout msd_layout(const spd_plane* x)
     return m;
 }
 
+// The register-window form of the boxcar kernel (8 consecutive starts per
+// lane): used for the list 1..n with n <= 16, and for lists of whole groups of
+// 8 unit-count widths that each step by 1 or 2 through one array from an
+// offset that is a multiple of 8.  Leaves wp.win = 0 when neither applies or
+// the padded window does not fit.
+static void plan_window(const int* W, int n, bool unit, int X, size_t lds_cap, WidthPlan& wp, BoxcarArgs& ba,
+                        int& waves)
+{
+    if (X != kWinX || !unit) return;
+    bool contiguous = n <= 16;
+    for (int i = 0; i < n && contiguous; ++i) contiguous = W[i] == i + 1;
+    int kind = contiguous ? 2 : 0;
+    if (!kind && n % kGroup == 0) {
+        kind = 1;
+        for (int g = 0; g < n / kGroup && kind; ++g) {
+            const int i0 = g * kGroup;
+            const int o = i0 ? W[i0 - 1] : 0;
+            const int d = W[i0] - o;
+            if (o % 8 != 0 || (d != 1 && d != 2)) kind = 0;
+            for (int j = 1; j < kGroup && kind; ++j)
+                if (W[i0 + j] - W[i0 + j - 1] != d) kind = 0;
+            int arr = -1;
+            for (int a = 0; a < wp.n_arr; ++a)
+                if (wp.arr_gap[a] == d) arr = a;
+            if (arr < 0) kind = 0;
+        }
+    }
+    if (!kind) return;
+    const int nlog = 64 * X + std::max(wp.nmax, kind == 2 ? 16 : 0) + 8;
+    const int npp = (nlog + 7) / 8 * 9;
+    const int n_arr = kind == 2 ? 1 : wp.n_arr;
+    // the region also holds the epilogue's transpose (64X floats + 64X bytes); 16-byte multiple
+    const int wave_floats = (std::max(n_arr * npp, 64 * X + 16 * X) + 3) & ~3;
+    const size_t per_wave = (size_t)wave_floats * 4;
+    const size_t tables = (size_t)kWinTableFloats * 4;
+    if (tables + per_wave > lds_cap) return;
+    for (int g = 0; g < (kind == 1 ? n / kGroup : 0); ++g) {
+        const int i0 = g * kGroup;
+        const int o = i0 ? W[i0 - 1] : 0;
+        const int d = W[i0] - o;
+        int arr = 0;
+        for (int a = 0; a < wp.n_arr; ++a)
+            if (wp.arr_gap[a] == d) arr = a;
+        wp.gbase[g] = (uint32_t)(arr * npp + win_phys(o));
+        wp.gstep[g] = (uint8_t)d;
+    }
+    wp.win = kind;
+    wp.n_arr = n_arr;
+    ba.npw = npp;
+    ba.wave_floats = wave_floats;
+    waves = (int)std::min<size_t>(4, (lds_cap - tables) / per_wave);
+}
+
 // Presummed LDS arrays and per-width steps for the boxcar kernel.
-bool build_width_plan(const spd_params* p, int X, WidthPlan& wp, BoxcarArgs& ba, int& waves, size_t lds_reserve)
+bool build_width_plan(const spd_params* p, int X, WidthPlan& wp, BoxcarArgs& ba, int& waves, size_t lds_reserve,
+                      bool window)
 {
     const int n = p->n_widths;
     const int* W = p->widths;
@@ -163,6 +218,8 @@ bool build_width_plan(const spd_params* p, int X, WidthPlan& wp, BoxcarArgs& ba,
     wp.unit_counts = unit ? 1 : 0;
     ba.npw = npw;
     ba.wave_floats = wp.n_arr * npw;
+    wp.win = 0;
+    if (window) plan_window(W, n, unit, X, lds_cap, wp, ba, waves);
     return true;
 }
 
@@ -212,7 +269,10 @@ spd_status plan_boxcar(const spd_plane* x, const spd_params* p, const spd_row_st
     const int X = kOutPerLane;
     memset(&bp.ba, 0, sizeof bp.ba);
     bp.waves = 4;
-    if (!build_width_plan(p, X, bp.wp, bp.ba, bp.waves)) return fail(SPD_E_UNSUPPORTED, "width list does not fit in LDS");
+    const char* form = getenv("SPD_BOXCAR_FORM");          // "strided": never the register-window form
+    const bool window = !(form && strcmp(form, "strided") == 0);
+    if (!build_width_plan(p, X, bp.wp, bp.ba, bp.waves, 0, window))
+        return fail(SPD_E_UNSUPPORTED, "width list does not fit in LDS");
     BoxcarArgs& ba = bp.ba;
     ba.scope = p->scope;
     ba.nout = nout;
@@ -225,6 +285,8 @@ spd_status plan_boxcar(const spd_plane* x, const spd_params* p, const spd_row_st
     ba.cand_capacity = cand_capacity;
     ba.cand_count = cand_count;
     ba.threshold = p->threshold;
+    ba.out_vec = ((snr_out && (uintptr_t)snr_out % 16 == 0 && out_stride % 4 == 0) ? 1u : 0u) |
+                 ((widx_out && (uintptr_t)widx_out % 8 == 0 && out_stride % 8 == 0) ? 2u : 0u);
     const uint64_t ntiles = (uint64_t)x->n_rows * (uint64_t)ba.tiles_per_row;
     if (ntiles * 64u * (uint64_t)bp.waves > kMaxGridItems) return fail(SPD_E_UNSUPPORTED, "plane too large for one launch");
     return SPD_OK;

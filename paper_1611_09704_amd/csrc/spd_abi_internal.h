@@ -23,7 +23,7 @@ PlaneArg plane_arg(const spd_plane* x);
 bool plane_vec_ok(const spd_plane* x);
 MsdLayout msd_layout(const spd_plane* x);
 bool build_width_plan(const spd_params* p, int X, WidthPlan& wp, BoxcarArgs& ba, int& waves,
-                      size_t lds_reserve = 0);
+                      size_t lds_reserve = 0, bool window = false);
 
 struct BoxcarPlan {
     WidthPlan wp;

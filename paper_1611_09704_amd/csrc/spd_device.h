@@ -6,11 +6,15 @@
 //   finalize_unit                FP64 merge across blocks, sigma_N, Sec. 2.1-2.2
 //   boxcar_tile                  boxcars, SNR, highest SNR and its first width,
 //                                fused threshold; Sec. 2.3 / Algorithm 1, Sec. 2.4
+//   boxcar_tile_win              the same for width lists of stepped groups,
+//                                with each group's LDS reads held in registers
 //
 // The path is a streaming reduction plus a sliding-window scan: no dense
 // contraction, so everything is vector ALU and LDS work.  Loads are coalesced
 // along time, the contiguous axis.
 #pragma once
+
+#include <type_traits>
 
 #include "spd_internal.h"
 
@@ -650,6 +654,298 @@ __device__ void boxcar_tile(const PlaneArg& pl, bool vec, int64_t r, int64_t tt,
 #pragma unroll
             for (int j = 7; j >= 0; --j) idx = (s[j] == mx[i]) ? i0 + j : idx;
             emit(i, mx[i], idx);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sec. 2.3 / Algorithm 1, register-window form
+// ---------------------------------------------------------------------------
+//
+// Lane l of a wave owns the kWinX consecutive starts t = tw + 8l + i (i < 8).
+// The wave's window sits in LDS with one pad float after every 8 (rows of 9):
+// logical element k of an array is at k + k/8, so lane l's starts begin at
+// 9l and a read of one logical offset by the 64 lanes hits distinct banks.
+// A group of 8 widths whose boxcar steps read one array at offsets
+// o, o+d, ..., o+7d (d = 1 or 2, o a multiple of 8) needs only the 8 + 7d
+// values D[8l + o + m], m < 8 + 7d, for all of its 64 (start, width) pairs:
+// they are read once into registers, where the pair (i, j) finds
+// D[t_i + o + d*j] at m = i + d*j.  The same holds for the list 1..n
+// (n <= 16) over x' itself.  Results are those of boxcar_tile: the same
+// running sums in the same order, and the same first-maximiser rule.
+
+template <int DT, int SMALLN>
+__device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t tt, const spd_row_stats& st,
+                                const BoxcarArgs& ba, const WidthPlan& wp, float* smem)
+{
+    constexpr int X = kWinX;
+    float* coef = smem;                                             // 1/sigma_w; NaN past n
+    uint32_t* tgb = (uint32_t*)(coef + kMaxWidthsPadded);           // per group: padded offset of its reads
+    uint32_t* tgs = tgb + kMaxGroups;                               // per group: step d
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
+    float* arrs = smem + kWinTableFloats + (size_t)wave * ba.wave_floats;
+    const int64_t tw = tt * (int64_t)(nwaves * 64 * X) + (int64_t)wave * 64 * X;
+    const int rows9 = ba.npw / 9;                                   // rows of 8 logical floats per array
+    const int nlog = rows9 * 8;
+
+    {
+        const bool zero_var = (st.flags & SPD_FLAG_ZERO_VAR) != 0;
+        for (int i = tid; i < kMaxWidthsPadded; i += blockDim.x) {
+            if (i < wp.n) {
+                const int w = wp.width[i];
+                const double sw = sqrt((double)w) * st.sigma + (double)(w - 1) * st.lin_coef;
+                coef[i] = (zero_var || !(sw > 0.0)) ? 0.f : (float)(1.0 / sw);   // Eq. (sd02)/(sd03)
+            } else {
+                coef[i] = __int_as_float(0x7fc00000);
+            }
+        }
+        for (int g = tid; g < kMaxGroups; g += blockDim.x) {
+            tgb[g] = wp.gbase[g];
+            tgs[g] = wp.gstep[g];
+        }
+    }
+    const float mu_hi = (float)st.mean;
+    const float mu_lo = (float)(st.mean - (double)mu_hi);
+
+    // stage x' = x - mean (array 0); zero beyond the row
+    Loader<DT> ld(pl, r);
+    for (int k = 4 * lane; k < nlog; k += 256) {
+        const float4 v = load4_shifted<DT>(ld, tw + k, pl.n_cols, vec, mu_hi, mu_lo);
+        float* d = arrs + win_phys(k);                              // k..k+3 share one row of 9
+        d[0] = v.x;
+        d[1] = v.y;
+        d[2] = v.z;
+        d[3] = v.w;
+    }
+    __syncthreads();
+    for (int a = 1; a < wp.n_arr; ++a) {                            // presummed arrays D_g
+        const int g = wp.arr_gap[a];
+        float* Da = arrs + (size_t)a * ba.npw;
+        for (int row = lane; row < rows9; row += 64) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const int k = 8 * row + c;
+                float s = 0.f;
+                if (k + g <= nlog) {
+                    s = arrs[win_phys(k)];
+                    for (int j = 1; j < g; ++j) s += arrs[win_phys(k + j)];
+                }
+                Da[9 * row + c] = s;
+            }
+        }
+    }
+    __syncthreads();
+
+    // lane base as one opaque register, so the reads below keep small immediate
+    // offsets (the paired LDS read encodes at most 255 dwords)
+    int lbo = kWinTableFloats + wave * ba.wave_floats + 9 * lane;
+    asm volatile("" : "+v"(lbo));
+    const float* lb = smem + lbo;
+    const int64_t t0 = tw + (int64_t)X * lane;
+    float sv[X];
+    int iv[X];
+
+    if constexpr (SMALLN > 0) {
+        // widths 1..n: every SNR of a start in registers, max tree, reverse select chain
+        constexpr int NS = SMALLN > 0 ? SMALLN : 1;
+        constexpr int NV = X + NS - 1;
+        float v[NV];
+#pragma unroll
+        for (int m = 0; m < NV; ++m) v[m] = lb[win_phys(m)];
+        float a[NS];
+#pragma unroll
+        for (int j = 0; j < NS; j += 4) {
+            const float4 c = *(const float4*)(coef + j);
+            a[j] = c.x; a[j + 1] = c.y; a[j + 2] = c.z; a[j + 3] = c.w;
+        }
+#pragma unroll
+        for (int i = 0; i < X; ++i) {
+            float b = 0.f, s[NS];
+#pragma unroll
+            for (int j = 0; j < NS; ++j) {
+                b = __fadd_rn(b, v[i + j]);
+                s[j] = __fmul_rn(b, a[j]);
+            }
+            if constexpr (NS == 16) {
+                // the half that holds the first maximiser, then a chain over its 8 SNRs
+                float mlo = s[0], mhi = s[8];
+#pragma unroll
+                for (int j = 1; j < 8; ++j) { mlo = fmaxf(mlo, s[j]); mhi = fmaxf(mhi, s[8 + j]); }
+                const float m = fmaxf(mlo, mhi);
+                const bool hi = !(mlo == m);
+                int idx = -1;
+#pragma unroll
+                for (int j = 7; j >= 0; --j) idx = ((hi ? s[8 + j] : s[j]) == m) ? j : idx;
+                sv[i] = m;
+                iv[i] = idx < 0 ? wp.n - 1 : idx + (hi ? 8 : 0);    // no match only for NaN input
+            } else {
+                float m = s[0];
+#pragma unroll
+                for (int j = 1; j < NS; ++j) m = fmaxf(m, s[j]);
+                int idx = wp.n - 1;
+#pragma unroll
+                for (int j = NS - 1; j >= 0; --j) idx = (s[j] == m) ? j : idx;
+                sv[i] = m;
+                iv[i] = idx;
+            }
+        }
+    } else {
+        float B[X], mx[X], Bg[X];
+        int gi[X];
+#pragma unroll
+        for (int i = 0; i < X; ++i) { B[i] = 0.f; mx[i] = -INFINITY; Bg[i] = 0.f; gi[i] = 0; }
+        auto group = [&](auto step_c, int g) {
+            constexpr int D = decltype(step_c)::value;
+            constexpr int NV = 8 + 7 * D;
+            const float* gb = lb + wp.gbase[g];
+            float v[NV];
+#pragma unroll
+            for (int m = 0; m < NV; ++m) v[m] = gb[win_phys(m)];
+            const float4 a03 = *(const float4*)(coef + g * kGroup);
+            const float4 a47 = *(const float4*)(coef + g * kGroup + 4);
+            const float a[8] = {a03.x, a03.y, a03.z, a03.w, a47.x, a47.y, a47.z, a47.w};
+#pragma unroll
+            for (int i = 0; i < X; ++i) {
+                float b = B[i];
+                float s[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    b = __fadd_rn(b, v[i + D * j]);
+                    s[j] = __fmul_rn(b, a[j]);
+                }
+                // running maximum folded into the group's max3 tree; c: this group beats all before it
+                const float mnew = fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(fmaxf(s[0], s[1]), s[2]), s[3]), s[4]),
+                                                           s[5]), s[6]), s[7]), mx[i]);
+                const bool c = mnew > mx[i];
+                Bg[i] = c ? B[i] : Bg[i];
+                gi[i] = c ? g : gi[i];
+                mx[i] = mnew;
+                B[i] = b;
+            }
+        };
+        const int ng = wp.n / kGroup;                               // n is a multiple of 8 in this form
+        // runs of groups with one step; two groups per trip let the carried
+        // sums and maxima alternate registers instead of being copied
+        for (int g = 0; g < ng;) {
+            const int d = wp.gstep[g];
+            int g1 = g + 1;
+            while (g1 < ng && wp.gstep[g1] == d) ++g1;
+            if (d == 1) {
+#pragma unroll 2
+                for (; g < g1; ++g) group(std::integral_constant<int, 1>(), g);
+            } else {
+#pragma unroll 2
+                for (; g < g1; ++g) group(std::integral_constant<int, 2>(), g);
+            }
+        }
+        // first width inside the winning group, with bit-identical operations
+#pragma unroll
+        for (int i = 0; i < X; ++i) {
+            const int g = gi[i];
+            const float* gb = lb + tgb[g];
+            const bool two = tgs[g] == 2u;
+            const float4 c03 = *(const float4*)(coef + g * kGroup);
+            const float4 c47 = *(const float4*)(coef + g * kGroup + 4);
+            const float cf[8] = {c03.x, c03.y, c03.z, c03.w, c47.x, c47.y, c47.z, c47.w};
+            float b = Bg[i];
+            float s[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                b = __fadd_rn(b, gb[two ? win_phys(i + 2 * j) : win_phys(i + j)]);
+                s[j] = __fmul_rn(b, cf[j]);
+            }
+            int idx = wp.n - 1;                                     // reached only if no SNR equals the max (NaN input)
+#pragma unroll
+            for (int j = 7; j >= 0; --j) idx = (s[j] == mx[i]) ? g * kGroup + j : idx;
+            sv[i] = mx[i];
+            iv[i] = idx;
+        }
+    }
+
+    // fused threshold (Sec. 2.4): a wave with no SNR at the threshold skips it; otherwise one
+    // ballot per start index and one atomic per wave with candidates
+    const int64_t left = ba.nout - t0;
+    const int nvalid = left <= 0 ? 0 : (left >= X ? X : (int)left);
+    float mall = sv[0];
+#pragma unroll
+    for (int i = 1; i < X; ++i) mall = fmaxf(mall, sv[i]);
+    if (ba.cand && __ballot(mall >= ba.threshold)) {
+#pragma unroll
+        for (int i = 0; i < X; ++i) {
+            const int64_t t = t0 + i;
+            const bool pred = i < nvalid && sv[i] >= ba.threshold;
+            const uint64_t mask = __ballot(pred);
+            if (mask) {
+                const int cntw = __popcll(mask);
+                const int before = __popcll(mask & ((1ull << lane) - 1ull));
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd((unsigned long long*)ba.cand_count, (unsigned long long)cntw);
+                base = __shfl(base, 0);
+                if (pred) {
+                    const unsigned long long k = base + (unsigned long long)before;
+                    if (k < (unsigned long long)ba.cand_capacity) {
+                        spd_candidate cd;
+                        cd.row = (int32_t)r + ba.row0;
+                        cd.width = wp.width[iv[i]];
+                        cd.t = t + ba.t_offset;
+                        cd.snr = sv[i];
+                        cd.beam = ba.beam;
+                        ba.cand[k] = cd;
+                    }
+                }
+            }
+        }
+    }
+    // per-start outputs.  Rows that allow vector stores take each lane's 8 starts
+    // directly; otherwise the wave transposes them through its LDS region (done
+    // with the window by now) and lane l stores starts tw + l + 64i, so every
+    // store instruction covers consecutive addresses.
+    if (!ba.snr && !ba.widx) return;
+    const uint32_t need_vec = (ba.snr ? 1u : 0u) | (ba.widx ? 2u : 0u);
+    if ((ba.out_vec & need_vec) == need_vec) {
+        if (ba.snr) {
+            float* dst = ba.snr + r * ba.out_stride + t0;
+            if (nvalid == X) {
+                *(float4*)dst = make_float4(sv[0], sv[1], sv[2], sv[3]);
+                *(float4*)(dst + 4) = make_float4(sv[4], sv[5], sv[6], sv[7]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < X; ++i)
+                    if (i < nvalid) dst[i] = sv[i];
+            }
+        }
+        if (ba.widx) {
+            uint8_t* dst = ba.widx + r * ba.out_stride + t0;
+            if (nvalid == X) {
+                uint2 u;
+                u.x = (uint32_t)iv[0] | ((uint32_t)iv[1] << 8) | ((uint32_t)iv[2] << 16) | ((uint32_t)iv[3] << 24);
+                u.y = (uint32_t)iv[4] | ((uint32_t)iv[5] << 8) | ((uint32_t)iv[6] << 16) | ((uint32_t)iv[7] << 24);
+                *(uint2*)dst = u;
+            } else {
+#pragma unroll
+                for (int i = 0; i < X; ++i)
+                    if (i < nvalid) dst[i] = (uint8_t)iv[i];
+            }
+        }
+        return;
+    }
+    float* xs = arrs;                                               // 64X floats, then 64X bytes
+    uint8_t* xb = (uint8_t*)(arrs + 64 * X);
+    wave_sync();                                                    // the wave's window reads are done
+    *(float4*)(xs + X * lane) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+    *(float4*)(xs + X * lane + 4) = make_float4(sv[4], sv[5], sv[6], sv[7]);
+    uint2 u;
+    u.x = (uint32_t)iv[0] | ((uint32_t)iv[1] << 8) | ((uint32_t)iv[2] << 16) | ((uint32_t)iv[3] << 24);
+    u.y = (uint32_t)iv[4] | ((uint32_t)iv[5] << 8) | ((uint32_t)iv[6] << 16) | ((uint32_t)iv[7] << 24);
+    *(uint2*)(xb + X * lane) = u;
+    wave_sync();
+    const int64_t wleft = ba.nout - tw;                             // valid starts of this wave
+    const int64_t rowo = r * ba.out_stride + tw + lane;
+#pragma unroll
+    for (int i = 0; i < X; ++i) {
+        if (lane + 64 * i < wleft) {
+            if (ba.snr) ba.snr[rowo + 64 * i] = xs[lane + 64 * i];
+            if (ba.widx) ba.widx[rowo + 64 * i] = xb[lane + 64 * i];
         }
     }
 }

@@ -15,6 +15,13 @@ constexpr int kGroup = 8;           // widths evaluated between two argmax bookk
 constexpr int kMaxArrays = 4;       // presummed LDS arrays per wave (gap sizes)
 constexpr int kOutPerLane = 8;      // boxcar outputs per lane (strided by 64)
 constexpr int kMaxWidthsPadded = SPD_MAX_WIDTHS + kGroup;
+constexpr int kMaxGroups = kMaxWidthsPadded / kGroup;
+constexpr int kWinX = 8;           // consecutive starts per lane in the register-window form
+constexpr int kWinTableFloats = (kMaxWidthsPadded + 2 * kMaxGroups + 63) / 64 * 64;
+
+// Register-window form: logical element m of a wave's LDS array is stored at
+// m + m/8 (one pad float after every 8).
+__host__ __device__ constexpr int win_phys(int m) { return m + (m >> 3); }
 // LDS floats of the boxcar kernel's coefficient and step tables, rounded up so
 // the per-wave arrays after them start on a 256-byte boundary.
 constexpr int kTableFloats = (3 * kMaxWidthsPadded + 63) / 64 * 64;
@@ -32,10 +39,14 @@ struct WidthPlan {
     int32_t n_arr;          // presummed arrays in use (array 0 is x' itself, gap 1)
     int32_t arr_gap[kMaxArrays];
     int32_t unit_counts;    // 1 when every cnt_i == 1
-    int32_t reserved;
+    int32_t win;            // register-window form: 0 none, 1 groups of 8, 2 the list 1..n (n <= 16)
     uint32_t off[kMaxWidthsPadded];    // element offset of the first read: array base + w_{i-1}
     uint32_t cg[kMaxWidthsPadded];     // cnt | (gap << 16)
     int16_t width[kMaxWidthsPadded];   // w_i
+    // register-window form, per group of 8 widths: padded LDS offset of the
+    // group's first read (array base + o + o/8, o = w_{8g-1}) and its step d
+    uint32_t gbase[kMaxGroups];
+    uint8_t gstep[kMaxGroups];
 };
 
 struct PlaneArg {
@@ -62,6 +73,8 @@ struct BoxcarArgs {
     int64_t* cand_count;
     float threshold;
     uint32_t beam;          // stored in each candidate (batched runs)
+    uint32_t out_vec;       // bit 0: snr rows allow 16-byte stores; bit 1: widx rows allow 8-byte stores
+    uint32_t reserved;
 };
 
 struct SelectArgs {

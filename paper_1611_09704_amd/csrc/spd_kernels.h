@@ -10,7 +10,7 @@ hipError_t launch_msd(int dtype, const PlaneArg& pl, bool vec, bool with_y, int6
 hipError_t launch_finalize(const double* part, int64_t n_units, int64_t per_unit, bool need_y,
                            bool accumulate, spd_msd_state* state, spd_row_stats* stats, int32_t nmax,
                            int32_t mode, double kappa, hipStream_t s);
-size_t boxcar_lds_bytes(int waves, const BoxcarArgs& ba);
+size_t boxcar_lds_bytes(int waves, const BoxcarArgs& ba, bool win = false);
 hipError_t launch_boxcar(int dtype, const PlaneArg& pl, bool vec, const spd_row_stats* stats,
                          const BoxcarArgs& ba, const WidthPlan& wp, int X, int waves, uint64_t ntiles,
                          hipStream_t s);

@@ -5,7 +5,9 @@
 //                                  coefficients, Sec. 2.1-2.2
 //   boxcar_kernel                  boxcars, SNR, highest SNR and its width,
 //                                  fused threshold, Sec. 2.3 / Algorithm 1,
-//                                  Sec. 2.4
+//                                  Sec. 2.4 (starts 64 apart per lane)
+//   boxcar_win_kernel              the same with 8 consecutive starts per lane
+//                                  and each group's reads held in registers
 //   select_kernel                  threshold over stored outputs, Sec. 2.4
 //
 // One work-group per (row, column block) or (row, time tile), numbered so that
@@ -58,6 +60,21 @@ __global__ __launch_bounds__(256) void boxcar_kernel(PlaneArg pl, bool vec, cons
     const int64_t tt = (int64_t)(tile % (uint64_t)ba.tiles_per_row);
     const spd_row_stats st = stats[ba.scope == SPD_SCOPE_ROW ? r : 0];
     boxcar_tile<DT, X, UNIT, SMALL>(pl, vec, r, tt, st, ba, wp, smem, true);
+}
+
+// The group form holds each start's running sum, maximum, group and group-start
+// sum plus two groups' windows; capping it at 128 VGPRs keeps 4 waves per SIMD
+// without spills (uncapped it takes 132 and drops to 3).
+template <int DT, int SMALLN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SMALLN == 0 ? 4 : 1))) void boxcar_win_kernel(PlaneArg pl, bool vec, const spd_row_stats* stats,
+                                                         BoxcarArgs ba, WidthPlan wp)
+{
+    extern __shared__ float smem[];
+    const uint64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t r = (int64_t)(tile / (uint64_t)ba.tiles_per_row);
+    const int64_t tt = (int64_t)(tile % (uint64_t)ba.tiles_per_row);
+    const spd_row_stats st = stats[ba.scope == SPD_SCOPE_ROW ? r : 0];
+    boxcar_tile_win<DT, SMALLN>(pl, vec, r, tt, st, ba, wp, smem);
 }
 
 // Sec. 2.4 over stored snr / width-index arrays.
@@ -148,9 +165,9 @@ hipError_t launch_finalize(const double* part, int64_t n_units, int64_t per_unit
     return hipGetLastError();
 }
 
-size_t boxcar_lds_bytes(int waves, const BoxcarArgs& ba)
+size_t boxcar_lds_bytes(int waves, const BoxcarArgs& ba, bool win)
 {
-    return (size_t)kTableFloats * 4 + (size_t)waves * ba.wave_floats * 4;
+    return (size_t)(win ? kWinTableFloats : kTableFloats) * 4 + (size_t)waves * ba.wave_floats * 4;
 }
 
 template <int DT>
@@ -158,9 +175,16 @@ static hipError_t launch_boxcar_dt(const PlaneArg& pl, bool vec, const spd_row_s
                                    const BoxcarArgs& ba, const WidthPlan& wp, int waves, uint64_t ntiles,
                                    hipStream_t s)
 {
-    const size_t lds = boxcar_lds_bytes(waves, ba);      // <= 64 KiB by construction of the plan
+    const size_t lds = boxcar_lds_bytes(waves, ba, wp.win != 0);   // <= 64 KiB by construction of the plan
     constexpr int X = kOutPerLane;
-    if (wp.unit_counts && wp.n <= 8)
+    if (wp.win == 1)
+        hipLaunchKernelGGL((boxcar_win_kernel<DT, 0>), dim3(ntiles), dim3(64 * waves), lds, s, pl, vec, stats, ba, wp);
+    else if (wp.win == 2 && wp.n <= 8)
+        hipLaunchKernelGGL((boxcar_win_kernel<DT, 8>), dim3(ntiles), dim3(64 * waves), lds, s, pl, vec, stats, ba, wp);
+    else if (wp.win == 2)
+        hipLaunchKernelGGL((boxcar_win_kernel<DT, 16>), dim3(ntiles), dim3(64 * waves), lds, s, pl, vec, stats, ba,
+                           wp);
+    else if (wp.unit_counts && wp.n <= 8)
         hipLaunchKernelGGL((boxcar_kernel<DT, X, true, 8>), dim3(ntiles), dim3(64 * waves), lds, s, pl, vec, stats,
                            ba, wp);
     else if (wp.unit_counts && wp.n <= 16)

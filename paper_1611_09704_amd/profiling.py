@@ -80,7 +80,8 @@ def _short(name: str, with_args: bool = False) -> str:
     if with_args and "<" in name.split("(")[0]:
         targs = "<" + name.split("(")[0].split("<", 1)[1]
     for key in ("batch_boxcar_grid_kernel", "batch_boxcar_kernel", "batch_msd_kernel", "batch_finalize_kernel",
-                "boxcar_kernel", "msd_xy_kernel", "msd_x_kernel", "msd_finalize_kernel", "select_kernel",
+                "boxcar_win_kernel", "boxcar_kernel", "msd_xy_kernel", "msd_x_kernel", "msd_finalize_kernel",
+                "select_kernel",
                 "fill_i64_kernel"):
         if key in name:
             return key + targs
@@ -183,7 +184,8 @@ def summarize(args):
             d = json.load(open(tpath))
         except (OSError, ValueError):
             d = {}
-        d[args.workload] = {"kernel_sha": sha, **traffic.get("boxcar_kernel", {}),
+        box = traffic.get("boxcar_win_kernel") or traffic.get("boxcar_kernel") or {}
+        d[args.workload] = {"kernel_sha": sha, **box,
                             "msd": traffic.get("msd_xy_kernel") or traffic.get("msd_x_kernel")}
         json.dump(d, open(tpath, "w"), indent=1)
         print("wrote", tpath)
