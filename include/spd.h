@@ -248,7 +248,8 @@ typedef struct {
                                 launch with one work-group per tile                      */
     int32_t tiles_per_grab;  /* tiles taken per atomic queue increment */
     int32_t tuned;           /* 0: default schedule, 1: timed at creation, 2: from the cache */
-    int32_t reserved0;
+    int32_t window;          /* 1: each lane takes out_per_lane consecutive starts and keeps a
+                                group's reads in registers; 0: starts 64 apart per lane    */
     int64_t msd_items;       /* (beam, row, column block) items */
     int64_t tiles;           /* (beam, row, time tile) items */
     int64_t rows;            /* rows over all beams */

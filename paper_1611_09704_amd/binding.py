@@ -53,7 +53,7 @@ class SpdParams(ctypes.Structure):
 class SpdBatchInfo(ctypes.Structure):
     _fields_ = [("out_per_lane", ctypes.c_int32), ("waves_per_group", ctypes.c_int32),
                 ("groups_per_cu", ctypes.c_int32), ("tiles_per_grab", ctypes.c_int32), ("tuned", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("msd_items", ctypes.c_int64), ("tiles", ctypes.c_int64),
+                ("window", ctypes.c_int32), ("msd_items", ctypes.c_int64), ("tiles", ctypes.c_int64),
                 ("rows", ctypes.c_int64)]
 
 
@@ -370,7 +370,7 @@ class BatchPlan:
     def describe(self) -> dict:
         info = SpdBatchInfo()
         _check(load().spd_batch_describe(self._h, ctypes.byref(info)))
-        return {f: getattr(info, f) for f, _ in SpdBatchInfo._fields_ if f != "reserved0"}
+        return {f: getattr(info, f) for f, _ in SpdBatchInfo._fields_}
 
     def tune_table(self) -> list:
         rows = (SpdBatchInfo * 64)()
@@ -378,6 +378,7 @@ class BatchPlan:
         n = load().spd_batch_tune_table(self._h, rows, ns, 64)
         return [{"out_per_lane": rows[i].out_per_lane, "waves_per_group": rows[i].waves_per_group,
                  "groups_per_cu": rows[i].groups_per_cu, "tiles_per_grab": rows[i].tiles_per_grab,
+                 "window": rows[i].window,
                  "ns_per_start": round(float(ns[i]), 5)} for i in range(min(n, 64))]
 
     def close(self):

@@ -179,6 +179,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(UNIT ? 5 : 
     boxcar_tile<DT, X, UNIT>(d.pl, d.vec != 0, r, tt, st, ba, wp, smem, true);
 }
 
+// The register-window form of the same grid launch (8 consecutive starts per
+// lane; tiles numbered for that form).  Capped at 128 VGPRs like the one-plane
+// kernel of the same form.
+template <int DT, int SMALLN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SMALLN == 0 ? 4 : 6))) void batch_boxcar_win_grid_kernel(
+    const BeamDesc* beams, int n_beams, const spd_row_stats* stats, BoxcarArgs ba, WidthPlan wp)
+{
+    extern __shared__ float smem[];
+    __shared__ int64_t starts[kMaxBeams];
+    for (int b = threadIdx.x; b < n_beams; b += blockDim.x) starts[b] = beams[b].tile_start;
+    __syncthreads();
+    const int64_t it = (int64_t)xcd_remap(blockIdx.x, gridDim.x);
+    const int b = find_beam(starts, n_beams, it);
+    const BeamDesc d = beams[b];
+    const int64_t local = it - d.tile_start;
+    const int64_t r = local / d.tiles_per_row, tt = local % d.tiles_per_row;
+    ba.tiles_per_row = d.tiles_per_row;
+    ba.nout = d.nout;
+    ba.beam = (uint32_t)b;
+    const spd_row_stats st = stats[d.unit_start + r];
+    boxcar_tile_win<DT, SMALLN>(d.pl, d.vec != 0, r, tt, st, ba, wp, smem);
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -188,7 +211,11 @@ struct Schedule {
     int waves = 4;          // waves per work-group
     int wgs_per_cu = 4;     // persistent work-groups per CU; 0 = one work-group per tile (grid launch)
     int grab = 4;           // tiles per queue grab (persistent only)
+    int win = 0;            // 1: register-window form (X = 8 consecutive starts, grid launch only)
 };
+
+// Plan slots: 0 strided X = 4, 1 strided X = 8, 2 register-window form.
+constexpr int kLayouts = 3;
 
 }  // namespace spd
 
@@ -199,15 +226,16 @@ struct spd_batch_plan {
     int cus = 0;
     std::vector<int32_t> widths;
     spd_params params{};
-    spd::WidthPlan wp[2];                   // for X = 4 and X = 8
-    spd::BoxcarArgs ba[2];
-    int max_waves[2] = {1, 1};
+    spd::WidthPlan wp[spd::kLayouts];       // strided X = 4, strided X = 8, register-window form
+    spd::BoxcarArgs ba[spd::kLayouts];
+    int max_waves[spd::kLayouts] = {1, 1, 1};
+    bool has_win = false;
     spd::Schedule sched;
     int tuned = 0;
     float tune_ms = 0.f;
-    int64_t msd_items = 0, tiles[2] = {0, 0}, units = 0;
+    int64_t msd_items = 0, tiles[spd::kLayouts] = {0, 0, 0}, units = 0;
     std::vector<spd::BeamDesc> host_beams;
-    spd::BeamDesc* d_beams[2] = {nullptr, nullptr};   // tile numbering depends on X
+    spd::BeamDesc* d_beams[spd::kLayouts] = {nullptr, nullptr, nullptr};   // tile numbering differs per slot
     double* d_part = nullptr;
     spd_row_stats* d_stats = nullptr;
     int64_t* d_counters = nullptr;          // [0] msd queue, [1] boxcar queue, [2] scratch count
@@ -223,6 +251,7 @@ struct spd_batch_plan {
 namespace spd {
 
 static int xi(int X) { return X == 4 ? 0 : 1; }
+static int slot(const Schedule& sc) { return sc.win ? 2 : xi(sc.X); }
 
 template <int DT>
 static hipError_t enqueue_msd(spd_batch_plan* P, hipStream_t s)
@@ -271,10 +300,30 @@ static hipError_t enqueue_boxcar_x(spd_batch_plan* P, const Schedule& sc, const 
 }
 
 template <int DT>
+static hipError_t enqueue_boxcar_win(spd_batch_plan* P, const Schedule& sc, const BoxcarArgs& ba, int64_t total,
+                                     hipStream_t s)
+{
+    const WidthPlan& wp = P->wp[2];
+    const size_t lds = boxcar_lds_bytes(sc.waves, P->ba[2], true);
+    if (total <= 0) return hipSuccess;
+    if ((uint64_t)total * 64u * (uint64_t)sc.waves > kMaxGridItems) return hipErrorInvalidConfiguration;
+    if (wp.win == 1)
+        hipLaunchKernelGGL((batch_boxcar_win_grid_kernel<DT, 0>), dim3((unsigned)total), dim3(64 * sc.waves), lds, s,
+                           P->d_beams[2], P->n_beams, P->d_stats, ba, wp);
+    else if (wp.n <= 8)
+        hipLaunchKernelGGL((batch_boxcar_win_grid_kernel<DT, 8>), dim3((unsigned)total), dim3(64 * sc.waves), lds, s,
+                           P->d_beams[2], P->n_beams, P->d_stats, ba, wp);
+    else
+        hipLaunchKernelGGL((batch_boxcar_win_grid_kernel<DT, 16>), dim3((unsigned)total), dim3(64 * sc.waves), lds,
+                           s, P->d_beams[2], P->n_beams, P->d_stats, ba, wp);
+    return hipGetLastError();
+}
+
+template <int DT>
 static hipError_t enqueue_boxcar(spd_batch_plan* P, const Schedule& sc, spd_candidate* cand, int64_t cap,
                                  int64_t* count, int64_t limit, hipStream_t s)
 {
-    const int k = xi(sc.X);
+    const int k = slot(sc);
     BoxcarArgs ba = P->ba[k];
     ba.cand = cand;
     ba.cand_capacity = cap;
@@ -282,6 +331,7 @@ static hipError_t enqueue_boxcar(spd_batch_plan* P, const Schedule& sc, spd_cand
     // Each work-group holds sc.waves waves; tiles were numbered for max_waves waves.
     // Renumbering is avoided by requiring sc.waves == max_waves (see tune()).
     const int64_t total = limit >= 0 ? std::min(limit, P->tiles[k]) : P->tiles[k];
+    if (sc.win) return enqueue_boxcar_win<DT>(P, sc, ba, total, s);
     return sc.X == 4 ? enqueue_boxcar_x<DT, 4>(P, sc, ba, total, s) : enqueue_boxcar_x<DT, 8>(P, sc, ba, total, s);
 }
 
@@ -333,7 +383,7 @@ static std::string tune_key(const spd_batch_plan* P)
     char buf[256];
     unsigned h = 2166136261u;
     for (int32_t w : P->widths) h = (h ^ (unsigned)w) * 16777619u;
-    snprintf(buf, sizeof buf, "v2|%s|cu%d|dt%d|n%zu|nmax%d|w%08x", prop.gcnArchName, P->cus, P->dtype,
+    snprintf(buf, sizeof buf, "v3|%s|cu%d|dt%d|n%zu|nmax%d|w%08x", prop.gcnArchName, P->cus, P->dtype,
              P->widths.size(), P->widths.back(), h);
     return buf;
 }
@@ -349,7 +399,8 @@ static bool cache_lookup(const std::string& key, Schedule& sc)
     while (fgets(line, sizeof line, f)) {
         char k[300];
         Schedule s;
-        if (sscanf(line, "%299s %d %d %d %d", k, &s.X, &s.waves, &s.wgs_per_cu, &s.grab) == 5 && key == k) {
+        if (sscanf(line, "%299s %d %d %d %d %d", k, &s.X, &s.waves, &s.wgs_per_cu, &s.grab, &s.win) == 6 &&
+            key == k) {
             sc = s;
             found = true;
         }
@@ -366,7 +417,7 @@ static void cache_store(const std::string& key, const Schedule& sc)
     if (path.empty()) return;
     FILE* f = fopen(path.c_str(), "a");
     if (!f) return;
-    fprintf(f, "%s %d %d %d %d\n", key.c_str(), sc.X, sc.waves, sc.wgs_per_cu, sc.grab);
+    fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), sc.X, sc.waves, sc.wgs_per_cu, sc.grab, sc.win);
     fclose(f);
 }
 
@@ -377,7 +428,7 @@ using namespace spd;
 static spd_status build_beams(spd_batch_plan* P, const spd_plane* beams)
 {
     P->host_beams.resize(P->n_beams);
-    int64_t msd = 0, units = 0, tiles[2] = {0, 0};
+    int64_t msd = 0, units = 0, tiles[kLayouts] = {0, 0, 0};
     const int nmax = P->widths.back();
     for (int b = 0; b < P->n_beams; ++b) {
         const spd_plane& x = beams[b];
@@ -394,7 +445,8 @@ static spd_status build_beams(spd_batch_plan* P, const spd_plane* beams)
     }
     P->msd_items = msd;
     P->units = units;
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kLayouts; ++k) {
+        if (k == 2 && !P->has_win) continue;
         const int X = k ? 8 : 4;
         std::vector<BeamDesc> v = P->host_beams;
         int64_t t = 0;
@@ -410,8 +462,7 @@ static spd_status build_beams(spd_batch_plan* P, const spd_plane* beams)
         e = hipMemcpy(P->d_beams[k], v.data(), sizeof(BeamDesc) * P->n_beams, hipMemcpyHostToDevice);
         if (e != hipSuccess) return device_status(e, "hipMemcpy(beams)");
     }
-    P->tiles[0] = tiles[0];
-    P->tiles[1] = tiles[1];
+    for (int k = 0; k < kLayouts; ++k) P->tiles[k] = tiles[k];
     if (P->units > 0x7fffffffLL || P->msd_items > 0x7fffffffLL)
         return fail(SPD_E_UNSUPPORTED, "batch too large");
     return SPD_OK;
@@ -428,8 +479,9 @@ static spd_status tune(spd_batch_plan* P, hipStream_t s)
     Schedule best;
     best.X = 8;
     best.waves = P->max_waves[1];
-    if (cache_lookup(key, best) && (best.X == 4 || best.X == 8) && best.wgs_per_cu >= 0 && best.grab >= 1) {
-        best.waves = P->max_waves[xi(best.X)];
+    if (cache_lookup(key, best) && (best.X == 4 || best.X == 8) && best.wgs_per_cu >= 0 && best.grab >= 1 &&
+        (!best.win || (P->has_win && best.X == 8 && best.wgs_per_cu == 0))) {
+        best.waves = P->max_waves[slot(best)];
         P->sched = best;
         P->tuned = 2;
         return SPD_OK;
@@ -449,24 +501,27 @@ static spd_status tune(spd_batch_plan* P, hipStream_t s)
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     float best_ms = 1e30f;
-    const int Xs[2] = {4, 8};
+    const int Xs[3] = {4, 8, 0};                      // 0: the register-window form (X = 8, grid launch)
     const int wpc[4] = {0, 2, 4, 6};                  // 0: grid launch, one work-group per tile
     const int grabs[2] = {1, 8};
     P->tune_table.clear();
-    for (int X : Xs)
+    for (int xv : Xs)
         for (int w : wpc)
             for (int g : grabs) {
-                if (w == 0 && g != 1) continue;
-                if (w == 0 && (uint64_t)P->tiles[xi(X)] * 64u * (uint64_t)P->max_waves[xi(X)] > kMaxGridItems)
-                    continue;                             // one launch cannot hold every tile
                 Schedule sc;
-                sc.X = X;
-                sc.waves = P->max_waves[xi(X)];
+                sc.win = xv == 0 ? 1 : 0;
+                sc.X = xv == 0 ? 8 : xv;
+                if (sc.win && (!P->has_win || w != 0)) continue;
+                const int k = slot(sc);
+                if (w == 0 && g != 1) continue;
+                if (w == 0 && (uint64_t)P->tiles[k] * 64u * (uint64_t)P->max_waves[k] > kMaxGridItems)
+                    continue;                             // one launch cannot hold every tile
+                sc.waves = P->max_waves[k];
                 sc.wgs_per_cu = w;
                 sc.grab = g;
                 // the same prefix of the work for every schedule: a few waves of
                 // persistent work-groups deep
-                const int64_t limit = std::min<int64_t>(P->tiles[xi(X)], (int64_t)P->cus * 6 * 8 * 6);
+                const int64_t limit = std::min<int64_t>(P->tiles[k], (int64_t)P->cus * 6 * 8 * 6);
                 float ms = 0.f;
                 for (int rep = 0; rep < 2; ++rep) {
                     launch_fill_i64(P->d_counters + 1, 2, 0, s);
@@ -478,7 +533,7 @@ static spd_status tune(spd_batch_plan* P, hipStream_t s)
                     hipEventElapsedTime(&ms, e0, e1);
                 }
                 if (e != hipSuccess) break;
-                const int64_t starts_done = limit * (int64_t)sc.waves * 64 * X;
+                const int64_t starts_done = limit * (int64_t)sc.waves * 64 * sc.X;
                 const float per = ms * 1e6f / (float)starts_done;      // ns per output start
                 P->tune_table.push_back({sc, per});
                 if (per < best_ms) {
@@ -532,9 +587,27 @@ spd_status spd_batch_plan_create(const spd_plane* beams, int32_t n_beams, const 
         P->ba[k].scope = SPD_SCOPE_ROW;
         P->ba[k].threshold = p->threshold;
     }
+    memset(&P->ba[2], 0, sizeof P->ba[2]);
+    if (build_width_plan(&P->params, kWinX, P->wp[2], P->ba[2], P->max_waves[2], kBatchLdsReserve, true) &&
+        P->wp[2].win) {
+        P->has_win = true;
+        P->ba[2].scope = SPD_SCOPE_ROW;
+        P->ba[2].threshold = p->threshold;
+    }
+    // default schedule: the register-window form where the width list allows it, else strided X = 8;
+    // one ordinary launch with one work-group per tile
     P->sched.X = 8;
-    P->sched.waves = P->max_waves[1];
+    P->sched.win = P->has_win ? 1 : 0;
+    P->sched.waves = P->max_waves[P->has_win ? 2 : 1];
+    P->sched.wgs_per_cu = 0;
+    P->sched.grab = 1;
     if ((st = build_beams(P, beams))) { spd_batch_plan_destroy(P); return st; }
+    if ((uint64_t)P->tiles[slot(P->sched)] * 64u * (uint64_t)P->sched.waves > kMaxGridItems) {
+        P->sched.win = 0;                       // too many tiles for one grid launch: persistent queue
+        P->sched.waves = P->max_waves[1];
+        P->sched.wgs_per_cu = 4;
+        P->sched.grab = 4;
+    }
     hipError_t e = hipMalloc((void**)&P->d_part, sizeof(double) * 6 * (size_t)P->msd_items);
     if (e == hipSuccess) e = hipMalloc((void**)&P->d_stats, sizeof(spd_row_stats) * (size_t)P->units);
     if (e == hipSuccess) e = hipMalloc((void**)&P->d_counters, sizeof(int64_t) * 4);
@@ -605,9 +678,9 @@ spd_status spd_batch_describe(const spd_batch_plan* P, spd_batch_info* info)
     info->groups_per_cu = P->sched.wgs_per_cu;
     info->tiles_per_grab = P->sched.grab;
     info->tuned = P->tuned;
-    info->reserved0 = 0;
+    info->window = P->sched.win;
     info->msd_items = P->msd_items;
-    info->tiles = P->tiles[xi(P->sched.X)];
+    info->tiles = P->tiles[slot(P->sched)];
     info->rows = P->units;
     return SPD_OK;
 }
@@ -625,6 +698,7 @@ int32_t spd_batch_tune_table(const spd_batch_plan* P, spd_batch_info* rows, floa
         r.waves_per_group = sc.waves;
         r.groups_per_cu = sc.wgs_per_cu;
         r.tiles_per_grab = sc.grab;
+        r.window = sc.win;
         ns_per_start[i] = P->tune_table[i].second;
     }
     return n;
@@ -636,7 +710,7 @@ void spd_batch_plan_destroy(spd_batch_plan* P)
     if (P->exec) hipGraphExecDestroy(P->exec);
     if (P->graph) hipGraphDestroy(P->graph);
     if (P->capture_stream) hipStreamDestroy(P->capture_stream);
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < kLayouts; ++k)
         if (P->d_beams[k]) hipFree(P->d_beams[k]);
     if (P->d_part) hipFree(P->d_part);
     if (P->d_stats) hipFree(P->d_stats);

@@ -46,6 +46,8 @@ def test_batch_matches_plain_and_oracle(widths, mode):
     planes = [pl.x for pl in cfg["planes"]]
     p = B.Params(widths, 5.0, "row", mode, 0.5)
     plan = B.BatchPlan(planes, p, autotune=False)
+    # the register-window form is the default wherever the width list is made of stepped groups
+    assert plan.describe()["window"] == (0 if widths[3] == 5 else 1)
     got = _cands_by_beam(_batch_run(plan))
     for b, x in enumerate(planes):
         plain = B.detect(x, widths, 5.0, sigma_mode=mode, kappa=0.5)
@@ -96,6 +98,8 @@ def test_batch_autotuned_schedule_gives_same_results(tmp_path, monkeypatch):
     tuned = B.BatchPlan(planes, p, autotune=True)
     info = tuned.describe()
     assert info["tuned"] == 1 and info["out_per_lane"] in (4, 8)
+    table = tuned.tune_table()
+    assert any(r["window"] for r in table) and any(not r["window"] for r in table)
     again = B.BatchPlan(planes, p, autotune=True)
     assert again.describe()["tuned"] == 2                       # from the cache
     ka = sorted((int(c["beam"]), int(c["row"]), int(c["t"]), float(c["snr"])) for c in _batch_run(base))
