@@ -722,15 +722,27 @@ __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t
         const int g = wp.arr_gap[a];
         float* Da = arrs + (size_t)a * ba.npw;
         for (int row = lane; row < rows9; row += 64) {
+            const float* xr = arrs + 9 * row;                       // logical 8row.., then the next row at 9
+            if (g == 2) {
+                // the 9 values of a row and the next one's first, read once
+                float v[9];
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const int k = 8 * row + c;
-                float s = 0.f;
-                if (k + g <= nlog) {
-                    s = arrs[win_phys(k)];
-                    for (int j = 1; j < g; ++j) s += arrs[win_phys(k + j)];
+                for (int c = 0; c < 8; ++c) v[c] = xr[c];
+                v[8] = row + 1 < rows9 ? xr[9] : 0.f;
+                const bool last = row + 1 == rows9;                 // its final sum would run past the window
+#pragma unroll
+                for (int c = 0; c < 8; ++c) Da[9 * row + c] = (last && c == 7) ? 0.f : v[c] + v[c + 1];
+            } else {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int k = 8 * row + c;
+                    float s = 0.f;
+                    if (k + g <= nlog) {
+                        s = arrs[win_phys(k)];
+                        for (int j = 1; j < g; ++j) s += arrs[win_phys(k + j)];
+                    }
+                    Da[9 * row + c] = s;
                 }
-                Da[9 * row + c] = s;
             }
         }
     }
@@ -838,7 +850,9 @@ __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t
                 for (; g < g1; ++g) group(std::integral_constant<int, 2>(), g);
             }
         }
-        // first width inside the winning group, with bit-identical operations
+        // first width inside the winning group, with bit-identical operations.  Both
+        // steps' reads sit at immediate offsets of the group base (inside the
+        // staged window either way); the lane's step picks the value.
 #pragma unroll
         for (int i = 0; i < X; ++i) {
             const int g = gi[i];
@@ -851,14 +865,15 @@ __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t
             float s[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
-                b = __fadd_rn(b, gb[two ? win_phys(i + 2 * j) : win_phys(i + j)]);
+                const float d1 = gb[win_phys(i + j)], d2 = gb[win_phys(i + 2 * j)];
+                b = __fadd_rn(b, two ? d2 : d1);
                 s[j] = __fmul_rn(b, cf[j]);
             }
-            int idx = wp.n - 1;                                     // reached only if no SNR equals the max (NaN input)
+            int jj = -1;
 #pragma unroll
-            for (int j = 7; j >= 0; --j) idx = (s[j] == mx[i]) ? g * kGroup + j : idx;
+            for (int j = 7; j >= 0; --j) jj = (s[j] == mx[i]) ? j : jj;
             sv[i] = mx[i];
-            iv[i] = idx;
+            iv[i] = jj < 0 ? wp.n - 1 : g * kGroup + jj;           // no match only for NaN input
         }
     }
 
