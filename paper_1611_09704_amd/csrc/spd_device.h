@@ -709,13 +709,35 @@ __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t
 
     // stage x' = x - mean (array 0); zero beyond the row
     Loader<DT> ld(pl, r);
-    for (int k = 4 * lane; k < nlog; k += 256) {
-        const float4 v = load4_shifted<DT>(ld, tw + k, pl.n_cols, vec, mu_hi, mu_lo);
-        float* d = arrs + win_phys(k);                              // k..k+3 share one row of 9
-        d[0] = v.x;
-        d[1] = v.y;
-        d[2] = v.z;
-        d[3] = v.w;
+    if (vec && tw + nlog <= pl.n_cols) {
+        // window inside the row (all but the last tiles): four vector loads per
+        // lane in flight before any is written; lanes past the window reload
+        // its last four samples and skip the write
+        for (int k0 = 4 * lane; k0 < nlog; k0 += 1024) {
+            float4 v[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) v[m] = ld.vec(tw + min(k0 + 256 * m, nlog - 4));
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int k = k0 + 256 * m;
+                if (k < nlog) {
+                    float* d = arrs + win_phys(k);                  // k..k+3 share one row of 9
+                    d[0] = (v[m].x - mu_hi) - mu_lo;
+                    d[1] = (v[m].y - mu_hi) - mu_lo;
+                    d[2] = (v[m].z - mu_hi) - mu_lo;
+                    d[3] = (v[m].w - mu_hi) - mu_lo;
+                }
+            }
+        }
+    } else {
+        for (int k = 4 * lane; k < nlog; k += 256) {
+            const float4 v = load4_shifted<DT>(ld, tw + k, pl.n_cols, vec, mu_hi, mu_lo);
+            float* d = arrs + win_phys(k);
+            d[0] = v.x;
+            d[1] = v.y;
+            d[2] = v.z;
+            d[3] = v.w;
+        }
     }
     __syncthreads();
     for (int a = 1; a < wp.n_arr; ++a) {                            // presummed arrays D_g
