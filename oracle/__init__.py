@@ -12,7 +12,10 @@ The functions follow the paper's steps:
 * ``stream_step`` / ``detect`` -- Sec. 2.1-2.3 and Algorithm 1: statistics per
   unit, sigma_N from Eq. (sd02) or the linear form Eq. (sd03), the highest SNR
   over the width list and the first width that reaches it;
-* ``select`` -- Sec. 2.4, the SNR threshold and the candidate list.
+* ``select`` -- Sec. 2.4, the SNR threshold and the candidate list;
+* ``dit_widths`` / ``dit_detect`` -- boxcars combined with decimation in time
+  (the direction Sec. 3 names for wide boxcars): the same definition with
+  width 2^l*w evaluated only at starts that are multiples of 2^l.
 
 The readings taken where the paper is silent or garbled are listed in the
 header of ``spd_oracle.c``.
@@ -64,6 +67,9 @@ def _load():
             lib.oracle_stream_step.argtypes = [d, i64, i64, i64, d, i32, ctypes.c_int, ctypes.c_int,
                                                ctypes.c_double, d, d, d, d, ctypes.c_int]
             lib.oracle_stream_step.restype = ctypes.c_int
+            lib.oracle_stream_step_strided.argtypes = [d, i64, i64, i64, d, d, i32, ctypes.c_int, ctypes.c_int,
+                                                       ctypes.c_double, d, d, d, d, ctypes.c_int]
+            lib.oracle_stream_step_strided.restype = ctypes.c_int
             lib.oracle_select.argtypes = [d, d, i64, i64, d, ctypes.c_double, i64, d, d, d, d, i64]
             lib.oracle_select.restype = i64
             lib.oracle_max_threads.argtypes = []
@@ -106,12 +112,13 @@ def new_state(n_units: int) -> np.ndarray:
 
 
 def stream_step(x, widths, *, new_col_begin=0, state=None, scope="row", sigma_mode="sqrtn",
-                kappa=1.0, nthreads=None):
+                kappa=1.0, nthreads=None, strides=None):
     """One step over a plane view; returns (state, stats, snr, widx).
 
     ``stats`` has one row per unit: mean, sigma, sigma_Nmax, linear coefficient,
     flags.  ``snr``/``widx`` have shape (R, L_view - Nmax + 1); ``widx`` indexes
-    ``widths``.
+    ``widths``.  ``strides`` (optional, one per width, the first 1) evaluates
+    width i only at starts that are multiples of strides[i].
     """
     x = np.ascontiguousarray(x, dtype=np.float64)
     if x.ndim != 2:
@@ -131,10 +138,19 @@ def stream_step(x, widths, *, new_col_begin=0, state=None, scope="row", sigma_mo
         raise ValueError("plane shorter than the widest boxcar")
     snr = np.zeros((R, n_out))
     widx = np.zeros((R, n_out), dtype=np.int32)
-    rc = _load().oracle_stream_step(_ptr(x), R, L, int(new_col_begin), _ptr(W), W.size,
-                                    SCOPES[scope], SIGMA_MODES[sigma_mode], float(kappa),
-                                    _ptr(state), _ptr(stats), _ptr(snr), _ptr(widx),
-                                    int(nthreads or default_threads()))
+    if strides is None:
+        rc = _load().oracle_stream_step(_ptr(x), R, L, int(new_col_begin), _ptr(W), W.size,
+                                        SCOPES[scope], SIGMA_MODES[sigma_mode], float(kappa),
+                                        _ptr(state), _ptr(stats), _ptr(snr), _ptr(widx),
+                                        int(nthreads or default_threads()))
+    else:
+        S = np.ascontiguousarray(strides, dtype=np.int32)
+        if S.shape != W.shape:
+            raise ValueError("one stride per width")
+        rc = _load().oracle_stream_step_strided(_ptr(x), R, L, int(new_col_begin), _ptr(W), _ptr(S), W.size,
+                                                SCOPES[scope], SIGMA_MODES[sigma_mode], float(kappa),
+                                                _ptr(state), _ptr(stats), _ptr(snr), _ptr(widx),
+                                                int(nthreads or default_threads()))
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return state, stats, snr, widx
@@ -165,6 +181,36 @@ def detect(x, widths, threshold, *, scope="row", sigma_mode="sqrtn", kappa=1.0, 
                                       kappa=kappa, nthreads=nthreads)
     cands = select(snr, widx, widths, threshold)
     return {"stats": stats, "snr": snr, "widx": widx, "cands": cands}
+
+
+def dit_widths(levels: int, base: int = 16):
+    """Widths and start strides of boxcars combined with decimation in time.
+
+    Level 0 runs widths 1..base on the series itself.  Level l >= 1 runs
+    widths base/2+1..base on the series decimated l times (adjacent pairs
+    summed each time): physical width 2^l*w at starts that are multiples of
+    2^l.  Returned in ascending width order, as (widths, strides)."""
+    if base < 2 or base % 2 or levels < 0:
+        raise ValueError("base must be even and >= 2, levels >= 0")
+    widths = list(range(1, base + 1))
+    strides = [1] * base
+    for lv in range(1, levels + 1):
+        for w in range(base // 2 + 1, base + 1):
+            widths.append(w << lv)
+            strides.append(1 << lv)
+    return widths, strides
+
+
+def dit_detect(x, levels, threshold, *, base=16, scope="row", sigma_mode="sqrtn", kappa=1.0, nthreads=None):
+    """The decimated search on one plane, one shot: for every start the highest
+    SNR over the widths evaluated there (first maximiser in ascending width),
+    and the candidates.  Statistics are those of the exhaustive path over the
+    same width list."""
+    widths, strides = dit_widths(levels, base)
+    _, stats, snr, widx = stream_step(x, widths, scope=scope, sigma_mode=sigma_mode, kappa=kappa,
+                                      nthreads=nthreads, strides=strides)
+    cands = select(snr, widx, widths, threshold)
+    return {"stats": stats, "snr": snr, "widx": widx, "cands": cands, "widths": widths, "strides": strides}
 
 
 def dequantize_u8(q, scale, zero) -> np.ndarray:

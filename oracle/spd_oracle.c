@@ -140,7 +140,9 @@ static void unit_coefficients(const double* st6, int sigma_mode, double kappa, i
 /* Sec. 2.3 Algorithm 1 for one row: for each start t the boxcar sum grows one
  * sample at a time; at every width in W the SNR is formed and compared with
  * the best so far (strict '>').                                             */
-static void detect_row(const double* row, int64_t n_out, const int32_t* W, int nW,
+/* One row of step 3.  stride[i] (NULL: all 1) restricts width W[i] to starts
+ * that are multiples of stride[i]; the running sum still passes through it.  */
+static void detect_row(const double* row, int64_t n_out, const int32_t* W, const int32_t* stride, int nW,
                        const double* stats5, double* snr, int32_t* widx)
 {
     double mu = stats5[0], sigma = stats5[1], coef = stats5[3];
@@ -154,6 +156,7 @@ static void detect_row(const double* row, int64_t n_out, const int32_t* W, int n
         int k = 0, bi = 0;
         for (int i = 0; i < nW; ++i) {
             while (k < W[i]) { B += row[t + k]; ++k; }
+            if (stride && t % stride[i] != 0) continue;
             double s = sig_w[i] > 0.0 ? (B - (double)W[i] * mu) / sig_w[i] : 0.0;
             if (s > best) { best = s; bi = i; }
         }
@@ -176,13 +179,38 @@ static void detect_row(const double* row, int64_t n_out, const int32_t* W, int n
  * a single step with a zeroed state and new_col_begin = 0.
  * Returns 0, or -1 for an argument error.
  */
+int oracle_stream_step_strided(const double* x, int64_t R, int64_t L_view, int64_t new_col_begin,
+                               const int32_t* W, const int32_t* stride, int32_t nW, int scope, int sigma_mode,
+                               double kappa, double* state, double* stats, double* snr, int32_t* widx,
+                               int nthreads);
+
 int oracle_stream_step(const double* x, int64_t R, int64_t L_view, int64_t new_col_begin,
                        const int32_t* W, int32_t nW, int scope, int sigma_mode, double kappa,
                        double* state, double* stats, double* snr, int32_t* widx, int nthreads)
 {
+    return oracle_stream_step_strided(x, R, L_view, new_col_begin, W, NULL, nW, scope, sigma_mode, kappa, state,
+                                      stats, snr, widx, nthreads);
+}
+
+/*
+ * The same step where width W[i] is evaluated only at starts t that are
+ * multiples of stride[i] (stride NULL: every start).  This is the search of
+ * boxcars combined with decimation in time, the direction Sec. 3 names for
+ * wide boxcars: decimating the series by 2 (summing adjacent pairs) l times
+ * and running a boxcar of w decimated samples gives exactly the window of
+ * w*2^l samples that starts at a multiple of 2^l, so the decimated search is
+ * this exhaustive definition restricted to those (start, width) pairs.
+ * Statistics are unchanged (sigma_Nmax uses every start of the widest width).
+ */
+int oracle_stream_step_strided(const double* x, int64_t R, int64_t L_view, int64_t new_col_begin,
+                               const int32_t* W, const int32_t* stride, int32_t nW, int scope, int sigma_mode,
+                               double kappa, double* state, double* stats, double* snr, int32_t* widx,
+                               int nthreads)
+{
     if (R < 1 || nW < 1 || L_view < 1 || new_col_begin < 0 || new_col_begin > L_view) return -1;
     for (int i = 0; i < nW; ++i)
-        if (W[i] < 1 || (i > 0 && W[i] <= W[i - 1])) return -1;
+        if (W[i] < 1 || (i > 0 && W[i] <= W[i - 1]) || (stride && stride[i] < 1)) return -1;
+    if (stride && stride[0] != 1) return -1;       /* every start keeps at least the first width */
     int nmax = W[nW - 1];
     if (nmax > L_view) return -1;
     int64_t n_out = L_view - nmax + 1;
@@ -222,7 +250,7 @@ int oracle_stream_step(const double* x, int64_t R, int64_t L_view, int64_t new_c
     #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
     for (int64_t r = 0; r < R; ++r) {
         int64_t u = (scope == SCOPE_PLANE) ? 0 : r;
-        detect_row(x + r * L_view, n_out, W, nW, stats + u * 5, snr + r * n_out, widx + r * n_out);
+        detect_row(x + r * L_view, n_out, W, stride, nW, stats + u * 5, snr + r * n_out, widx + r * n_out);
     }
     return 0;
 }

@@ -6,7 +6,9 @@ Mutations: the unsquared Eq. (MSD03) update; mu instead of w*mu in the SNR;
 coefficient; the Eq. (MSD04) weights swapped; a shifted boxcar window; a
 strict threshold; sample instead of population sigma; the MSD04 ratio
 inverted; a widest-boxcar series one sample short; w instead of sqrt(w) in
-Eq. (sd02); the AUTO switch at rho > kappa.
+Eq. (sd02); the AUTO switch at rho > kappa; and in the decimated search, the
+start tested against the width instead of its stride, an inverted stride test
+and a stride grid shifted by one.
 """
 import os
 import subprocess
@@ -35,7 +37,11 @@ MUTATIONS = {
                           "for (int k = 0; k < nmax - 1; ++k) b += row[t + k];"),
     "w_not_sqrt_w": ("sig_w[i] = sqrt((double)W[i]) * sigma", "sig_w[i] = (double)W[i] * sigma"),
     "auto_at_kappa": ("if (rho > 1.0 + kappa) {", "if (rho > kappa) {"),
+    "stride_by_width": ("if (stride && t % stride[i] != 0) continue;", "if (stride && t % W[i] != 0) continue;"),
+    "stride_inverted": ("if (stride && t % stride[i] != 0) continue;", "if (stride && t % stride[i] == 0) continue;"),
+    "stride_shifted": ("if (stride && t % stride[i] != 0) continue;", "if (stride && (t + 1) % stride[i] != 0) continue;"),
 }
+PINS = ["test_oracle_pins.py", "test_oracle_dit_pins.py"]
 
 
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
@@ -48,7 +54,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     so = tmp_path / ("%s.so" % name)
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-o", str(so), str(c), "-lm"])
     env = dict(os.environ, SPD_ORACLE_LIB=str(so), OMP_NUM_THREADS="2")
-    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")], cwd=ROOT, env=env,
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider"] +
+                       [os.path.join(ROOT, "tests", f) for f in PINS], cwd=ROOT, env=env,
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, "planted mistake %s passed every pin:\n%s" % (name, r.stdout[-500:])
