@@ -183,6 +183,27 @@ spd_status boxcar_snr(const spd_plane* x, const spd_params* p, const spd_row_sta
                       void* stream);
 
 /*
+ * boxcar_snr_dit -- boxcars combined with decimation in time, the direction
+ *   Sec. 3 gives for boxcars wider than 16 samples: level 0 runs widths 1..16
+ *   at every start; level l = 1..levels runs widths 9..16 on the series
+ *   decimated l times (adjacent pairs summed each time), which is the window
+ *   of 2^l*(9..16) samples at starts that are multiples of 2^l.  Every
+ *   evaluated window's SNR is the one boxcar_snr gives for it; only the set of
+ *   windows is smaller (about a third of the work of 1..16 plus every width
+ *   step up to 256, for levels = 4), at the cost of sensitivity to pulses
+ *   between the decimated grid points and widths.
+ *   p->widths must be exactly that list in ascending order: 1..16, then
+ *   2^l*9 .. 2^l*16 in steps of 2^l for l = 1..levels (levels 0..4, so the
+ *   widest boxcar is 16*2^levels).  stats come from msd_compute with the same
+ *   params.  Outputs as in boxcar_snr: per start t in [0, n_cols - Nmax], the
+ *   highest SNR over the widths evaluated at t and the index (into p->widths)
+ *   of the first width reaching it; candidates {r, width, t + t_offset, snr}.
+ */
+spd_status boxcar_snr_dit(const spd_plane* x, const spd_params* p, int32_t levels, const spd_row_stats* stats,
+                          float* snr_out, uint8_t* widx_out, int64_t out_stride, int64_t t_offset,
+                          spd_candidate* cand, int64_t cand_capacity, int64_t* cand_count, void* stream);
+
+/*
  * select_candidates -- Sec. 2.4 on stored outputs: every (r, t) with
  *   snr[r*out_stride + t] >= p->threshold, t < n_out_cols, becomes
  *   {r, p->widths[widx[...]], t + t_offset, snr}.  Unordered; capacity and

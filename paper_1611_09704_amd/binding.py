@@ -103,6 +103,8 @@ def load():
         lib.spd_detect.argtypes = [P(SpdPlane), P(SpdParams), vp, vp, vp, i64, i64, vp, i64, vp, vp,
                                    ctypes.c_size_t, i32, vp, vp]
         lib.spd_detect.restype = ctypes.c_int
+        lib.boxcar_snr_dit.argtypes = [P(SpdPlane), P(SpdParams), i32, vp, vp, vp, i64, i64, vp, i64, vp, vp]
+        lib.boxcar_snr_dit.restype = ctypes.c_int
         lib.spd_batch_plan_create.argtypes = [P(SpdPlane), i32, P(SpdParams), i32, P(vp)]
         lib.spd_batch_plan_create.restype = ctypes.c_int
         lib.spd_batch_run.argtypes = [vp, vp, i64, vp, i32, vp]
@@ -236,6 +238,39 @@ def boxcar_snr(x: torch.Tensor, params: Params, stats: torch.Tensor, *, scale=No
                           widx.data_ptr() if widx is not None else None, int(out_stride), int(t_offset),
                           cand.data_ptr() if cand is not None else None, int(cap),
                           cand_count.data_ptr() if cand_count is not None else None, _stream(stream)))
+
+
+DIT_BASE = 16
+
+
+def dit_widths(levels: int) -> list:
+    """Widths of the decimated search: 1..16, then 2^l*(9..16) for l = 1..levels."""
+    w = list(range(1, DIT_BASE + 1))
+    for lv in range(1, levels + 1):
+        w += [k << lv for k in range(DIT_BASE // 2 + 1, DIT_BASE + 1)]
+    return w
+
+
+def dit_params(levels: int, threshold: float, scope: str = "row", sigma_mode: str = "sqrtn",
+               kappa: float = 1.0) -> Params:
+    return Params(dit_widths(levels), threshold, scope, sigma_mode, kappa)
+
+
+def boxcar_snr_dit(x: torch.Tensor, params: Params, levels: int, stats: torch.Tensor, *, scale=None, zero=None,
+                   snr: Optional[torch.Tensor] = None, widx: Optional[torch.Tensor] = None,
+                   out_stride: Optional[int] = None, t_offset: int = 0, cand: Optional[torch.Tensor] = None,
+                   cand_count: Optional[torch.Tensor] = None, stream=None) -> None:
+    """Boxcars combined with decimation in time (widths from dit_widths)."""
+    lib = load()
+    pl = plane_struct(x, scale, zero)
+    if out_stride is None:
+        out_stride = snr.stride(0) if snr is not None else (widx.stride(0) if widx is not None else 0)
+    cap = cand.shape[0] if cand is not None else 0
+    _check(lib.boxcar_snr_dit(ctypes.byref(pl), ctypes.byref(params.c), int(levels), stats.data_ptr(),
+                              snr.data_ptr() if snr is not None else None,
+                              widx.data_ptr() if widx is not None else None, int(out_stride), int(t_offset),
+                              cand.data_ptr() if cand is not None else None, int(cap),
+                              cand_count.data_ptr() if cand_count is not None else None, _stream(stream)))
 
 
 def select_candidates(snr: torch.Tensor, widx: torch.Tensor, params: Params, *, n_out_cols: Optional[int] = None,

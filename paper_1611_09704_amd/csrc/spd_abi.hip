@@ -448,6 +448,54 @@ spd_status spd_detect(const spd_plane* x, const spd_params* p, spd_row_stats* st
     return SPD_OK;
 }
 
+spd_status boxcar_snr_dit(const spd_plane* x, const spd_params* p, int32_t levels, const spd_row_stats* stats,
+                          float* snr_out, uint8_t* widx_out, int64_t out_stride, int64_t t_offset,
+                          spd_candidate* cand, int64_t cand_capacity, int64_t* cand_count, void* stream)
+{
+    clear_error();
+    spd_status st;
+    if ((st = check_params(p)) || (st = check_plane(x, p))) return st;
+    if (levels < 0 || levels > kDitMaxLevels)
+        return fail(SPD_E_INVALID, "levels=%d outside [0, %d]", levels, kDitMaxLevels);
+    const int n = kDitBase + (kDitBase / 2) * levels;
+    bool ok = p->n_widths == n;
+    for (int i = 0; i < n && ok; ++i) {
+        const int lv = i < kDitBase ? 0 : 1 + (i - kDitBase) / (kDitBase / 2);
+        const int w = i < kDitBase ? i + 1 : (kDitBase / 2 + 1 + (i - kDitBase) % (kDitBase / 2)) << lv;
+        ok = p->widths[i] == w;
+    }
+    if (!ok) return fail(SPD_E_INVALID, "widths must be 1..16, then 2^l*(9..16) for l = 1..levels");
+    BoxcarPlan bp;
+    if ((st = plan_boxcar(x, p, stats, snr_out, widx_out, out_stride, t_offset, cand, cand_capacity, cand_count,
+                          bp)))
+        return st;
+    // the decimated layout: x' in padded rows of 9, then one region per level
+    WidthPlan& wp = bp.wp;
+    BoxcarArgs& ba = bp.ba;
+    const int X = kWinX;
+    const int nlog = 64 * X + wp.nmax + 8;
+    const int npw = (nlog + 7) / 8 * 9;
+    int wave_floats = npw;
+    for (int lv = 1; lv <= levels; ++lv) wave_floats += dit_level_floats(levels, lv);
+    wave_floats = (std::max(wave_floats, 64 * X + 16 * X) + 3) & ~3;
+    const size_t tables = (size_t)kWinTableFloats * 4;
+    if (tables + (size_t)wave_floats * 4 > 65536) return fail(SPD_E_UNSUPPORTED, "decimated window does not fit in LDS");
+    wp.win = 3;
+    wp.n_arr = 1;
+    ba.npw = npw;
+    ba.wave_floats = wave_floats;
+    bp.waves = (int)std::min<size_t>(4, (65536 - tables) / ((size_t)wave_floats * 4));
+    ba.tiles_per_row = (ba.nout + (int64_t)bp.waves * 64 * X - 1) / ((int64_t)bp.waves * 64 * X);
+    if ((uint64_t)x->n_rows * (uint64_t)ba.tiles_per_row * 64u * (uint64_t)bp.waves > kMaxGridItems)
+        return fail(SPD_E_UNSUPPORTED, "plane too large for one launch");
+    hipStream_t s = (hipStream_t)stream;
+    if (cand) {
+        hipError_t e = launch_zero_count(cand_count, s);
+        if (e != hipSuccess) return device_status(e, "count reset launch");
+    }
+    return enqueue_boxcar(x, stats, bp, 0, x->n_rows, s);
+}
+
 spd_status select_candidates(const float* snr, const uint8_t* widx, int64_t n_rows, int64_t n_out_cols,
                              int64_t out_stride, const spd_params* p, int64_t t_offset, spd_candidate* cand,
                              int64_t cand_capacity, int64_t* cand_count, void* stream)

@@ -674,7 +674,7 @@ __device__ void boxcar_tile(const PlaneArg& pl, bool vec, int64_t r, int64_t tt,
 // (n <= 16) over x' itself.  Results are those of boxcar_tile: the same
 // running sums in the same order, and the same first-maximiser rule.
 
-template <int DT, int SMALLN>
+template <int DT, int SMALLN, bool DIT = false>
 __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t tt, const spd_row_stats& st,
                                 const BoxcarArgs& ba, const WidthPlan& wp, float* smem)
 {
@@ -822,6 +822,64 @@ __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t
                 sv[i] = m;
                 iv[i] = idx;
             }
+        }
+        if constexpr (DIT) {
+            // Decimated levels: level lv holds x'_lv[k] = x'_{lv-1}[2k] + x'_{lv-1}[2k+1].
+            // Lane l evaluates widths 9..16 at its 8/2^lv decimated starts
+            // 8l/2^lv + j (level 4: lane l/2, even lanes only), i.e. physical
+            // widths 2^lv*(9..16) at starts 8l + 2^lv*j, and keeps them where
+            // they beat the narrower widths (ascending width, strict '>').
+            const int levels = (wp.n - kDitBase) / (kDitBase / 2);
+            float* lev = arrs + ba.npw;
+            auto level = [&](auto lv_c) {
+                constexpr int LV = decltype(lv_c)::value;
+                constexpr int S = LV < 4 ? (8 >> LV) : 1;              // decimated starts per lane
+                float* dst = lev;
+                for (int l2 = 1; l2 < LV; ++l2) dst += dit_level_floats(levels, l2);
+                const float* src = LV == 1 ? arrs : dst - dit_level_floats(levels, LV - 1);
+                const int n = dit_level_len(levels, LV);
+                for (int k = lane; k < n; k += 64) {
+                    const int a = LV == 1 ? win_phys(2 * k) : dit_pad(LV - 1, 2 * k);
+                    const int b = LV == 1 ? win_phys(2 * k + 1) : dit_pad(LV - 1, 2 * k + 1);
+                    dst[dit_pad(LV, k)] = __fadd_rn(src[a], src[b]);
+                }
+                wave_sync();
+                const int lstride = LV == 1 ? 5 : LV == 2 ? 3 : 1;      // padded offset of lane l's first start
+                const float* lbv = dst + (LV < 4 ? lstride * lane : (lane >> 1));
+                constexpr int NV = S + kDitBase - 1;
+                float v[NV];
+#pragma unroll
+                for (int m = 0; m < NV; ++m) v[m] = lbv[dit_pad(LV, m)];
+                const int c0 = kDitBase + (kDitBase / 2) * (LV - 1);
+                const float4 a03 = *(const float4*)(coef + c0);
+                const float4 a47 = *(const float4*)(coef + c0 + 4);
+                const float a[8] = {a03.x, a03.y, a03.z, a03.w, a47.x, a47.y, a47.z, a47.w};
+#pragma unroll
+                for (int j = 0; j < S; ++j) {
+                    float b = 0.f, sk[8];
+#pragma unroll
+                    for (int q = 0; q < kDitBase; ++q) {
+                        b = __fadd_rn(b, v[j + q]);
+                        if (q >= kDitBase / 2) sk[q - kDitBase / 2] = __fmul_rn(b, a[q - kDitBase / 2]);
+                    }
+                    float m = sk[0];
+#pragma unroll
+                    for (int q = 1; q < 8; ++q) m = fmaxf(m, sk[q]);
+                    int kk = 0;
+#pragma unroll
+                    for (int q = 7; q >= 0; --q) kk = (sk[q] == m) ? q : kk;
+                    const int i = LV < 4 ? (j << LV) : 0;
+                    const bool here = LV < 4 || (lane & 1) == 0;
+                    if (here && m > sv[i]) {
+                        sv[i] = m;
+                        iv[i] = c0 + kk;
+                    }
+                }
+            };
+            if (levels >= 1) level(std::integral_constant<int, 1>());
+            if (levels >= 2) level(std::integral_constant<int, 2>());
+            if (levels >= 3) level(std::integral_constant<int, 3>());
+            if (levels >= 4) level(std::integral_constant<int, 4>());
         }
     } else {
         float B[X], mx[X], Bg[X];

@@ -22,6 +22,23 @@ constexpr int kWinTableFloats = (kMaxWidthsPadded + 2 * kMaxGroups + 63) / 64 * 
 // Register-window form: logical element m of a wave's LDS array is stored at
 // m + m/8 (one pad float after every 8).
 __host__ __device__ constexpr int win_phys(int m) { return m + (m >> 3); }
+
+// Decimated search (boxcars combined with decimation in time): base widths
+// 1..kDitBase, then kDitBase/2+1..kDitBase on the series decimated 1..levels
+// times.  Level lv of a wave holds dit_level_len(levels, lv) decimated
+// samples, padded so that the starts of lane l begin at a conflict-free offset
+// (level 1: one pad per 4, level 2: one pad per 2, level >= 3: none).
+constexpr int kDitBase = 16;
+constexpr int kDitMaxLevels = 4;
+__host__ __device__ constexpr int dit_level_len(int levels, int lv)
+{
+    return (64 * kWinX + (kDitBase - 1) * (1 << levels)) >> lv;
+}
+__host__ __device__ constexpr int dit_pad(int lv, int k) { return lv == 1 ? k + (k >> 2) : lv == 2 ? k + (k >> 1) : k; }
+__host__ __device__ constexpr int dit_level_floats(int levels, int lv)
+{
+    return (dit_pad(lv, dit_level_len(levels, lv) - 1) + 1 + 3) & ~3;
+}
 // LDS floats of the boxcar kernel's coefficient and step tables, rounded up so
 // the per-wave arrays after them start on a 256-byte boundary.
 constexpr int kTableFloats = (3 * kMaxWidthsPadded + 63) / 64 * 64;
@@ -39,7 +56,8 @@ struct WidthPlan {
     int32_t n_arr;          // presummed arrays in use (array 0 is x' itself, gap 1)
     int32_t arr_gap[kMaxArrays];
     int32_t unit_counts;    // 1 when every cnt_i == 1
-    int32_t win;            // register-window form: 0 none, 1 groups of 8, 2 the list 1..n (n <= 16)
+    int32_t win;            // register-window form: 0 none, 1 groups of 8, 2 the list 1..n (n <= 16),
+                            // 3 the decimated search (1..16, then 2^l*(9..16))
     uint32_t off[kMaxWidthsPadded];    // element offset of the first read: array base + w_{i-1}
     uint32_t cg[kMaxWidthsPadded];     // cnt | (gap << 16)
     int16_t width[kMaxWidthsPadded];   // w_i

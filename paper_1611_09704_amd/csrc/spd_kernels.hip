@@ -8,6 +8,8 @@
 //                                  Sec. 2.4 (starts 64 apart per lane)
 //   boxcar_win_kernel              the same with 8 consecutive starts per lane
 //                                  and each group's reads held in registers
+//   boxcar_dit_kernel              boxcars combined with decimation in time
+//                                  (widths 2^l*(9..16) on the decimated series)
 //   select_kernel                  threshold over stored outputs, Sec. 2.4
 //
 // One work-group per (row, column block) or (row, time tile), numbered so that
@@ -75,6 +77,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SMALLN == 0
     const int64_t tt = (int64_t)(tile % (uint64_t)ba.tiles_per_row);
     const spd_row_stats st = stats[ba.scope == SPD_SCOPE_ROW ? r : 0];
     boxcar_tile_win<DT, SMALLN>(pl, vec, r, tt, st, ba, wp, smem);
+}
+
+// Boxcars combined with decimation in time: widths 1..16 at every start, and
+// 2^l*(9..16) at starts that are multiples of 2^l, l = 1..levels.
+template <int DT>
+__global__ __launch_bounds__(256) void boxcar_dit_kernel(PlaneArg pl, bool vec, const spd_row_stats* stats,
+                                                         BoxcarArgs ba, WidthPlan wp)
+{
+    extern __shared__ float smem[];
+    const uint64_t tile = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t r = (int64_t)(tile / (uint64_t)ba.tiles_per_row);
+    const int64_t tt = (int64_t)(tile % (uint64_t)ba.tiles_per_row);
+    const spd_row_stats st = stats[ba.scope == SPD_SCOPE_ROW ? r : 0];
+    boxcar_tile_win<DT, kDitBase, true>(pl, vec, r, tt, st, ba, wp, smem);
 }
 
 // Sec. 2.4 over stored snr / width-index arrays.
@@ -177,7 +193,9 @@ static hipError_t launch_boxcar_dt(const PlaneArg& pl, bool vec, const spd_row_s
 {
     const size_t lds = boxcar_lds_bytes(waves, ba, wp.win != 0);   // <= 64 KiB by construction of the plan
     constexpr int X = kOutPerLane;
-    if (wp.win == 1)
+    if (wp.win == 3)
+        hipLaunchKernelGGL((boxcar_dit_kernel<DT>), dim3(ntiles), dim3(64 * waves), lds, s, pl, vec, stats, ba, wp);
+    else if (wp.win == 1)
         hipLaunchKernelGGL((boxcar_win_kernel<DT, 0>), dim3(ntiles), dim3(64 * waves), lds, s, pl, vec, stats, ba, wp);
     else if (wp.win == 2 && wp.n <= 8)
         hipLaunchKernelGGL((boxcar_win_kernel<DT, 8>), dim3(ntiles), dim3(64 * waves), lds, s, pl, vec, stats, ba, wp);

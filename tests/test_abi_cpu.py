@@ -127,6 +127,24 @@ def test_detect_validation(lib):
         assert msg in _err(lib), (kw, _err(lib))
 
 
+def test_dit_validation(lib):
+    import oracle
+    for lv in range(5):
+        assert B.dit_widths(lv) == oracle.dit_widths(lv)[0]
+    pl = _plane(cols=3000, stride=3000)
+    p = B.dit_params(2, 6.0)
+
+    def call(params=p, levels=2, stats=FAKE, snr=FAKE, stride=3000):
+        return lib.boxcar_snr_dit(ctypes.byref(pl), ctypes.byref(params.c), levels, stats, snr, None, stride, 0,
+                                  None, 0, None, None)
+
+    for kw, msg in [(dict(levels=5), "levels"), (dict(levels=-1), "levels"), (dict(levels=3), "widths must"),
+                    (dict(params=B.Params(list(range(1, 17)) + [18], 6.0)), "widths must"),
+                    (dict(stats=None), "stats"), (dict(snr=None), "no output"), (dict(stride=10), "out_stride")]:
+        assert call(**kw) == 1, kw
+        assert msg in _err(lib), (kw, _err(lib))
+
+
 def test_batch_validation(lib):
     p = B.Params([1, 2, 4, 8], 5.0)
     out = ctypes.c_void_p(123)
