@@ -308,10 +308,10 @@ __device__ void msd_block_xy(const PlaneArg& pl, bool vec, int64_t r, int64_t b,
     for (int64_t u0 = c0 + (int64_t)wave * TSW; u0 < c1; u0 += (int64_t)nw * TSW) {
         const int64_t u1 = min(u0 + TSW, c1);
         float carry = 0.f;
-        for (int m = 0; m < nrow; ++m) {
+        // one row of 256 samples: raw statistics, then its share of the prefix E
+        auto row = [&](int m, float4 v) {
             const int p = 256 * m + 4 * lane;
             const int64_t c = u0 + p;
-            const float4 v = load4_shifted<DT>(ld, c, pl.n_cols, vec, K, 0.f);
             if (p < TSW) msd_add4_clipped(sx, v, c, xlo, u1);
             const float l0 = v.x, l1 = l0 + v.y, l2 = l1 + v.z, l3 = l2 + v.w;
             const float inc = wave_inclusive_scan(l3);
@@ -319,6 +319,24 @@ __device__ void msd_block_xy(const PlaneArg& pl, bool vec, int64_t r, int64_t b,
             carry += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(inc), 63));
             const float4 e = make_float4(ex, ex + l0, ex + l1, ex + l2);
             *(float4*)(E + p) = e;
+        };
+        if (vec && u0 + 256 * nrow <= pl.n_cols) {
+            // the sub-tile and its halo inside the row: four vector loads in flight at once
+            for (int m0 = 0; m0 < nrow; m0 += 4) {
+                float4 v[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] = ld.vec(u0 + 256 * min(m0 + j, nrow - 1) + 4 * lane);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    if (m0 + j < nrow) {
+                        float4 w = v[j];
+                        w.x -= K; w.y -= K; w.z -= K; w.w -= K;
+                        row(m0 + j, w);
+                    }
+                }
+            }
+        } else {
+            for (int m = 0; m < nrow; ++m) row(m, load4_shifted<DT>(ld, u0 + 256 * m + 4 * lane, pl.n_cols, vec, K, 0.f));
         }
         wave_sync();
 #pragma unroll
