@@ -42,6 +42,11 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
+def boxcar_kernel_name() -> str:
+    """The one-plane boxcar kernel the library launches for the SKA and 1..16 lists."""
+    return "boxcar_kernel" if os.environ.get("SPD_BOXCAR_FORM") == "strided" else "boxcar_win_kernel"
+
+
 def load_traffic(workload: str):
     """HBM bytes per launch from committed rocprofv3 counters, if they were
     taken on the current kernel sources."""
@@ -164,7 +169,7 @@ def main():
                    "scope": "row", "outputs": "snr f32 + width u8 per sample, fused candidate list"},
         "roofline": {"bound": "alu", "achieved": round(box_tops, 3), "peak": round(VALU_PEAK_TOPS, 2),
                      "unit": "TFLOP/s", "frac": round(box_tops / VALU_PEAK_TOPS, 4),
-                     "traffic": load_traffic(args.workload), "kernel": "boxcar_kernel",
+                     "traffic": load_traffic(args.workload), "kernel": boxcar_kernel_name(),
                      "work_per_launch": "%d (t,w) evaluations x %d FP32 ops" % (evals, OPS_PER_EVAL)},
         "kernels": {
             "msd_compute": {"ms": round(msd_ms, 4), "GB/s": round(msd_bytes / msd_ms / 1e6, 1),
@@ -187,7 +192,7 @@ def main():
             "unit": "GSamples/s", "ms_per_step": round(w16 / args.steps * 1e3, 3),
             "roofline": {"bound": "hbm", "achieved": round(bb16 / b16 / 1e6, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(bb16 / b16 / 1e6 / HBM_PEAK_GBS, 4),
-                         "traffic": load_traffic("ska16"), "kernel": "boxcar_kernel"},
+                         "traffic": load_traffic("ska16"), "kernel": boxcar_kernel_name()},
             "msd_ms": round(m16, 4), "boxcar_ms": round(b16, 4),
             "msd_hbm_frac": round(msd_bytes / m16 / 1e6 / HBM_PEAK_GBS, 4),
         }
@@ -378,7 +383,7 @@ def run_dit(args, dev, levels=4):
                    "threshold": thr, "sigma_mode": "auto", "kappa": 1.0,
                    "outputs": "snr f32 + width u8 per sample, fused candidate list"},
         "roofline": {"bound": "alu", "achieved": round(tops, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
-                     "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": None, "kernel": "boxcar_dit_kernel",
+                     "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": load_traffic("dit"), "kernel": "boxcar_dit_kernel",
                      "work_per_launch": "%d (t,w) evaluations (%.3f per start) x %d FP32 ops" % (
                          evals, per_start, OPS_PER_EVAL)},
         "kernels": {"msd_compute": {"ms": round(msd_ms, 4)}, "boxcar_snr_dit": {"ms": round(box_ms, 4)}},

@@ -26,7 +26,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 COPY_BYTES = 1 << 31          # calibration copy: reads and writes 2 GiB
-WORKLOADS = {"ska": None, "ska16": list(range(1, 17))}
+WORKLOADS = {"ska": None, "ska16": list(range(1, 17)), "dit": "dit"}
+DIT_LEVELS = 4
 
 
 def kernel_source_sha() -> str:
@@ -52,7 +53,8 @@ def run(args):
     del src, dst
     cfg = synth.ska(device=dev, R=args.rows, L=args.cols)
     x = cfg["plane"].x
-    W = WORKLOADS[args.workload] or cfg["widths"]
+    dit = WORKLOADS[args.workload] == "dit"
+    W = B.dit_widths(DIT_LEVELS) if dit else (WORKLOADS[args.workload] or cfg["widths"])
     p = B.Params(W, cfg["threshold"], "row", cfg["sigma_mode"], cfg["kappa"])
     R, L = x.shape
     nout = L - p.nmax + 1
@@ -64,7 +66,10 @@ def run(args):
     count = torch.zeros(1, dtype=torch.int64, device=dev)
     for k in range(args.steps):
         B.msd_compute(x, p, stats=stats, workspace=ws)
-        B.boxcar_snr(x, p, stats, snr=snr, widx=widx, cand=cand, cand_count=count)
+        if dit:
+            B.boxcar_snr_dit(x, p, DIT_LEVELS, stats, snr=snr, widx=widx, cand=cand, cand_count=count)
+        else:
+            B.boxcar_snr(x, p, stats, snr=snr, widx=widx, cand=cand, cand_count=count)
         torch.cuda.synchronize()
         print("step %d done, %d candidates" % (k, int(count.item())), flush=True)
 
@@ -79,8 +84,8 @@ def _short(name: str, with_args: bool = False) -> str:
     targs = ""
     if with_args and "<" in name.split("(")[0]:
         targs = "<" + name.split("(")[0].split("<", 1)[1]
-    for key in ("batch_boxcar_grid_kernel", "batch_boxcar_kernel", "batch_msd_kernel", "batch_finalize_kernel",
-                "boxcar_win_kernel", "boxcar_kernel", "msd_xy_kernel", "msd_x_kernel", "msd_finalize_kernel",
+    for key in ("batch_boxcar_win_grid_kernel", "batch_boxcar_grid_kernel", "batch_boxcar_kernel", "batch_msd_kernel",
+                "batch_finalize_kernel", "boxcar_dit_kernel", "boxcar_win_kernel", "boxcar_kernel", "msd_xy_kernel", "msd_x_kernel", "msd_finalize_kernel",
                 "select_kernel",
                 "fill_i64_kernel"):
         if key in name:
@@ -184,7 +189,8 @@ def summarize(args):
             d = json.load(open(tpath))
         except (OSError, ValueError):
             d = {}
-        box = traffic.get("boxcar_win_kernel") or traffic.get("boxcar_kernel") or {}
+        box = (traffic.get("boxcar_dit_kernel") or traffic.get("boxcar_win_kernel") or traffic.get("boxcar_kernel")
+               or {})
         d[args.workload] = {"kernel_sha": sha, **box,
                             "msd": traffic.get("msd_xy_kernel") or traffic.get("msd_x_kernel")}
         json.dump(d, open(tpath, "w"), indent=1)
