@@ -1054,11 +1054,21 @@ __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t
     wave_sync();
     const int64_t wleft = ba.nout - tw;                             // valid starts of this wave
     const int64_t rowo = r * ba.out_stride + tw + lane;
+    float* ds = ba.snr ? ba.snr + rowo : nullptr;                   // one base each, immediate offsets below
+    uint8_t* db = ba.widx ? ba.widx + rowo : nullptr;
+    if (wleft >= 64 * X) {
 #pragma unroll
-    for (int i = 0; i < X; ++i) {
-        if (lane + 64 * i < wleft) {
-            if (ba.snr) ba.snr[rowo + 64 * i] = xs[lane + 64 * i];
-            if (ba.widx) ba.widx[rowo + 64 * i] = xb[lane + 64 * i];
+        for (int i = 0; i < X; ++i) {
+            if (ds) ds[64 * i] = xs[lane + 64 * i];
+            if (db) db[64 * i] = xb[lane + 64 * i];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < X; ++i) {
+            if (lane + 64 * i < wleft) {
+                if (ds) ds[64 * i] = xs[lane + 64 * i];
+                if (db) db[64 * i] = xb[lane + 64 * i];
+            }
         }
     }
 }
