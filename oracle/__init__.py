@@ -15,7 +15,11 @@ The functions follow the paper's steps:
 * ``select`` -- Sec. 2.4, the SNR threshold and the candidate list;
 * ``dit_widths`` / ``dit_detect`` -- boxcars combined with decimation in time
   (the direction Sec. 3 names for wide boxcars): the same definition with
-  width 2^l*w evaluated only at starts that are multiples of 2^l.
+  width 2^l*w evaluated only at starts that are multiples of 2^l;
+* ``cluster_peaks`` -- peak-finding over the candidates of Sec. 2.4 (a step
+  the paper leaves out: its list is unclustered): a candidate is kept iff no
+  sample within the DM-row and time radii has a higher SNR, and no sample
+  there with the same SNR comes first in row-major order.
 
 The readings taken where the paper is silent or garbled are listed in the
 header of ``spd_oracle.c``.
@@ -211,6 +215,32 @@ def dit_detect(x, levels, threshold, *, base=16, scope="row", sigma_mode="sqrtn"
                                       nthreads=nthreads, strides=strides)
     cands = select(snr, widx, widths, threshold)
     return {"stats": stats, "snr": snr, "widx": widx, "cands": cands, "widths": widths, "strides": strides}
+
+
+def cluster_peaks(snr, threshold, dm_radius, t_radius):
+    """Peaks among the candidates (snr >= threshold) of a snr plane [rows][starts].
+
+    (r, t) is a peak iff snr[r, t] >= threshold and every other (r', t') with
+    |r' - r| <= dm_radius and |t' - t| <= t_radius inside the plane has
+    snr[r', t'] < snr[r, t], or an equal SNR and a later row-major position.
+    Returns row and t arrays in row-major order."""
+    snr = np.asarray(snr, dtype=np.float64)
+    R, L = snr.shape
+    rows, ts = [], []
+    for r, t in np.argwhere(snr >= threshold):
+        v = snr[r, t]
+        r0, r1 = max(0, r - dm_radius), min(R, r + dm_radius + 1)
+        t0, t1 = max(0, t - t_radius), min(L, t + t_radius + 1)
+        win = snr[r0:r1, t0:t1]
+        if np.any(win > v):
+            continue
+        rr, tt = np.nonzero(win == v)
+        rr, tt = rr + r0, tt + t0
+        if np.any((rr < r) | ((rr == r) & (tt < t))):
+            continue
+        rows.append(int(r))
+        ts.append(int(t))
+    return {"row": np.array(rows, dtype=np.int64), "t": np.array(ts, dtype=np.int64)}
 
 
 def dequantize_u8(q, scale, zero) -> np.ndarray:
