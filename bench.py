@@ -34,10 +34,14 @@ VALU_PEAK_TOPS = 256 * 4 * 2 * 64 / 4 * 2.4e9 / 1e12
 OPS_PER_EVAL = 3          # boxcar add, SNR multiply, running-max compare per (t, w)
 
 
-def kernel_source_sha() -> str:
+BOXCAR_SOURCES = ("spd_device.h", "spd_kernels.hip", "spd_kernels.h", "spd_internal.h")
+CLUSTER_SOURCES = ("spd_cluster.hip",)
+
+
+def kernel_source_sha(files=BOXCAR_SOURCES) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1611_09704_amd", "csrc")
-    for f in ("spd_device.h", "spd_kernels.hip", "spd_kernels.h", "spd_internal.h"):   # device code
+    for f in files:   # device code
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -56,7 +60,7 @@ def load_traffic(workload: str):
     except (OSError, ValueError):
         return None
     e = d.get(workload)
-    if not e or e.get("kernel_sha") != kernel_source_sha():
+    if not e or e.get("kernel_sha") != kernel_source_sha(CLUSTER_SOURCES if workload == "cluster" else BOXCAR_SOURCES):
         return None
     return e.get("hbm_bytes_per_launch")
 
@@ -72,7 +76,7 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--workload", default="ska", choices=["ska", "ska16"],
                     help="ska: widths 1..16,18..256/2 (default); ska16: the same plane with widths 1..16 only")
-    ap.add_argument("--form", default="plain", choices=["plain", "batch", "serve", "precision", "dit"],
+    ap.add_argument("--form", default="plain", choices=["plain", "batch", "serve", "precision", "dit", "cluster"],
                     help="plain: the SKA-like plane (default); batch: 48 uneven beams in one persistent, "
                          "graph-replayed launch per step, against per-beam plain launches")
     ap.add_argument("--batch-samples", type=float, default=40e9,
@@ -104,6 +108,9 @@ def main():
         return
     if args.form == "dit":
         print(json.dumps(run_dit(args, dev)), flush=True)
+        return
+    if args.form == "cluster":
+        print(json.dumps(run_cluster(args, dev)), flush=True)
         return
     cfg = synth.ska(device=dev, R=args.rows, L=args.cols)
     x = cfg["plane"].x
@@ -396,6 +403,126 @@ def run_dit(args, dev, levels=4):
                         "best_snr_ratio_p05": round(float(np.percentile(r, 5)), 4),
                         "best_snr_ratio_min": round(float(r.min()), 4),
                         "detected_dit": int(found_d), "detected_exhaustive": int(found_e)},
+    }
+
+
+def run_cluster(args, dev, dm_radius=2, t_radius=256):
+    """Peak-finding over the candidate list (cluster_candidates) on the
+    SKA-like plane, radii 2 DM rows x 256 starts.  The step is the whole path
+    (statistics, boxcars with stored SNRs and the fused threshold) plus the
+    peak-finding, in the headline configuration (AUTO sigma_N); the same plane
+    in sqrt(N) mode, whose signal-dominated rows flood the list, is timed too,
+    and the reported roofline is the peak-finding kernel's on that flood: HBM,
+    with the algorithmic bytes the candidate and peak records plus every plane
+    sample inside some candidate's neighbourhood read once."""
+    import numpy as np
+    import torch
+
+    from paper_1611_09704_amd import binding as B
+    from paper_1611_09704_amd import synth
+    cfg = synth.ska(device=dev, R=args.rows, L=args.cols)
+    pl = cfg["plane"]
+    x = pl.x
+    R, L = x.shape
+    thr = cfg["threshold"]
+    stream = torch.cuda.current_stream()
+    stats = torch.empty((R, B.STATS_FIELDS), dtype=torch.float64, device=dev)
+    cap = 1 << 23
+    cand = B.new_candidates(cap, dev)
+    peaks = B.new_candidates(1 << 20, dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    pcount = torch.zeros(1, dtype=torch.int64, device=dev)
+    out = {}
+    for mode in ("auto", "sqrtn"):
+        p = B.Params(cfg["widths"], thr, "row", mode, 1.0)
+        ws = torch.empty(B.workspace_bytes(x, p), dtype=torch.uint8, device=dev)
+        nout = L - p.nmax + 1
+        snr = torch.empty((R, nout), dtype=torch.float32, device=dev)
+
+        def path(ev=None):
+            if ev: ev[0].record(stream)
+            B.msd_compute(x, p, stats=stats, workspace=ws, stream=stream)
+            B.boxcar_snr(x, p, stats, snr=snr, cand=cand, cand_count=count, stream=stream)
+            if ev: ev[1].record(stream)
+            B.cluster_candidates(snr, cand, count, dm_radius, t_radius, peaks=peaks, peak_count=pcount,
+                                 stream=stream)
+            if ev: ev[2].record(stream)
+
+        K = args.steps if mode == "auto" else max(2, args.steps // 2)
+        for _ in range(args.warmup):
+            path()
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+        t0 = time.perf_counter()
+        for k in range(K):
+            path(ev[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        path_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+        cl_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+        n_c, n_p = int(count.item()), int(pcount.item())
+        if n_c > cap or n_p > peaks.shape[0]:
+            raise RuntimeError("candidate or peak list overflowed (%d, %d)" % (n_c, n_p))
+        recs = B.candidates_to_numpy(cand, n_c)
+        # plane samples inside some candidate's neighbourhood: dilate the
+        # candidate mask by the radii (prefix sums along each axis)
+        mask = torch.zeros((R + 1, nout + 1), dtype=torch.int32, device=dev)
+        rows_t = torch.from_numpy(recs["row"].astype(np.int64)).to(dev)
+        ts_t = torch.from_numpy(recs["t"].astype(np.int64)).to(dev)
+        mask[rows_t, ts_t] = 1
+        del rows_t, ts_t
+        c = torch.cumsum(mask, 1, dtype=torch.int32)
+        del mask
+        lo_t = torch.clamp(torch.arange(nout, device=dev) - t_radius - 1, min=-1)
+        hi_t = torch.clamp(torch.arange(nout, device=dev) + t_radius, max=nout - 1)
+        row_hit = torch.empty((R, nout), dtype=torch.int32, device=dev)
+        for r0 in range(0, R, 256):
+            r1 = min(R, r0 + 256)
+            cr = c[r0:r1]
+            lo_v = torch.where(lo_t >= 0, cr[:, lo_t.clamp(min=0)], torch.zeros_like(cr[:, :nout]))
+            row_hit[r0:r1] = (cr[:, hi_t] - lo_v) > 0
+            del cr, lo_v
+        del c
+        rc = torch.cumsum(torch.cat([torch.zeros((1, nout), dtype=torch.int32, device=dev), row_hit]), 0,
+                          dtype=torch.int32)
+        ri = torch.arange(R, device=dev)
+        hi_r = torch.clamp(ri + dm_radius + 1, max=R)
+        lo_r = torch.clamp(ri - dm_radius, min=0)
+        touched = 0
+        for r0 in range(0, R, 256):
+            r1 = min(R, r0 + 256)
+            touched += int(((rc[hi_r[r0:r1]] - rc[lo_r[r0:r1]]) > 0).sum().item())
+        del rc, row_hit
+        torch.cuda.empty_cache()
+        alg = 24 * n_c + 24 * n_p + 4 * touched
+        gbs = alg / (cl_ms * 1e-3) / 1e9
+        # every injected pulse should leave a peak within dm_radius rows and one width of its start
+        pk = B.candidates_to_numpy(peaks, n_p)
+        hit = 0
+        for q in pl.pulses:
+            sel = (np.abs(pk["row"] - q.row) <= dm_radius) & (np.abs(pk["t"] - q.t0) <= q.width)
+            hit += bool(sel.any())
+        out[mode] = {"n_candidates": n_c, "n_peaks": n_p, "path_ms": round(path_ms, 4),
+                     "cluster_ms": round(cl_ms, 4), "candidates_per_s": round(n_c / (cl_ms * 1e-3), 1),
+                     "neighbourhood_samples": touched,
+                     "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                  "traffic": load_traffic("cluster") if mode == "sqrtn" else None,
+                                  "kernel": "cluster_kernel", "bytes_per_launch": alg},
+                     "pulses_with_a_peak": hit, "pulses": len(pl.pulses),
+                     "value": round(R * L * K / wall / 1e9, 3)}
+        del snr, ws
+        torch.cuda.empty_cache()
+    a = out["auto"]
+    return {
+        "metric": METRIC, "value": a["value"], "unit": "GSamples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(R * L / (a["value"] * 1e9) * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "cluster-" + cfg["name"], "widths": "1..16,18..256/2", "threshold": thr,
+                   "sigma_mode": "auto", "kappa": 1.0, "dm_radius": dm_radius, "t_radius": t_radius,
+                   "outputs": "snr f32 per sample, fused candidate list, peak list"},
+        "roofline": out["sqrtn"]["roofline"], "auto": a, "sqrtn": out["sqrtn"],
     }
 
 

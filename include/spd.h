@@ -253,6 +253,37 @@ spd_status spd_detect(const spd_plane* x, const spd_params* p, spd_row_stats* st
                       void* workspace, size_t workspace_bytes, int32_t row_chunks,
                       void* stream, void* aux_stream);
 
+/*
+ * cluster_candidates -- peak-finding over a candidate list, a step after
+ *   Sec. 2.4, whose list keeps every sample above the threshold (the paper
+ *   does not cluster): candidate c is kept iff, with r = c.row and
+ *   t = c.t - t_offset, no (r', t') with |r' - r| <= dm_radius,
+ *   |t' - t| <= t_radius inside the plane has snr[r'][t'] > snr[r][t], or an
+ *   equal SNR and (r', t') earlier in row-major order.  A plateau therefore
+ *   keeps one sample, and peaks farther apart than the radii all survive.
+ *   snr         [n_rows][out_stride] float on the device, the plane boxcar_snr
+ *               (or boxcar_snr_dit) wrote for these candidates; out_stride >=
+ *               n_out_cols.  Read only.
+ *   cand        device list; min(*cand_count, cand_capacity) entries are read
+ *               (cand_count is a device int64, as boxcar_snr leaves it).
+ *               Entries whose (row, t - t_offset) lies outside the plane are
+ *               never kept.
+ *   peaks       device list of peak_capacity entries, not overlapping cand;
+ *               each kept candidate is copied there whole, unordered.
+ *   peak_count  device int64, reset by the call, receives the number of
+ *               peaks, which may exceed peak_capacity (then only that many
+ *               are written).
+ *   dm_radius   0..SPD_MAX_DM_RADIUS rows; t_radius 0..SPD_MAX_T_RADIUS
+ *               starts.  Both 0 keep every candidate.
+ *   Enqueued on stream; nothing is allocated.
+ */
+#define SPD_MAX_DM_RADIUS 4096
+#define SPD_MAX_T_RADIUS (1 << 20)
+spd_status cluster_candidates(const float* snr, int64_t n_rows, int64_t n_out_cols, int64_t out_stride,
+                              int64_t t_offset, const spd_candidate* cand, int64_t cand_capacity,
+                              const int64_t* cand_count, int32_t dm_radius, int32_t t_radius,
+                              spd_candidate* peaks, int64_t peak_capacity, int64_t* peak_count, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched form: the same path over many beams of uneven shape per step.
  * Every beam gets per-row statistics (Sec. 2.1-2.2), then the boxcar/SNR

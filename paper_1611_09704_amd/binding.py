@@ -104,6 +104,8 @@ def load():
                                    ctypes.c_size_t, i32, vp, vp]
         lib.spd_detect.restype = ctypes.c_int
         lib.boxcar_snr_dit.argtypes = [P(SpdPlane), P(SpdParams), i32, vp, vp, vp, i64, i64, vp, i64, vp, vp]
+        lib.cluster_candidates.argtypes = [vp, i64, i64, i64, i64, vp, i64, vp, i32, i32, vp, i64, vp, vp]
+        lib.cluster_candidates.restype = ctypes.c_int
         lib.boxcar_snr_dit.restype = ctypes.c_int
         lib.spd_batch_plan_create.argtypes = [P(SpdPlane), i32, P(SpdParams), i32, P(vp)]
         lib.spd_batch_plan_create.restype = ctypes.c_int
@@ -277,11 +279,39 @@ def select_candidates(snr: torch.Tensor, widx: torch.Tensor, params: Params, *, 
                       t_offset: int = 0, cand: torch.Tensor, cand_count: torch.Tensor, stream=None) -> None:
     """Threshold of Sec. 2.4 over stored snr / width-index arrays."""
     lib = load()
+    if snr.dtype != torch.float32 or widx.dtype != torch.uint8 or snr.dim() != 2 or widx.shape != snr.shape:
+        raise ValueError("snr (float32) and widx (uint8) must be 2-D arrays of one shape")
+    if snr.stride(1) != 1 or widx.stride(1) != 1 or widx.stride(0) != snr.stride(0):
+        raise ValueError("snr and widx must share one row stride with unit column stride")
     n_rows = snr.shape[0]
     ncols = snr.shape[1] if n_out_cols is None else int(n_out_cols)
     _check(lib.select_candidates(snr.data_ptr(), widx.data_ptr(), n_rows, ncols, snr.stride(0),
                                  ctypes.byref(params.c), int(t_offset), cand.data_ptr(), cand.shape[0],
                                  cand_count.data_ptr(), _stream(stream)))
+
+
+def cluster_candidates(snr: torch.Tensor, cand: torch.Tensor, cand_count: torch.Tensor, dm_radius: int,
+                       t_radius: int, *, n_out_cols: Optional[int] = None, t_offset: int = 0,
+                       peaks: Optional[torch.Tensor] = None, peak_count: Optional[torch.Tensor] = None,
+                       stream=None):
+    """Peak-finding over a candidate list in (DM row, time) against the snr
+    plane it came from: keeps the candidates with no higher SNR within the
+    radii (ties go to the first sample in row-major order).  Returns
+    (peaks, peak_count); the count is a device int64 and may exceed the
+    peak list's capacity (by default that of the candidate list)."""
+    lib = load()
+    if snr.dtype != torch.float32 or snr.dim() != 2 or snr.stride(1) != 1:
+        raise ValueError("snr must be a float32 [rows][stride] view with unit column stride")
+    ncols = snr.shape[1] if n_out_cols is None else int(n_out_cols)
+    if peaks is None:
+        peaks = new_candidates(max(1, cand.shape[0]), snr.device)
+    if peak_count is None:
+        peak_count = torch.zeros(1, dtype=torch.int64, device=snr.device)
+    _check(lib.cluster_candidates(snr.data_ptr(), snr.shape[0], ncols, snr.stride(0), int(t_offset),
+                                  cand.data_ptr(), cand.shape[0], cand_count.data_ptr(), int(dm_radius),
+                                  int(t_radius), peaks.data_ptr(), peaks.shape[0], peak_count.data_ptr(),
+                                  _stream(stream)))
+    return peaks, peak_count
 
 
 _aux_streams = {}

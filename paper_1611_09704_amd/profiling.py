@@ -26,14 +26,17 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 COPY_BYTES = 1 << 31          # calibration copy: reads and writes 2 GiB
-WORKLOADS = {"ska": None, "ska16": list(range(1, 17)), "dit": "dit"}
+WORKLOADS = {"ska": None, "ska16": list(range(1, 17)), "dit": "dit", "cluster": "cluster"}
+BOXCAR_SOURCES = ("spd_device.h", "spd_kernels.hip", "spd_kernels.h", "spd_internal.h")
+CLUSTER_SOURCES = ("spd_cluster.hip",)
+CLUSTER_RADII = (2, 256)     # DM rows, starts
 DIT_LEVELS = 4
 
 
-def kernel_source_sha() -> str:
+def kernel_source_sha(files=BOXCAR_SOURCES) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1611_09704_amd", "csrc")
-    for f in ("spd_device.h", "spd_kernels.hip", "spd_kernels.h", "spd_internal.h"):   # device code
+    for f in files:   # device code
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -54,24 +57,31 @@ def run(args):
     cfg = synth.ska(device=dev, R=args.rows, L=args.cols)
     x = cfg["plane"].x
     dit = WORKLOADS[args.workload] == "dit"
-    W = B.dit_widths(DIT_LEVELS) if dit else (WORKLOADS[args.workload] or cfg["widths"])
-    p = B.Params(W, cfg["threshold"], "row", cfg["sigma_mode"], cfg["kappa"])
+    cluster = WORKLOADS[args.workload] == "cluster"
+    W = B.dit_widths(DIT_LEVELS) if dit else (cfg["widths"] if cluster else WORKLOADS[args.workload] or cfg["widths"])
+    # the peak-finding workload runs sqrt(N) mode, whose signal-dominated rows flood the list
+    p = B.Params(W, cfg["threshold"], "row", "sqrtn" if cluster else cfg["sigma_mode"], cfg["kappa"])
     R, L = x.shape
     nout = L - p.nmax + 1
     stats = torch.empty((R, B.STATS_FIELDS), dtype=torch.float64, device=dev)
     ws = torch.empty(B.workspace_bytes(x, p), dtype=torch.uint8, device=dev)
     snr = torch.empty((R, nout), dtype=torch.float32, device=dev)
     widx = torch.empty((R, nout), dtype=torch.uint8, device=dev)
-    cand = B.new_candidates(1 << 21, dev)
+    cand = B.new_candidates(1 << 23 if cluster else 1 << 21, dev)
     count = torch.zeros(1, dtype=torch.int64, device=dev)
+    peaks = B.new_candidates(1 << 20, dev)
+    pcount = torch.zeros(1, dtype=torch.int64, device=dev)
     for k in range(args.steps):
         B.msd_compute(x, p, stats=stats, workspace=ws)
         if dit:
             B.boxcar_snr_dit(x, p, DIT_LEVELS, stats, snr=snr, widx=widx, cand=cand, cand_count=count)
         else:
             B.boxcar_snr(x, p, stats, snr=snr, widx=widx, cand=cand, cand_count=count)
+        if cluster:
+            B.cluster_candidates(snr, cand, count, *CLUSTER_RADII, peaks=peaks, peak_count=pcount)
         torch.cuda.synchronize()
-        print("step %d done, %d candidates" % (k, int(count.item())), flush=True)
+        print("step %d done, %d candidates%s" % (k, int(count.item()),
+                                                 ", %d peaks" % int(pcount.item()) if cluster else ""), flush=True)
 
 
 def _csvs(d, suffix):
@@ -86,7 +96,7 @@ def _short(name: str, with_args: bool = False) -> str:
         targs = "<" + name.split("(")[0].split("<", 1)[1]
     for key in ("batch_boxcar_win_grid_kernel", "batch_boxcar_grid_kernel", "batch_boxcar_kernel", "batch_msd_kernel",
                 "batch_finalize_kernel", "boxcar_dit_kernel", "boxcar_win_kernel", "boxcar_kernel", "msd_xy_kernel", "msd_x_kernel", "msd_finalize_kernel",
-                "select_kernel",
+                "select_kernel", "cluster_kernel",
                 "fill_i64_kernel"):
         if key in name:
             return key + targs
@@ -120,7 +130,7 @@ def summarize(args):
         total = sum(float(r["TotalDurationNs"]) for r in rows) or 1.0
         for row in rows:
             name = _short(row["Name"], with_args=True)
-            if not any(k in name for k in ("boxcar", "msd", "select", "finalize", "fill_i64")):
+            if not any(k in name for k in ("boxcar", "msd", "select", "finalize", "fill_i64", "cluster")):
                 continue
             lines.append("| %s | %s | %.4f | %.3f | %.2f%% |" % (
                 name, row["Calls"], float(row["AverageNs"]) / 1e6, float(row["TotalDurationNs"]) / 1e6,
@@ -132,7 +142,7 @@ def summarize(args):
         meta = {}
         for row in csv.DictReader(open(traces[0])):
             name = _short(row["Kernel_Name"], with_args=True)
-            if not any(k in name for k in ("boxcar", "msd", "select", "finalize", "fill_i64")):
+            if not any(k in name for k in ("boxcar", "msd", "select", "finalize", "fill_i64", "cluster")):
                 continue
             key = (name, int(row["Grid_Size_X"]))
             groups[key].append((int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e6)
@@ -163,7 +173,7 @@ def summarize(args):
         lines.append("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read GB | written GB |")
         lines.append("|---|---|---|---|---|---|")
         for k in sorted(set(fc) | set(wc)):
-            if not any(s in k for s in ("boxcar", "msd", "select")):
+            if not any(s in k for s in ("boxcar", "msd", "select", "cluster")):
                 continue
             f = fc.get(k, {}).get("FETCH_SIZE", [])
             w = wc.get(k, {}).get("WRITE_SIZE", [])
@@ -189,10 +199,13 @@ def summarize(args):
             d = json.load(open(tpath))
         except (OSError, ValueError):
             d = {}
-        box = (traffic.get("boxcar_dit_kernel") or traffic.get("boxcar_win_kernel") or traffic.get("boxcar_kernel")
-               or {})
-        d[args.workload] = {"kernel_sha": sha, **box,
-                            "msd": traffic.get("msd_xy_kernel") or traffic.get("msd_x_kernel")}
+        if args.workload == "cluster":
+            d["cluster"] = {"kernel_sha": kernel_source_sha(CLUSTER_SOURCES), **traffic.get("cluster_kernel", {})}
+        else:
+            box = (traffic.get("boxcar_dit_kernel") or traffic.get("boxcar_win_kernel")
+                   or traffic.get("boxcar_kernel") or {})
+            d[args.workload] = {"kernel_sha": sha, **box,
+                                "msd": traffic.get("msd_xy_kernel") or traffic.get("msd_x_kernel")}
         json.dump(d, open(tpath, "w"), indent=1)
         print("wrote", tpath)
 

@@ -244,3 +244,32 @@ def stream_chunks(n_chunks: int, R: int, L_chunk: int, *, seed: int, device="cpu
                 c[p.row, a - lo:b - lo] += p.amp
         chunks.append(c.to(dtype))
     return chunks, pulses
+
+
+# ---------------------------------------------------------------------------
+# SNR-like planes for the peak-finding step on its own.
+# ---------------------------------------------------------------------------
+
+def snr_plane(R: int, L: int, *, seed: int, n_bumps: int = 8, quantum: float = 0.25,
+              n_plateaus: int = 2) -> np.ndarray:
+    """A float32 [R][L] plane shaped like the SNR output of the boxcar step:
+    N(0,1) background, plus ``n_bumps`` clouds that fall off over DM rows and
+    starts from a peak of 6..30 (the cloud one bright pulse leaves), plus
+    ``n_plateaus`` flat rectangles.  Values are rounded to multiples of
+    ``quantum`` so that equal SNRs (ties) are common.  NumPy only."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    x = rng.standard_normal((R, L))
+    rr = np.arange(R)[:, None]
+    tt = np.arange(L)[None, :]
+    for _ in range(n_bumps):
+        r0, t0 = int(rng.integers(0, R)), int(rng.integers(0, L))
+        peak = float(rng.uniform(6.0, 30.0))
+        dr, dt = float(rng.uniform(0.5, 4.0)), float(rng.uniform(2.0, 200.0))
+        x += peak * np.exp(-np.abs(rr - r0) / dr - np.abs(tt - t0) / dt)
+    for _ in range(n_plateaus):
+        r0, t0 = int(rng.integers(0, R)), int(rng.integers(0, L))
+        h, w = int(rng.integers(1, 4)), int(rng.integers(1, 40))
+        x[r0:r0 + h, t0:t0 + w] = float(rng.uniform(8.0, 12.0))
+    if quantum > 0:
+        x = np.round(x / quantum) * quantum
+    return x.astype(np.float32)

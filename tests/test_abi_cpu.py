@@ -145,6 +145,22 @@ def test_dit_validation(lib):
         assert msg in _err(lib), (kw, _err(lib))
 
 
+def test_cluster_validation(lib):
+    C = B.CANDIDATE_DTYPE.itemsize
+
+    def call(snr=FAKE, rows=4, cols=100, stride=100, cand=FAKE, cap=10, count=FAKE, dr=1, dt=8,
+             peaks=FAKE + 4096, pcap=10, pcount=FAKE):
+        return lib.cluster_candidates(snr, rows, cols, stride, 0, cand, cap, count, dr, dt, peaks, pcap, pcount, None)
+
+    for kw, msg in [(dict(snr=None), "required"), (dict(count=None), "required"), (dict(peaks=None), "required"),
+                    (dict(pcount=None), "required"), (dict(rows=-1), "shape"), (dict(stride=99), "shape"),
+                    (dict(cap=-1), "capacities"), (dict(pcap=-2), "capacities"), (dict(dr=-1), "radii"),
+                    (dict(dt=(1 << 20) + 1), "radii"), (dict(dr=4097), "radii"),
+                    (dict(peaks=FAKE + 9 * C), "overlap"), (dict(peaks=FAKE - 10 * C + 1), "overlap")]:
+        assert call(**kw) == 1, kw
+        assert msg in _err(lib), (kw, _err(lib))
+
+
 def test_batch_validation(lib):
     p = B.Params([1, 2, 4, 8], 5.0)
     out = ctypes.c_void_p(123)

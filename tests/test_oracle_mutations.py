@@ -9,6 +9,11 @@ inverted; a widest-boxcar series one sample short; w instead of sqrt(w) in
 Eq. (sd02); the AUTO switch at rho > kappa; and in the decimated search, the
 start tested against the width instead of its stride, an inverted stride test
 and a stride grid shifted by one.
+
+The peak-finding step of the oracle (Python) gets its own slips, planted in
+a copy of the oracle package: '>=' instead of '>' against the neighbours, the
+tie broken towards the later sample, a time radius one short, the DM radius
+ignored, and a strict threshold.
 """
 import os
 import subprocess
@@ -56,5 +61,35 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     env = dict(os.environ, SPD_ORACLE_LIB=str(so), OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider"] +
                        [os.path.join(ROOT, "tests", f) for f in PINS], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0, "planted mistake %s passed every pin:\n%s" % (name, r.stdout[-500:])
+
+
+PY_SRC = os.path.join(ROOT, "oracle", "__init__.py")
+PY_MUTATIONS = {
+    "peak_ge": ("if np.any(win > v):", "if np.any(win >= v):"),
+    "peak_tie_later": ("if np.any((rr < r) | ((rr == r) & (tt < t))):", "if np.any((rr > r) | ((rr == r) & (tt > t))):"),
+    "peak_t_radius_short": ("t0, t1 = max(0, t - t_radius), min(L, t + t_radius + 1)",
+                            "t0, t1 = max(0, t - t_radius + 1), min(L, t + t_radius)"),
+    "peak_no_dm_radius": ("r0, r1 = max(0, r - dm_radius), min(R, r + dm_radius + 1)", "r0, r1 = r, r + 1"),
+    "peak_strict_threshold": ("for r, t in np.argwhere(snr >= threshold):", "for r, t in np.argwhere(snr > threshold):"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTATIONS))
+def test_cluster_pins_catch_planted_mistake(name, tmp_path):
+    a, b = PY_MUTATIONS[name]
+    src = open(PY_SRC).read()
+    assert src.count(a) == 1, "mutation site not found"
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    (pkg / "__init__.py").write_text(src.replace(a, b))
+    lib = os.path.join(ROOT, "oracle", "libspd_oracle.so")
+    env = dict(os.environ, SPD_ORACLE_LIB=lib, PYTHONPATH=str(tmp_path) + os.pathsep + ROOT)
+    probe = subprocess.run([sys.executable, "-c", "import oracle; print(oracle.__file__)"], cwd=str(tmp_path),
+                           env=env, capture_output=True, text=True)
+    assert probe.stdout.strip().startswith(str(tmp_path)), probe.stdout + probe.stderr
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "--rootdir", str(tmp_path),
+                        os.path.join(ROOT, "tests", "test_oracle_cluster_pins.py")], cwd=str(tmp_path), env=env,
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, "planted mistake %s passed every pin:\n%s" % (name, r.stdout[-500:])
