@@ -46,6 +46,36 @@ def kernel_source_sha(files=BOXCAR_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
+def measured_copy_gbs(dev, nbytes=1 << 31, reps=5) -> float:
+    """Streaming-copy rate of the device (read + write bytes per second, GB/s):
+    the practical HBM ceiling the kernels are also compared against."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def boxcar_kernel_name() -> str:
     """The one-plane boxcar kernel the library launches for the SKA and 1..16 lists."""
     return "boxcar_kernel" if os.environ.get("SPD_BOXCAR_FORM") == "strided" else "boxcar_win_kernel"
@@ -68,8 +98,8 @@ def load_traffic(workload: str):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--rows", type=int, default=4096)
     ap.add_argument("--cols", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -153,9 +183,12 @@ def main():
         wall = time.perf_counter() - t0
         msd_ms = sum(e[0].elapsed_time(e[1]) for e in evs) / K
         box_ms = sum(e[1].elapsed_time(e[2]) for e in evs) / K
+        timed.step_ms = np.array([e[0].elapsed_time(e[2]) for e in evs])
         return wall, msd_ms, box_ms
 
+    copy_gbs = measured_copy_gbs(dev)
     wall, msd_ms, box_ms = timed(p, args.steps, args.warmup)
+    step_ms = timed.step_ms
     n_cand = int(count.item())
     if n_cand > cap:
         print("warning: %d candidates exceed the list capacity %d" % (n_cand, cap), file=sys.stderr)
@@ -178,13 +211,19 @@ def main():
                      "unit": "TFLOP/s", "frac": round(box_tops / VALU_PEAK_TOPS, 4),
                      "traffic": load_traffic(args.workload), "kernel": boxcar_kernel_name(),
                      "work_per_launch": "%d (t,w) evaluations x %d FP32 ops" % (evals, OPS_PER_EVAL)},
+        "step_ms_events": {"p10": round(float(np.percentile(step_ms, 10)), 3),
+                           "p50": round(float(np.percentile(step_ms, 50)), 3),
+                           "p90": round(float(np.percentile(step_ms, 90)), 3)},
         "kernels": {
             "msd_compute": {"ms": round(msd_ms, 4), "GB/s": round(msd_bytes / msd_ms / 1e6, 1),
-                            "hbm_frac": round(msd_bytes / msd_ms / 1e6 / HBM_PEAK_GBS, 4)},
-            "boxcar_snr": {"ms": round(box_ms, 4), "GB/s": round(box_bytes / box_ms / 1e6, 1),
+                            "hbm_frac": round(msd_bytes / msd_ms / 1e6 / HBM_PEAK_GBS, 4),
+                            "frac_of_measured_copy": round(msd_bytes / msd_ms / 1e6 / copy_gbs, 4)},
+            "boxcar_snr": {"ms": round(box_ms, 4), "GSamples/s": round(samples / box_ms / 1e6, 3),
+                           "GB/s": round(box_bytes / box_ms / 1e6, 1),
                            "hbm_frac": round(box_bytes / box_ms / 1e6 / HBM_PEAK_GBS, 4),
                            "valu_frac": round(box_tops / VALU_PEAK_TOPS, 4)},
         },
+        "measured_copy_GB/s": round(copy_gbs, 1),
         "n_candidates": n_cand,
         "kernel_sha": kernel_source_sha(),
     }
@@ -224,7 +263,16 @@ def main():
         out["cpu_baseline"] = {"value": round(nrows * L / dt / 1e9, 5), "unit": "GSamples/s", "cores": cores,
                                "kind": "oracle",
                                "sample": "%d of %d rows x %d samples, same widths / AUTO sigma_N, FP64, "
-                                         "%.1f s wall" % (nrows, R, L, dt)}
+                                         "%.1f s wall" % (nrows, R, L, dt),
+                               "cpu_model": cpu_model()}
+        # one thread on the small plane (64 x 65,536, widths 1..32, sqrt(N) sigma_N)
+        small = synth.tiny(device="cpu")["plane"].x.double().numpy()
+        t0 = time.perf_counter()
+        oracle.stream_step(small, list(range(1, 33)), sigma_mode="sqrtn", nthreads=1)
+        d1 = time.perf_counter() - t0
+        out["cpu_baseline"]["one_thread_small_plane"] = {"value": round(small.size / d1 / 1e9, 5),
+                                                         "unit": "GSamples/s", "seconds": round(d1, 3),
+                                                         "sample": "64 x 65536, widths 1..32"}
     print(json.dumps(out), flush=True)
 
 

@@ -19,7 +19,12 @@ The functions follow the paper's steps:
 * ``cluster_peaks`` -- peak-finding over the candidates of Sec. 2.4 (a step
   the paper leaves out: its list is unclustered): a candidate is kept iff no
   sample within the DM-row and time radii has a higher SNR, and no sample
-  there with the same SNR comes first in row-major order.
+  there with the same SNR comes first in row-major order;
+* ``dedisp_channel_factors`` / ``dedisp_delays`` / ``dedisperse`` -- the step
+  before the path (Sec. 1: detection runs on de-dispersed series): brute-force
+  incoherent de-dispersion of a frequency x time filterbank, the sum over
+  channels of each channel shifted by its cold-plasma dispersion delay,
+  rounded to whole samples.
 
 The readings taken where the paper is silent or garbled are listed in the
 header of ``spd_oracle.c``.
@@ -241,6 +246,48 @@ def cluster_peaks(snr, threshold, dm_radius, t_radius):
         rows.append(int(r))
         ts.append(int(t))
     return {"row": np.array(rows, dtype=np.int64), "t": np.array(ts, dtype=np.int64)}
+
+
+# Dispersion constant of the cold-plasma delay law, in MHz^2 pc^-1 cm^3 s:
+# a signal at frequency f (MHz) through dispersion measure DM (pc cm^-3)
+# arrives KDM * DM / f^2 seconds later than at infinite frequency.
+KDM = 4.148808e3
+
+
+def dedisp_channel_factors(n_chan, f_top_mhz, chan_bw_mhz, t_samp_s):
+    """k_c, the delay of channel c relative to channel 0 per unit DM, in samples:
+    KDM * (1/f_c^2 - 1/f_top^2) / t_samp with f_c = f_top - c * chan_bw
+    (channel 0 is the highest frequency).  FP64, evaluated in that order."""
+    f = float(f_top_mhz) - np.arange(int(n_chan), dtype=np.float64) * float(chan_bw_mhz)
+    ft = float(f_top_mhz)
+    return KDM * (1.0 / (f * f) - 1.0 / (ft * ft)) / float(t_samp_s)
+
+
+def dedisp_delays(dm, kc) -> np.ndarray:
+    """Delay of channel c at trial DM d, rounded to the nearest sample (halves
+    up): floor(dm[d] * k_c + 0.5), the product and the sum each rounded in
+    FP64.  int64 [n_dm][n_chan]."""
+    dm = np.asarray(dm, dtype=np.float64)
+    kc = np.asarray(kc, dtype=np.float64)
+    return np.floor(dm[:, None] * kc[None, :] + 0.5).astype(np.int64)
+
+
+def dedisperse(fb, dm, kc) -> np.ndarray:
+    """De-dispersed series of a filterbank fb [n_chan][n_samp]: for every trial
+    d and every t < n_samp - max delay, y[d][t] = sum over channels c of
+    fb[c][t + delay[d][c]].  Summed in FP64 (exact for 8-bit samples).
+    Returns [n_dm][n_out]."""
+    fb = np.asarray(fb)
+    delays = dedisp_delays(dm, kc)
+    n_out = fb.shape[1] - int(delays.max())
+    if n_out <= 0:
+        raise ValueError("the series is shorter than the largest delay")
+    out = np.zeros((delays.shape[0], n_out), dtype=np.float64)
+    for d in range(delays.shape[0]):
+        for c in range(fb.shape[0]):
+            k = int(delays[d, c])
+            out[d] += fb[c, k:k + n_out]
+    return out
 
 
 def dequantize_u8(q, scale, zero) -> np.ndarray:

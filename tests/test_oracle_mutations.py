@@ -10,10 +10,14 @@ Eq. (sd02); the AUTO switch at rho > kappa; and in the decimated search, the
 start tested against the width instead of its stride, an inverted stride test
 and a stride grid shifted by one.
 
-The peak-finding step of the oracle (Python) gets its own slips, planted in
-a copy of the oracle package: '>=' instead of '>' against the neighbours, the
-tie broken towards the later sample, a time radius one short, the DM radius
-ignored, and a strict threshold.
+The peak-finding and de-dispersion steps of the oracle (Python) get their
+own slips, planted in a copy of the oracle package.  Peak-finding: '>='
+instead of '>' against the neighbours, the tie broken towards the later
+sample, a time radius one short, the DM radius ignored, a strict threshold.
+De-dispersion: the frequency terms swapped (delays of the wrong sign),
+channels counted upwards from the top frequency, delays truncated instead of
+rounded, the output one sample short, the delay table read transposed, and
+the dispersion constant off by the factor 1e3 of a units slip.
 """
 import os
 import subprocess
@@ -67,6 +71,12 @@ def test_pins_catch_planted_mistake(name, tmp_path):
 
 PY_SRC = os.path.join(ROOT, "oracle", "__init__.py")
 PY_MUTATIONS = {
+    "dedisp_sign": ("KDM * (1.0 / (f * f) - 1.0 / (ft * ft))", "KDM * (1.0 / (ft * ft) - 1.0 / (f * f))"),
+    "dedisp_channel_up": ("f = float(f_top_mhz) - np.arange", "f = float(f_top_mhz) + np.arange"),
+    "dedisp_truncate": ("np.floor(dm[:, None] * kc[None, :] + 0.5)", "np.floor(dm[:, None] * kc[None, :])"),
+    "dedisp_short": ("n_out = fb.shape[1] - int(delays.max())", "n_out = fb.shape[1] - int(delays.max()) - 1"),
+    "dedisp_transposed": ("k = int(delays[d, c])", "k = int(delays.T.reshape(delays.shape)[d, c])"),
+    "dedisp_units": ("KDM = 4.148808e3", "KDM = 4.148808"),
     "peak_ge": ("if np.any(win > v):", "if np.any(win >= v):"),
     "peak_tie_later": ("if np.any((rr < r) | ((rr == r) & (tt < t))):", "if np.any((rr > r) | ((rr == r) & (tt > t))):"),
     "peak_t_radius_short": ("t0, t1 = max(0, t - t_radius), min(L, t + t_radius + 1)",
@@ -77,7 +87,7 @@ PY_MUTATIONS = {
 
 
 @pytest.mark.parametrize("name", sorted(PY_MUTATIONS))
-def test_cluster_pins_catch_planted_mistake(name, tmp_path):
+def test_python_pins_catch_planted_mistake(name, tmp_path):
     a, b = PY_MUTATIONS[name]
     src = open(PY_SRC).read()
     assert src.count(a) == 1, "mutation site not found"
@@ -89,7 +99,8 @@ def test_cluster_pins_catch_planted_mistake(name, tmp_path):
     probe = subprocess.run([sys.executable, "-c", "import oracle; print(oracle.__file__)"], cwd=str(tmp_path),
                            env=env, capture_output=True, text=True)
     assert probe.stdout.strip().startswith(str(tmp_path)), probe.stdout + probe.stderr
+    pins = "test_oracle_dedisp_pins.py" if name.startswith("dedisp") else "test_oracle_cluster_pins.py"
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-x", "-p", "no:cacheprovider", "--rootdir", str(tmp_path),
-                        os.path.join(ROOT, "tests", "test_oracle_cluster_pins.py")], cwd=str(tmp_path), env=env,
+                        os.path.join(ROOT, "tests", pins)], cwd=str(tmp_path), env=env,
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0, "planted mistake %s passed every pin:\n%s" % (name, r.stdout[-500:])
