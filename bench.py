@@ -36,6 +36,7 @@ OPS_PER_EVAL = 3          # boxcar add, SNR multiply, running-max compare per (t
 
 BOXCAR_SOURCES = ("spd_device.h", "spd_kernels.hip", "spd_kernels.h", "spd_internal.h")
 CLUSTER_SOURCES = ("spd_cluster.hip",)
+DEDISP_SOURCES = ("spd_dedisp.hip",)
 
 
 def kernel_source_sha(files=BOXCAR_SOURCES) -> str:
@@ -46,24 +47,31 @@ def kernel_source_sha(files=BOXCAR_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_copy_gbs(dev, nbytes=1 << 31, reps=5) -> float:
-    """Streaming-copy rate of the device (read + write bytes per second, GB/s):
-    the practical HBM ceiling the kernels are also compared against."""
+def measured_stream_gbs(dev, nbytes=1 << 32, reps=5):
+    """Streaming rates measured on the device with library kernels (GB/s): a
+    device copy (read + write bytes) and a sum reduction (read bytes), the
+    practical HBM ceilings the kernels are also compared against."""
     import torch
     src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
     dst.copy_(src)
+    src.sum()
     torch.cuda.synchronize()
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    b.record()
-    torch.cuda.synchronize()
-    gbs = 2 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+
+    def rate(fn, moved):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return moved * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+
+    copy = rate(lambda: dst.copy_(src), 2 * nbytes)
+    read = rate(lambda: src.sum(), nbytes)
     del src, dst
     torch.cuda.empty_cache()
-    return gbs
+    return copy, read
 
 
 def cpu_model() -> str:
@@ -90,7 +98,8 @@ def load_traffic(workload: str):
     except (OSError, ValueError):
         return None
     e = d.get(workload)
-    if not e or e.get("kernel_sha") != kernel_source_sha(CLUSTER_SOURCES if workload == "cluster" else BOXCAR_SOURCES):
+    files = {"cluster": CLUSTER_SOURCES, "dedisp": DEDISP_SOURCES}.get(workload, BOXCAR_SOURCES)
+    if not e or e.get("kernel_sha") != kernel_source_sha(files):
         return None
     return e.get("hbm_bytes_per_launch")
 
@@ -106,7 +115,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--workload", default="ska", choices=["ska", "ska16"],
                     help="ska: widths 1..16,18..256/2 (default); ska16: the same plane with widths 1..16 only")
-    ap.add_argument("--form", default="plain", choices=["plain", "batch", "serve", "precision", "dit", "cluster"],
+    ap.add_argument("--form", default="plain",
+                    choices=["plain", "batch", "serve", "precision", "dit", "cluster", "dedisp"],
                     help="plain: the SKA-like plane (default); batch: 48 uneven beams in one persistent, "
                          "graph-replayed launch per step, against per-beam plain launches")
     ap.add_argument("--batch-samples", type=float, default=40e9,
@@ -141,6 +151,9 @@ def main():
         return
     if args.form == "cluster":
         print(json.dumps(run_cluster(args, dev)), flush=True)
+        return
+    if args.form == "dedisp":
+        print(json.dumps(run_dedisp(args, dev)), flush=True)
         return
     cfg = synth.ska(device=dev, R=args.rows, L=args.cols)
     x = cfg["plane"].x
@@ -186,7 +199,7 @@ def main():
         timed.step_ms = np.array([e[0].elapsed_time(e[2]) for e in evs])
         return wall, msd_ms, box_ms
 
-    copy_gbs = measured_copy_gbs(dev)
+    copy_gbs, read_gbs = measured_stream_gbs(dev)
     wall, msd_ms, box_ms = timed(p, args.steps, args.warmup)
     step_ms = timed.step_ms
     n_cand = int(count.item())
@@ -217,13 +230,13 @@ def main():
         "kernels": {
             "msd_compute": {"ms": round(msd_ms, 4), "GB/s": round(msd_bytes / msd_ms / 1e6, 1),
                             "hbm_frac": round(msd_bytes / msd_ms / 1e6 / HBM_PEAK_GBS, 4),
-                            "frac_of_measured_copy": round(msd_bytes / msd_ms / 1e6 / copy_gbs, 4)},
+                            "frac_of_measured_read": round(msd_bytes / msd_ms / 1e6 / read_gbs, 4)},
             "boxcar_snr": {"ms": round(box_ms, 4), "GSamples/s": round(samples / box_ms / 1e6, 3),
                            "GB/s": round(box_bytes / box_ms / 1e6, 1),
                            "hbm_frac": round(box_bytes / box_ms / 1e6 / HBM_PEAK_GBS, 4),
                            "valu_frac": round(box_tops / VALU_PEAK_TOPS, 4)},
         },
-        "measured_copy_GB/s": round(copy_gbs, 1),
+        "measured_stream_GB/s": {"copy": round(copy_gbs, 1), "sum_read": round(read_gbs, 1)},
         "n_candidates": n_cand,
         "kernel_sha": kernel_source_sha(),
     }
@@ -572,6 +585,123 @@ def run_cluster(args, dev, dm_radius=2, t_radius=256):
                    "outputs": "snr f32 per sample, fused candidate list, peak list"},
         "roofline": out["sqrtn"]["roofline"], "auto": a, "sqrtn": out["sqrtn"],
     }
+
+
+LDS_PEAK_ADDS = 256 * 128 / 4 * 2 * 2.4e9 / 1e12   # T adds/s: 128 B/clk/CU of LDS reads, 2 adds per 4 B
+
+
+def run_dedisp(args, dev, n_chan=4096, n_samp=1 << 20, n_dm=6000, n_pulses=40):
+    """De-dispersion in front of the path, the end-to-end search the paper
+    quotes against real time: an SKA-like 8-bit filterbank (4,096 channels,
+    1550 MHz down to 1250 MHz, 2^20 samples of 64 us = 67.1 s), 6,000 trial
+    DMs one sample of delay apart at the bottom of the band (0 to ~413 pc
+    cm^-3), 40 dispersed pulses.  A step is spd_dedisperse into the DM x time
+    plane, then msd_compute + boxcar_snr with the fused threshold
+    (candidates only), widths 1..16 (the paper's widest measured boxcar) and
+    AUTO sigma_N.  The real-time factor is the de-dispersed span (n_samp -
+    max delay samples, the advance of a streaming search) over the step time.
+    Roofline of the de-dispersion kernel: LDS bandwidth, two additions per
+    32-bit LDS read."""
+    import numpy as np
+    import torch
+
+    from paper_1611_09704_amd import binding as B
+    from paper_1611_09704_amd import synth
+    band = (1550.0, 300.0 / n_chan, 64e-6)
+    # trial spacing: one more sample of delay per trial at the lowest channel
+    f_low = band[0] - (n_chan - 1) * band[1]
+    samples_per_dm = 4.148808e3 * (1.0 / f_low ** 2 - 1.0 / band[0] ** 2) / band[2]
+    dm = np.arange(n_dm) / samples_per_dm
+    fb = synth.filterbank(n_chan, n_samp, seed=1611097060, device=dev)
+    delays, max_delay = B.dedisp_delay_table(n_chan, *band, dm)
+    rng = np.random.default_rng(1611097061)
+    pulses = []
+    for _ in range(n_pulses):
+        k = int(rng.integers(0, n_dm))
+        w = int(rng.integers(1, 17))
+        t = int(rng.integers(0, n_samp - max_delay - 64))
+        amp = int(rng.integers(1, 4))          # de-dispersed SNR ~ 4 * amp * sqrt(w): 4 .. 48
+        synth.inject_along(fb, delays[k], t, w, amp)
+        pulses.append((k, t, w, amp))
+    plan = B.DedispPlan(n_chan, *band, dm)
+    n_out = n_samp - plan.max_delay
+    # rows padded to 256 B so that the detection kernels take vector loads
+    y = torch.empty((n_dm, (n_out + 63) // 64 * 64), dtype=torch.float32, device=dev)[:, :n_out]
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, W in (("widths 1..16", list(range(1, 17))), ("SKA list 1..16,18..256/2", list(synth.SKA_WIDTHS))):
+        p = B.Params(W, 7.0, "row", "auto", 1.0)
+        stats = torch.empty((n_dm, B.STATS_FIELDS), dtype=torch.float64, device=dev)
+        ws = torch.empty(B.workspace_bytes(y, p), dtype=torch.uint8, device=dev)
+        cand = B.new_candidates(1 << 24, dev)
+        count = torch.zeros(1, dtype=torch.int64, device=dev)
+
+        def step(ev=None):
+            if ev: ev[0].record(stream)
+            plan.run(fb, out=y, stream=stream)
+            if ev: ev[1].record(stream)
+            B.msd_compute(y, p, stats=stats, workspace=ws, stream=stream)
+            B.boxcar_snr(y, p, stats, cand=cand, cand_count=count, stream=stream)
+            if ev: ev[2].record(stream)
+
+        K = args.steps if not out else max(2, args.steps // 4)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(K)]
+        t0 = time.perf_counter()
+        for k in range(K):
+            step(ev[k])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        dd_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+        det_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / K
+        n_c = int(count.item())
+        if n_c > cand.shape[0]:
+            raise RuntimeError("candidate list overflowed (%d)" % n_c)
+        c = B.candidates_to_numpy(cand, n_c)
+        found = 0
+        for (k, t, w, amp) in pulses:
+            sel = (np.abs(c["row"] - k) <= 2) & (np.abs(c["t"] - t) <= 16)
+            found += bool(sel.any())
+        out[name] = {"step_ms": round(wall / K * 1e3, 3), "dedisp_ms": round(dd_ms, 3),
+                     "detection_ms": round(det_ms, 3), "n_candidates": n_c, "pulses_found": found,
+                     "real_time_factor": round(n_out * band[2] / (wall / K), 2),
+                     "value": round(n_dm * n_out * K / wall / 1e9, 3)}
+        del stats, ws, cand
+    a = out["widths 1..16"]
+    adds = n_dm * n_chan * n_out
+    dd_ms = min(v["dedisp_ms"] for v in out.values())
+    tadds = adds / (dd_ms * 1e-3) / 1e12
+    res = {
+        "metric": METRIC, "value": a["value"], "unit": "GSamples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": a["step_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8 in, int32 sums, f32 plane", "data": "synthetic",
+        "config": {"workload": "dedisp-%dch-%dx%d-u8" % (n_chan, n_dm, n_samp), "band_mhz": [1550.0, 1250.0],
+                   "t_samp_s": band[2], "n_dm": n_dm, "dm_max": round(float(dm[-1]), 2),
+                   "max_delay": plan.max_delay, "n_out": n_out, "pulses": n_pulses,
+                   "detection": "msd_compute + boxcar_snr, AUTO sigma_N, threshold 7, candidates only"},
+        "roofline": {"bound": "lds", "achieved": round(tadds, 3), "peak": round(LDS_PEAK_ADDS, 2),
+                     "unit": "T adds/s", "frac": round(tadds / LDS_PEAK_ADDS, 4), "traffic": load_traffic("dedisp"),
+                     "kernel": "dedisp_u8_kernel", "work_per_launch": "%d additions (trials x channels x starts)" % adds},
+        "end_to_end": out,
+        "value_note": "value counts de-dispersed samples (trials x starts) per second through the whole step",
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        kc = oracle.dedisp_channel_factors(n_chan, *band)
+        trials = np.linspace(0, n_dm - 1, 4).astype(np.int64)
+        wcols = 20000
+        sub = fb[:, :wcols + plan.max_delay].cpu().numpy()
+        t0 = time.perf_counter()
+        oracle.dedisperse(sub, dm[trials], kc)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": round(len(trials) * wcols / dt / 1e9, 6), "unit": "GSamples/s", "cores": 1,
+                               "kind": "oracle", "sample": "%d trials x %d starts x %d channels, numpy FP64, %.1f s"
+                                                           % (len(trials), wcols, n_chan, dt)}
+    del y, fb
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_precision(args, dev):

@@ -285,6 +285,64 @@ spd_status cluster_candidates(const float* snr, int64_t n_rows, int64_t n_out_co
                               spd_candidate* peaks, int64_t peak_capacity, int64_t* peak_count, void* stream);
 
 /* ------------------------------------------------------------------------
+ * De-dispersion: the step before the path.  Detection runs on de-dispersed
+ * time series (Sec. 1); this builds them from a filterbank of 8-bit samples
+ * x[c][s], channel 0 the highest frequency, by brute-force incoherent
+ * de-dispersion:
+ *     y[d][t] = sum over c of x[c][t + delay(d, c)],   0 <= t < n_samp - max delay,
+ *     delay(d, c) = floor(dm[d] * k_c + 0.5),
+ *     k_c = 4.148808e3 * (1/f_c^2 - 1/f_top^2) / t_samp,   f_c = f_top - c * chan_bw,
+ * the cold-plasma dispersion delay (MHz, s, pc cm^-3) rounded to whole
+ * samples; the product and the sum in delay() are each rounded to FP64.
+ * The sums are exact (whole counts; below 2^24 for up to 65,536 channels).
+ * The output is a DM-trial x time plane that msd_compute / boxcar_snr take
+ * as they are.
+ * ------------------------------------------------------------------------ */
+#define SPD_MAX_CHANNELS 65536
+#define SPD_MAX_DM_TRIALS (1 << 20)
+#define SPD_MAX_DELAY (1 << 30)
+
+typedef struct {
+    int32_t n_chan;          /* channels, 1 .. SPD_MAX_CHANNELS */
+    int32_t reserved0;
+    double f_top_mhz;        /* frequency of channel 0 (the highest), MHz */
+    double chan_bw_mhz;      /* channel spacing, MHz, > 0: f_c = f_top - c * chan_bw > 0 */
+    double t_samp_s;         /* sampling time, s */
+} spd_band;
+
+typedef struct spd_dedisp_plan spd_dedisp_plan;
+
+/* Plan for one band and one list of trial DMs (host array dm[n_dm], pc cm^-3,
+ * finite, >= 0, non-decreasing; copied).  Computes the per-channel factors
+ * k_c, the largest delay and the largest delay difference between trials 16
+ * apart, and copies the tables to the current device (the only allocation).
+ * SPD_E_UNSUPPORTED when trials 16 apart differ by more delay than the LDS
+ * staging holds (about 16,000 samples) or the largest delay exceeds
+ * SPD_MAX_DELAY.                                                            */
+spd_status spd_dedisp_plan_create(const spd_band* band, const double* dm, int32_t n_dm, spd_dedisp_plan** plan);
+void spd_dedisp_plan_destroy(spd_dedisp_plan* plan);
+
+/* The largest delay (samples; n_out = n_samp - max_delay) and the largest
+ * delay difference between trials 16 apart.  Either pointer may be NULL.   */
+spd_status spd_dedisp_describe(const spd_dedisp_plan* plan, int32_t* max_delay, int32_t* span16);
+
+/* The plan's delay table, delay(d, c), into host delays[n_dm][n_chan].    */
+spd_status spd_dedisp_delays(const spd_dedisp_plan* plan, int32_t* delays);
+
+/* The same table and largest delay without a plan (host only, no device):
+ * validates band and dm as spd_dedisp_plan_create does; delays (host
+ * [n_dm][n_chan]) and max_delay may each be NULL.                          */
+spd_status spd_dedisp_delay_table(const spd_band* band, const double* dm, int32_t n_dm, int32_t* delays,
+                                  int32_t* max_delay);
+
+/* De-disperse fb (SPD_U8, n_rows = n_chan, n_cols = n_samp > max delay, data
+ * and row_stride 4-byte aligned, no row_scale / row_zero) into
+ * out[n_dm][out_stride] float (device), writing t < n_samp - max_delay of
+ * every row.  Enqueued on stream, on the plan's device.                    */
+spd_status spd_dedisperse(const spd_dedisp_plan* plan, const spd_plane* fb, float* out, int64_t out_stride,
+                          void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched form: the same path over many beams of uneven shape per step.
  * Every beam gets per-row statistics (Sec. 2.1-2.2), then the boxcar/SNR
  * pass with the fused threshold (Sec. 2.3-2.4); candidates carry their beam

@@ -57,6 +57,11 @@ class SpdBatchInfo(ctypes.Structure):
                 ("rows", ctypes.c_int64)]
 
 
+class SpdBand(ctypes.Structure):
+    _fields_ = [("n_chan", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("f_top_mhz", ctypes.c_double),
+                ("chan_bw_mhz", ctypes.c_double), ("t_samp_s", ctypes.c_double)]
+
+
 class SpdServerConfig(ctypes.Structure):
     _fields_ = [("n_beams", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n_rows", ctypes.c_int64),
                 ("chunk_cols", ctypes.c_int64), ("cand_capacity", ctypes.c_int64),
@@ -106,6 +111,18 @@ def load():
         lib.boxcar_snr_dit.argtypes = [P(SpdPlane), P(SpdParams), i32, vp, vp, vp, i64, i64, vp, i64, vp, vp]
         lib.cluster_candidates.argtypes = [vp, i64, i64, i64, i64, vp, i64, vp, i32, i32, vp, i64, vp, vp]
         lib.cluster_candidates.restype = ctypes.c_int
+        lib.spd_dedisp_plan_create.argtypes = [P(SpdBand), P(ctypes.c_double), i32, P(vp)]
+        lib.spd_dedisp_plan_create.restype = ctypes.c_int
+        lib.spd_dedisp_plan_destroy.argtypes = [vp]
+        lib.spd_dedisp_plan_destroy.restype = None
+        lib.spd_dedisp_describe.argtypes = [vp, P(i32), P(i32)]
+        lib.spd_dedisp_describe.restype = ctypes.c_int
+        lib.spd_dedisp_delays.argtypes = [vp, P(i32)]
+        lib.spd_dedisp_delays.restype = ctypes.c_int
+        lib.spd_dedisp_delay_table.argtypes = [P(SpdBand), P(ctypes.c_double), i32, P(i32), P(i32)]
+        lib.spd_dedisp_delay_table.restype = ctypes.c_int
+        lib.spd_dedisperse.argtypes = [vp, P(SpdPlane), vp, i64, vp]
+        lib.spd_dedisperse.restype = ctypes.c_int
         lib.boxcar_snr_dit.restype = ctypes.c_int
         lib.spd_batch_plan_create.argtypes = [P(SpdPlane), i32, P(SpdParams), i32, P(vp)]
         lib.spd_batch_plan_create.restype = ctypes.c_int
@@ -404,6 +421,73 @@ def detect(x: torch.Tensor, widths: Sequence[int], threshold: float, *, scope: s
         capacity = n
     return {"params": params, "stats": stats, "snr": snr, "widx": widx,
             "cands": candidates_to_numpy(cand, n), "n_cands": n}
+
+
+def dedisp_delay_table(n_chan: int, f_top_mhz: float, chan_bw_mhz: float, t_samp_s: float, dm):
+    """The library's delay table (host only) and largest delay."""
+    lib = load()
+    band = SpdBand(int(n_chan), 0, float(f_top_mhz), float(chan_bw_mhz), float(t_samp_s))
+    dm = np.ascontiguousarray(np.asarray(dm, dtype=np.float64))
+    out = np.empty((dm.size, int(n_chan)), dtype=np.int32)
+    md = ctypes.c_int32()
+    _check(lib.spd_dedisp_delay_table(ctypes.byref(band), dm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      int(dm.size), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      ctypes.byref(md)))
+    return out, int(md.value)
+
+
+class DedispPlan:
+    """Brute-force de-dispersion plan (spd_dedisp_*): one band (n_chan
+    channels from f_top_mhz down in steps of chan_bw_mhz, sampling t_samp_s)
+    and one non-decreasing list of trial DMs."""
+
+    def __init__(self, n_chan: int, f_top_mhz: float, chan_bw_mhz: float, t_samp_s: float, dm):
+        lib = load()
+        self._lib = lib
+        self.band = SpdBand(int(n_chan), 0, float(f_top_mhz), float(chan_bw_mhz), float(t_samp_s))
+        self.dm = np.ascontiguousarray(np.asarray(dm, dtype=np.float64))
+        self._h = ctypes.c_void_p()
+        _check(lib.spd_dedisp_plan_create(ctypes.byref(self.band),
+                                          self.dm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          int(self.dm.size), ctypes.byref(self._h)))
+        md, sp = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.spd_dedisp_describe(self._h, ctypes.byref(md), ctypes.byref(sp)))
+        self.max_delay, self.span16 = int(md.value), int(sp.value)
+
+    @property
+    def n_dm(self) -> int:
+        return int(self.dm.size)
+
+    def delays(self) -> np.ndarray:
+        out = np.empty((self.n_dm, self.band.n_chan), dtype=np.int32)
+        _check(self._lib.spd_dedisp_delays(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out
+
+    def run(self, fb: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """De-disperse fb (uint8 [n_chan][n_samp] device tensor, rows 4-byte
+        aligned) into out (float32 [n_dm][>= n_samp - max_delay]); returns out
+        narrowed to the valid columns."""
+        if fb.dtype != torch.uint8 or fb.dim() != 2 or fb.stride(1) != 1 or not fb.is_cuda:
+            raise ValueError("fb must be a uint8 device tensor [n_chan][n_samp] with a contiguous time axis")
+        n_out = fb.shape[1] - self.max_delay
+        if out is None:
+            out = torch.empty((self.n_dm, max(n_out, 1)), dtype=torch.float32, device=fb.device)
+        if out.dtype != torch.float32 or out.dim() != 2 or out.stride(1) != 1:
+            raise ValueError("out must be a float32 [n_dm][>= n_out] view with unit column stride")
+        pl = SpdPlane(fb.data_ptr(), SPD_U8, 0, fb.shape[0], fb.shape[1], fb.stride(0), None, None)
+        _check(self._lib.spd_dedisperse(self._h, ctypes.byref(pl), out.data_ptr(), out.stride(0), _stream(stream)))
+        return out[:, :n_out]
+
+    def close(self):
+        if self._h:
+            self._lib.spd_dedisp_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class BatchPlan:

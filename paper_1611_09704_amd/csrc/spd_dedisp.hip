@@ -1,0 +1,370 @@
+// spd_dedisp.hip -- brute-force incoherent de-dispersion, the step before the
+// detection path (Sec. 1: detection runs on de-dispersed time series).
+//
+// A filterbank of 8-bit samples x[c][s] (channel 0 the highest frequency)
+// becomes one series per trial DM:
+//     y[d][t] = sum over c of x[c][t + delay(d, c)],  t < n_samp - max delay,
+// with delay(d, c) = floor(dm[d] * k_c + 0.5) and
+// k_c = KDM * (1/f_c^2 - 1/f_top^2) / t_samp, the cold-plasma delay law.  The
+// sums are of whole 8-bit counts, so they are exact in every form below and
+// the output (float) holds them exactly (below 2^24 for up to 65,793
+// channels).
+//
+// Kernel layout (gfx950).  A work-group owns 16 consecutive trials x 512
+// consecutive starts; each of its 4 waves owns 4 trials, and lane l the
+// starts t0 + l + 64k (k < 8).  Channels come in chunks of up to 16.  For
+// each channel of a chunk the group stages, in LDS, the entries
+//     P[e] = x[g + e] | x[g + e + 64] << 16,   g = (t0 + delay(d0, c)) & ~3,
+// so one 32-bit LDS read gives a lane two of its starts (t and t + 64) for a
+// trial, and one 32-bit integer add accumulates both: two 16-bit sums per
+// register, flushed into 32-bit totals every 256 channels (256 * 255 <
+// 65536).  Lanes read consecutive entries, so the reads are free of bank
+// conflicts; the trials' delays differ per channel by at most the span
+// staged.  Each add is two of the definition's additions, and the LDS read
+// per add is the binding resource.
+//
+// The delays are evaluated where they are used, in FP64, with the product and
+// the sum rounded separately (no fused multiply-add), the same way the host
+// evaluates them for the plan's maximum delay and span.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "spd_abi_internal.h"
+
+namespace spd {
+namespace {
+
+constexpr double kKdm = 4.148808e3;          // MHz^2 pc^-1 cm^3 s
+constexpr int kDdWaves = 4;
+constexpr int kDdDmPerWave = 4;
+constexpr int kDdDms = kDdWaves * kDdDmPerWave;   // trials per work-group
+constexpr int kDdOut = 512;                       // starts per work-group
+constexpr int kDdFlush = 256;                     // channels per 16-bit partial sum
+constexpr int kDdMaxChunk = 16;                   // channels per LDS chunk (<= 256 / kDdDms)
+constexpr size_t kDdLdsMax = 65536;
+
+struct DedispArgs {
+    const uint8_t* fb;
+    int64_t stride, n_samp;
+    const double* dm;
+    const double* kc;
+    float* out;
+    int64_t out_stride, n_out;
+    int32_t n_chan, n_dm, n_dm_tiles, entries, chunk;
+};
+
+// floor(dm * k + 0.5) with the product and the sum each rounded to FP64.
+__host__ __device__ inline int32_t dd_delay(double dm, double k)
+{
+#pragma clang fp contract(off)
+    const double p = dm * k;
+    return (int32_t)floor(p + 0.5);
+}
+
+// Four bytes of a channel row from byte g on (g a multiple of 4); bytes at or
+// beyond n_samp read as zero.
+__device__ inline uint32_t dd_load4(const uint8_t* row, int64_t g, int64_t n_samp)
+{
+    if (g + 3 < n_samp) return *(const uint32_t*)(row + g);
+    uint32_t v = 0;
+    for (int i = 0; i < 4; ++i)
+        if (g + i < n_samp) v |= (uint32_t)row[g + i] << (8 * i);
+    return v;
+}
+
+__global__ __launch_bounds__(64 * kDdWaves) void dedisp_u8_kernel(DedispArgs a)
+{
+    extern __shared__ __align__(16) uint32_t dd_smem[];
+    uint32_t* P = dd_smem;                                   // [chunk][entries]
+    int32_t* dl = (int32_t*)(P + a.chunk * a.entries);       // [chunk][16] delay - first trial's delay
+    int32_t* base = dl + a.chunk * kDdDms;                   // [chunk] first trial's delay
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t t0 = (int64_t)(blockIdx.x / (uint32_t)a.n_dm_tiles) * kDdOut;
+    const int d0 = (int)(blockIdx.x % (uint32_t)a.n_dm_tiles) * kDdDms;
+
+    uint32_t part[kDdDmPerWave][4];
+    uint32_t tot[kDdDmPerWave][8];
+#pragma unroll
+    for (int j = 0; j < kDdDmPerWave; ++j) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part[j][i] = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) tot[j][k] = 0;
+    }
+    int since = 0;
+    const int nq = a.entries / 4;
+    for (int c0 = 0; c0 < a.n_chan; c0 += a.chunk) {
+        const int ncc = min(a.chunk, a.n_chan - c0);
+        __syncthreads();                                     // the previous chunk is consumed
+        if (tid < ncc * kDdDms) {
+            const int cc = tid / kDdDms, j = tid % kDdDms;
+            const double k = a.kc[c0 + cc];
+            const int32_t db = dd_delay(a.dm[d0], k);
+            dl[tid] = dd_delay(a.dm[min(d0 + j, a.n_dm - 1)], k) - db;
+            if (j == 0) base[cc] = db;
+        }
+        __syncthreads();
+        // wave w stages channels w, w + 4, ...; lane l the entries 4q..4q+3, q = l, l + 64, ...
+        for (int cc = wv; cc < ncc; cc += kDdWaves) {
+            const uint8_t* row = a.fb + (int64_t)(c0 + cc) * a.stride;
+            const int64_t g0 = (t0 + base[cc]) & ~(int64_t)3;
+            uint32_t* pc = P + cc * a.entries;
+            for (int q = lane; q < nq; q += 64) {
+                const int64_t g = g0 + 4 * q;
+                const uint32_t A = dd_load4(row, g, a.n_samp), B = dd_load4(row, g + 64, a.n_samp);
+                uint4 v;
+                v.x = (A & 0xffu) | ((B & 0xffu) << 16);
+                v.y = ((A >> 8) & 0xffu) | (((B >> 8) & 0xffu) << 16);
+                v.z = ((A >> 16) & 0xffu) | (((B >> 16) & 0xffu) << 16);
+                v.w = (A >> 24) | ((B >> 24) << 16);
+                *(uint4*)(pc + 4 * q) = v;
+            }
+        }
+        __syncthreads();
+        // Per lane, one of this wave's 64 (channel, trial) delays and one
+        // channel's entry offset; the loop takes them as scalars (readlane),
+        // so every LDS access below is one of the accumulating reads.
+        const int32_t my_dl = (lane >> 2) < ncc ? dl[(lane >> 2) * kDdDms + wv * kDdDmPerWave + (lane & 3)] : 0;
+        const int32_t my_off = lane < ncc ? lane * a.entries + (int)((t0 + base[lane]) & 3) : 0;
+        for (int cc = 0; cc < ncc; ++cc) {
+            const int32_t off_c = __builtin_amdgcn_readlane(my_off, cc);
+            uint32_t v[kDdDmPerWave][4];                     // all reads of the channel in flight at once
+#pragma unroll
+            for (int j = 0; j < kDdDmPerWave; ++j) {
+                const uint32_t* q = P + off_c + __builtin_amdgcn_readlane(my_dl, cc * kDdDmPerWave + j) + lane;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[j][i] = q[128 * i];
+            }
+#pragma unroll
+            for (int j = 0; j < kDdDmPerWave; ++j) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) part[j][i] += v[j][i];
+            }
+        }
+        since += ncc;
+        if (since + a.chunk > kDdFlush || c0 + a.chunk >= a.n_chan) {
+#pragma unroll
+            for (int j = 0; j < kDdDmPerWave; ++j) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    tot[j][2 * i] += part[j][i] & 0xffffu;
+                    tot[j][2 * i + 1] += part[j][i] >> 16;
+                    part[j][i] = 0;
+                }
+            }
+            since = 0;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kDdDmPerWave; ++j) {
+        const int d = d0 + wv * kDdDmPerWave + j;
+        if (d >= a.n_dm) continue;
+        float* orow = a.out + (int64_t)d * a.out_stride;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t t = t0 + lane + 64 * k;
+            if (t < a.n_out) orow[t] = (float)tot[j][k];
+        }
+    }
+}
+
+}  // namespace
+}  // namespace spd
+
+using namespace spd;
+
+struct spd_dedisp_plan {
+    spd_band band;
+    int32_t n_dm;
+    std::vector<double> dm, kc;
+    double* d_dm = nullptr;
+    double* d_kc = nullptr;
+    int32_t max_delay = 0, span = 0, entries = 0, chunk = 0;
+    int device = 0;
+};
+
+extern "C" {
+
+}  // extern "C"
+
+namespace {
+
+// Validation shared by the plan and the host delay table; fills k_c.
+spd_status dd_prepare(const spd_band* band, const double* dm, int32_t n_dm, std::vector<double>& kc,
+                      int32_t* max_delay)
+{
+    if (!band || !dm) return fail(SPD_E_INVALID, "band and dm are required");
+    const spd_band b = *band;
+    if (b.n_chan < 1 || b.n_chan > SPD_MAX_CHANNELS) return fail(SPD_E_INVALID, "n_chan must lie in [1, %d]", SPD_MAX_CHANNELS);
+    if (!(b.f_top_mhz > 0.0) || !(b.chan_bw_mhz > 0.0) || !(b.t_samp_s > 0.0) || !isfinite(b.f_top_mhz) ||
+        !isfinite(b.chan_bw_mhz) || !isfinite(b.t_samp_s))
+        return fail(SPD_E_INVALID, "f_top_mhz, chan_bw_mhz and t_samp_s must be finite and > 0");
+    if (!(b.f_top_mhz - (double)(b.n_chan - 1) * b.chan_bw_mhz > 0.0))
+        return fail(SPD_E_INVALID, "the lowest channel frequency must be > 0");
+    if (n_dm < 1 || n_dm > SPD_MAX_DM_TRIALS) return fail(SPD_E_INVALID, "n_dm must lie in [1, %d]", SPD_MAX_DM_TRIALS);
+    for (int32_t d = 0; d < n_dm; ++d) {
+        if (!isfinite(dm[d]) || dm[d] < 0.0) return fail(SPD_E_INVALID, "dm[%d] must be finite and >= 0", d);
+        if (d && dm[d] < dm[d - 1]) return fail(SPD_E_INVALID, "dm must be non-decreasing (dm[%d] < dm[%d])", d, d - 1);
+    }
+    kc.resize(b.n_chan);
+    for (int32_t c = 0; c < b.n_chan; ++c) {
+        const double f = b.f_top_mhz - (double)c * b.chan_bw_mhz, ft = b.f_top_mhz;
+        kc[c] = kKdm * (1.0 / (f * f) - 1.0 / (ft * ft)) / b.t_samp_s;
+    }
+    // the delays grow with the trial and towards the last channel
+    const double p = dm[n_dm - 1] * kc[b.n_chan - 1];
+    if (!(p < (double)SPD_MAX_DELAY)) return fail(SPD_E_UNSUPPORTED, "largest delay exceeds %d samples", SPD_MAX_DELAY);
+    *max_delay = dd_delay(dm[n_dm - 1], kc[b.n_chan - 1]);
+    return SPD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+spd_status spd_dedisp_delay_table(const spd_band* band, const double* dm, int32_t n_dm, int32_t* delays,
+                                  int32_t* max_delay)
+{
+    clear_error();
+    std::vector<double> kc;
+    int32_t md = 0;
+    spd_status st = dd_prepare(band, dm, n_dm, kc, &md);
+    if (st) return st;
+    if (max_delay) *max_delay = md;
+    if (delays)
+        for (int32_t d = 0; d < n_dm; ++d)
+            for (int32_t c = 0; c < band->n_chan; ++c) delays[(int64_t)d * band->n_chan + c] = dd_delay(dm[d], kc[c]);
+    return SPD_OK;
+}
+
+spd_status spd_dedisp_plan_create(const spd_band* band, const double* dm, int32_t n_dm, spd_dedisp_plan** plan)
+{
+    clear_error();
+    if (!plan) return fail(SPD_E_INVALID, "plan is required");
+    *plan = nullptr;
+    std::vector<double> kc;
+    int32_t md = 0;
+    spd_status st = dd_prepare(band, dm, n_dm, kc, &md);
+    if (st) return st;
+    spd_dedisp_plan* P = new (std::nothrow) spd_dedisp_plan;
+    if (!P) return fail(SPD_E_NOMEM, "host allocation");
+    const spd_band b = *band;
+    P->band = b;
+    P->n_dm = n_dm;
+    P->dm.assign(dm, dm + n_dm);
+    P->kc = kc;
+    P->max_delay = md;
+    int32_t span = 0;
+    for (int32_t d0 = 0; d0 < n_dm; d0 += kDdDms) {
+        const int32_t d1 = d0 + kDdDms - 1 < n_dm - 1 ? d0 + kDdDms - 1 : n_dm - 1;
+        for (int32_t c = 0; c < b.n_chan; ++c) {
+            const int32_t s = dd_delay(P->dm[d1], P->kc[c]) - dd_delay(P->dm[d0], P->kc[c]);
+            span = s > span ? s : span;
+        }
+    }
+    P->span = span;
+    // entries per channel: the largest index read is 3 + 63 + 384 + span
+    P->entries = (451 + span + 3) & ~3;
+    const size_t per_chan = (size_t)P->entries * 4 + kDdDms * 4 + 4;
+    P->chunk = 0;
+    for (int cc = kDdMaxChunk; cc >= 1; cc >>= 1)
+        if ((size_t)cc * per_chan <= kDdLdsMax) { P->chunk = cc; break; }
+    if (!P->chunk) {
+        delete P;
+        return fail(SPD_E_UNSUPPORTED, "trials 16 apart differ by %d samples of delay; at most about %d fit the LDS",
+                    span, (int)(kDdLdsMax / 4) - 460);
+    }
+    hipError_t e = hipGetDevice(&P->device);
+    if (e == hipSuccess) e = hipMalloc((void**)&P->d_dm, sizeof(double) * n_dm);
+    if (e == hipSuccess) e = hipMalloc((void**)&P->d_kc, sizeof(double) * b.n_chan);
+    if (e == hipSuccess) e = hipMemcpy(P->d_dm, P->dm.data(), sizeof(double) * n_dm, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(P->d_kc, P->kc.data(), sizeof(double) * b.n_chan, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (P->d_dm) (void)hipFree(P->d_dm);
+        if (P->d_kc) (void)hipFree(P->d_kc);
+        delete P;
+        return device_status(e, "de-dispersion plan tables");
+    }
+    *plan = P;
+    return SPD_OK;
+}
+
+void spd_dedisp_plan_destroy(spd_dedisp_plan* plan)
+{
+    if (!plan) return;
+    if (plan->d_dm) (void)hipFree(plan->d_dm);
+    if (plan->d_kc) (void)hipFree(plan->d_kc);
+    delete plan;
+}
+
+spd_status spd_dedisp_describe(const spd_dedisp_plan* plan, int32_t* max_delay, int32_t* span16)
+{
+    clear_error();
+    if (!plan) return fail(SPD_E_INVALID, "plan is required");
+    if (max_delay) *max_delay = plan->max_delay;
+    if (span16) *span16 = plan->span;
+    return SPD_OK;
+}
+
+spd_status spd_dedisp_delays(const spd_dedisp_plan* plan, int32_t* delays)
+{
+    clear_error();
+    if (!plan || !delays) return fail(SPD_E_INVALID, "plan and delays are required");
+    const int32_t C = plan->band.n_chan;
+    for (int32_t d = 0; d < plan->n_dm; ++d)
+        for (int32_t c = 0; c < C; ++c) delays[(int64_t)d * C + c] = dd_delay(plan->dm[d], plan->kc[c]);
+    return SPD_OK;
+}
+
+spd_status spd_dedisperse(const spd_dedisp_plan* plan, const spd_plane* fb, float* out, int64_t out_stride,
+                          void* stream)
+{
+    clear_error();
+    if (!plan || !fb || !out) return fail(SPD_E_INVALID, "plan, fb and out are required");
+    if (!fb->data) return fail(SPD_E_INVALID, "fb->data is NULL");
+    if (fb->dtype != SPD_U8) return fail(SPD_E_UNSUPPORTED, "de-dispersion takes 8-bit filterbanks (SPD_U8)");
+    if (fb->row_scale || fb->row_zero) return fail(SPD_E_INVALID, "de-dispersion sums raw counts: no scale or zero");
+    if (fb->n_rows != plan->band.n_chan) return fail(SPD_E_INVALID, "fb has %lld rows, the plan %d channels",
+                                                     (long long)fb->n_rows, plan->band.n_chan);
+    if (fb->row_stride < fb->n_cols || fb->row_stride % 4 != 0 || ((uintptr_t)fb->data & 3))
+        return fail(SPD_E_INVALID, "fb rows must be 4-byte aligned: data and row_stride (>= n_cols) multiples of 4");
+    const int64_t n_out = fb->n_cols - plan->max_delay;
+    if (n_out < 1) return fail(SPD_E_INVALID, "n_cols %lld must exceed the largest delay %d", (long long)fb->n_cols,
+                               plan->max_delay);
+    if (out_stride < n_out) return fail(SPD_E_INVALID, "out_stride < n_out (%lld)", (long long)n_out);
+    int dev = 0;
+    hipError_t ge = hipGetDevice(&dev);
+    if (ge != hipSuccess) return device_status(ge, "hipGetDevice");
+    if (dev != plan->device) return fail(SPD_E_INVALID, "the plan was made on device %d, not %d", plan->device, dev);
+    const int64_t n_dm_tiles = (plan->n_dm + kDdDms - 1) / kDdDms;
+    const int64_t n_t_tiles = (n_out + kDdOut - 1) / kDdOut;
+    if ((uint64_t)(n_dm_tiles * n_t_tiles) * 64 * kDdWaves > kMaxGridItems)
+        return fail(SPD_E_UNSUPPORTED, "output too large for one launch");
+    DedispArgs a;
+    memset(&a, 0, sizeof a);
+    a.fb = (const uint8_t*)fb->data;
+    a.stride = fb->row_stride;
+    a.n_samp = fb->n_cols;
+    a.dm = plan->d_dm;
+    a.kc = plan->d_kc;
+    a.out = out;
+    a.out_stride = out_stride;
+    a.n_out = n_out;
+    a.n_chan = plan->band.n_chan;
+    a.n_dm = plan->n_dm;
+    a.n_dm_tiles = (int32_t)n_dm_tiles;
+    a.entries = plan->entries;
+    a.chunk = plan->chunk;
+    const size_t lds = (size_t)plan->chunk * ((size_t)plan->entries * 4 + kDdDms * 4 + 4);
+    hipLaunchKernelGGL(dedisp_u8_kernel, dim3((uint32_t)(n_dm_tiles * n_t_tiles)), dim3(64 * kDdWaves), lds,
+                       (hipStream_t)stream, a);
+    return device_status(hipGetLastError(), "de-dispersion launch");
+}
+
+}  // extern "C"

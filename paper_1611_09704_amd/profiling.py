@@ -26,9 +26,10 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 COPY_BYTES = 1 << 31          # calibration copy: reads and writes 2 GiB
-WORKLOADS = {"ska": None, "ska16": list(range(1, 17)), "dit": "dit", "cluster": "cluster"}
+WORKLOADS = {"ska": None, "ska16": list(range(1, 17)), "dit": "dit", "cluster": "cluster", "dedisp": "dedisp"}
 BOXCAR_SOURCES = ("spd_device.h", "spd_kernels.hip", "spd_kernels.h", "spd_internal.h")
 CLUSTER_SOURCES = ("spd_cluster.hip",)
+DEDISP_SOURCES = ("spd_dedisp.hip",)
 CLUSTER_RADII = (2, 256)     # DM rows, starts
 DIT_LEVELS = 4
 
@@ -54,6 +55,9 @@ def run(args):
     dst.copy_(src)                       # calibration dispatch
     torch.cuda.synchronize()
     del src, dst
+    if WORKLOADS[args.workload] == "dedisp":
+        run_dedisp(args, dev)
+        return
     cfg = synth.ska(device=dev, R=args.rows, L=args.cols)
     x = cfg["plane"].x
     dit = WORKLOADS[args.workload] == "dit"
@@ -84,6 +88,26 @@ def run(args):
                                                  ", %d peaks" % int(pcount.item()) if cluster else ""), flush=True)
 
 
+def run_dedisp(args, dev, n_chan=4096, n_dm=6000):
+    """The de-dispersion kernel alone on the benchmark's SKA-like filterbank
+    (4,096 channels x 2^20 samples, 6,000 trials one sample apart)."""
+    import numpy as np
+    import torch
+
+    from paper_1611_09704_amd import binding as B
+    from paper_1611_09704_amd import synth
+    band = (1550.0, 300.0 / n_chan, 64e-6)
+    f_low = band[0] - (n_chan - 1) * band[1]
+    dm = np.arange(n_dm) / (4.148808e3 * (1.0 / f_low ** 2 - 1.0 / band[0] ** 2) / band[2])
+    fb = synth.filterbank(n_chan, args.cols, seed=1611097060, device=dev)
+    plan = B.DedispPlan(n_chan, *band, dm)
+    y = torch.empty((n_dm, args.cols - plan.max_delay), dtype=torch.float32, device=dev)
+    for k in range(args.steps):
+        plan.run(fb, out=y)
+        torch.cuda.synchronize()
+        print("step %d done" % k, flush=True)
+
+
 def _csvs(d, suffix):
     return sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
 
@@ -96,7 +120,7 @@ def _short(name: str, with_args: bool = False) -> str:
         targs = "<" + name.split("(")[0].split("<", 1)[1]
     for key in ("batch_boxcar_win_grid_kernel", "batch_boxcar_grid_kernel", "batch_boxcar_kernel", "batch_msd_kernel",
                 "batch_finalize_kernel", "boxcar_dit_kernel", "boxcar_win_kernel", "boxcar_kernel", "msd_xy_kernel", "msd_x_kernel", "msd_finalize_kernel",
-                "select_kernel", "cluster_kernel",
+                "select_kernel", "cluster_kernel", "dedisp_u8_kernel",
                 "fill_i64_kernel"):
         if key in name:
             return key + targs
@@ -130,7 +154,7 @@ def summarize(args):
         total = sum(float(r["TotalDurationNs"]) for r in rows) or 1.0
         for row in rows:
             name = _short(row["Name"], with_args=True)
-            if not any(k in name for k in ("boxcar", "msd", "select", "finalize", "fill_i64", "cluster")):
+            if not any(k in name for k in ("boxcar", "msd", "select", "finalize", "fill_i64", "cluster", "dedisp")):
                 continue
             lines.append("| %s | %s | %.4f | %.3f | %.2f%% |" % (
                 name, row["Calls"], float(row["AverageNs"]) / 1e6, float(row["TotalDurationNs"]) / 1e6,
@@ -142,7 +166,7 @@ def summarize(args):
         meta = {}
         for row in csv.DictReader(open(traces[0])):
             name = _short(row["Kernel_Name"], with_args=True)
-            if not any(k in name for k in ("boxcar", "msd", "select", "finalize", "fill_i64", "cluster")):
+            if not any(k in name for k in ("boxcar", "msd", "select", "finalize", "fill_i64", "cluster", "dedisp")):
                 continue
             key = (name, int(row["Grid_Size_X"]))
             groups[key].append((int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e6)
@@ -173,7 +197,7 @@ def summarize(args):
         lines.append("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | read GB | written GB |")
         lines.append("|---|---|---|---|---|---|")
         for k in sorted(set(fc) | set(wc)):
-            if not any(s in k for s in ("boxcar", "msd", "select", "cluster")):
+            if not any(s in k for s in ("boxcar", "msd", "select", "cluster", "dedisp")):
                 continue
             f = fc.get(k, {}).get("FETCH_SIZE", [])
             w = wc.get(k, {}).get("WRITE_SIZE", [])
@@ -201,6 +225,8 @@ def summarize(args):
             d = {}
         if args.workload == "cluster":
             d["cluster"] = {"kernel_sha": kernel_source_sha(CLUSTER_SOURCES), **traffic.get("cluster_kernel", {})}
+        elif args.workload == "dedisp":
+            d["dedisp"] = {"kernel_sha": kernel_source_sha(DEDISP_SOURCES), **traffic.get("dedisp_u8_kernel", {})}
         else:
             box = (traffic.get("boxcar_dit_kernel") or traffic.get("boxcar_win_kernel")
                    or traffic.get("boxcar_kernel") or {})

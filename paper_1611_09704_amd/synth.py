@@ -273,3 +273,37 @@ def snr_plane(R: int, L: int, *, seed: int, n_bumps: int = 8, quantum: float = 0
     if quantum > 0:
         x = np.round(x / quantum) * quantum
     return x.astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Filterbanks (frequency channels x time) for the de-dispersion step.
+# ---------------------------------------------------------------------------
+
+def filterbank(C: int, S: int, *, seed: int, device="cpu", mean: float = 96.0, sigma: float = 16.0,
+               stride: Optional[int] = None) -> torch.Tensor:
+    """uint8 [C][S] noise filterbank (rows padded to ``stride`` bytes, a
+    multiple of 4, default the next one up from S): round(mean + sigma * z)
+    clamped to 0..255, z ~ N(0, 1) drawn with torch on ``device`` from a seed
+    taken from numpy's SeedSequence(seed).  Returns the [C][S] view."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed)))
+    g = torch.Generator(device=device)
+    g.manual_seed(int(rng.integers(0, 2 ** 62)))
+    stride = stride or (S + 3) // 4 * 4
+    buf = torch.empty((C, stride), dtype=torch.uint8, device=device)
+    for c0 in range(0, C, 256):                      # bounded float scratch
+        c1 = min(C, c0 + 256)
+        z = torch.randn((c1 - c0, S), generator=g, device=device, dtype=torch.float32)
+        buf[c0:c1, :S] = torch.clamp(torch.round(mean + sigma * z), 0, 255).to(torch.uint8)
+        buf[c0:c1, S:] = 0
+    return buf[:, :S]
+
+
+def inject_along(fb: torch.Tensor, delays_row, t0: int, width: int, amp: int) -> None:
+    """Add ``amp`` counts (saturating at 255) to fb[c][t0 + delays_row[c] + k]
+    for k < width: a pulse that reaches channel c after the given delay (the
+    caller supplies the delay curve)."""
+    d = torch.as_tensor(np.asarray(delays_row, dtype=np.int64), device=fb.device)
+    cols = t0 + d[:, None] + torch.arange(width, device=fb.device)[None, :]
+    rows = torch.arange(fb.shape[0], device=fb.device)[:, None].expand_as(cols)
+    v = fb[rows, cols].to(torch.int32) + int(amp)
+    fb[rows, cols] = torch.clamp(v, 0, 255).to(torch.uint8)

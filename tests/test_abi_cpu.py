@@ -161,6 +161,27 @@ def test_cluster_validation(lib):
         assert msg in _err(lib), (kw, _err(lib))
 
 
+def test_dedisp_delay_table_and_validation(lib):
+    import numpy as np
+    import oracle
+    for C, band, dm in [(256, (1550.0, 300 / 256, 64e-6), np.arange(40) * 0.5),
+                        (4096, (1550.0, 300 / 4096, 64e-6), np.arange(6000) * 0.0689),
+                        (7, (400.0, 10.0, 1e-3), [0, 1.5, 1.5, 800.25])]:
+        table, md = B.dedisp_delay_table(C, *band, dm)
+        want = oracle.dedisp_delays(dm, oracle.dedisp_channel_factors(C, *band))
+        assert np.array_equal(table, want) and md == want.max()
+    for args, msg in [((0, 1500.0, 1.0, 1e-4, [0.0]), "n_chan"), ((8, -1.0, 1.0, 1e-4, [0.0]), "finite"),
+                      ((8, 1500.0, 0.0, 1e-4, [0.0]), "finite"), ((8, 1500.0, 1.0, 0.0, [0.0]), "finite"),
+                      ((8, 10.0, 2.0, 1e-4, [0.0]), "lowest channel"), ((8, 1500.0, 1.0, 1e-4, []), "n_dm"),
+                      ((8, 1500.0, 1.0, 1e-4, [1.0, 0.5]), "non-decreasing"),
+                      ((8, 1500.0, 1.0, 1e-4, [-1.0]), ">= 0"), ((8, 1500.0, 1.0, 1e-4, [float("nan")]), "finite"),
+                      ((8, 1500.0, 100.0, 1e-9, [1e9]), "exceeds")]:
+        with pytest.raises(B.SpdError) as e:
+            B.dedisp_delay_table(*args)
+        assert msg in str(e.value), (args, str(e.value))
+    assert lib.spd_dedisperse(None, None, None, 0, None) == 1 and "required" in _err(lib)
+
+
 def test_batch_validation(lib):
     p = B.Params([1, 2, 4, 8], 5.0)
     out = ctypes.c_void_p(123)

@@ -1,0 +1,129 @@
+"""De-dispersion on the GPU (spd_dedisperse) against the oracle
+(oracle.dedisperse).  8-bit samples sum to whole numbers, so the outputs
+must be equal exactly, element by element:
+
+* small and ragged filterbanks, channel counts around the 16-channel LDS
+  chunks and the 256-channel flush of the 16-bit partial sums, trial counts
+  around the 16-trial work-group, padded rows, repeated and zero DMs, and a
+  coarse DM grid that needs a smaller channel chunk;
+* saturated input (every sample 255 over 4,096 channels), whose sums are
+  known in closed form;
+* the SKA-like filterbank (4,096 channels x 2^20 samples, 6,000 trials) in
+  the benchmark's launch configuration, checked on sampled trials over
+  column windows at the start, the middle and the ragged end;
+* end to end: a pulse laid along one trial's delay curve comes out of the
+  detection path at that trial and time.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1611_09704_amd import binding as B
+from paper_1611_09704_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def run(fb, band, dm, out_pad=0):
+    C, S = fb.shape
+    plan = B.DedispPlan(C, *band, dm)
+    n_out = S - plan.max_delay
+    buf = torch.full((len(dm), n_out + out_pad), -7.0, device=DEV)
+    y = plan.run(fb, out=buf)
+    torch.cuda.synchronize()
+    if out_pad:
+        assert torch.all(buf[:, n_out:] == -7.0), "wrote past n_out"
+    return plan, y
+
+
+def check(C, S, dm, band, seed, out_pad=0, stride=None):
+    print("case: dedisp C=%d S=%d n_dm=%d band=%s" % (C, S, len(dm), band), flush=True)
+    fb = synth.filterbank(C, S, seed=seed, device=DEV, stride=stride)
+    plan, y = run(fb, band, dm, out_pad)
+    kc = oracle.dedisp_channel_factors(C, *band)
+    want = oracle.dedisperse(fb.cpu().numpy(), dm, kc)
+    assert y.shape == want.shape
+    got = y.cpu().numpy().astype(np.float64)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, "first mismatch at %s: %g vs %g" % (bad[0], got[tuple(bad[0])], want[tuple(bad[0])])
+    return plan
+
+
+SKA_BAND = (1550.0, 300.0 / 4096, 64e-6)
+
+
+@pytest.mark.parametrize("C,S,n_dm,stride", [(1, 700, 1, None), (7, 1000, 5, None), (16, 2000, 16, 2048),
+                                             (17, 1500, 17, None), (64, 4096 + 13, 37, None),
+                                             (300, 3001, 20, 3008), (513, 2500, 33, None)])
+def test_matches_oracle(C, S, n_dm, stride):
+    band = (1500.0, 40.0 / C, 64e-6)
+    kc_max = oracle.dedisp_channel_factors(C, *band)[-1]
+    dm = np.linspace(0.0, 0.4 * S / max(kc_max, 1e-9), n_dm) if C > 1 else np.linspace(0, 50, n_dm)
+    check(C, S, dm, band, seed=100 + C, out_pad=3, stride=stride)
+
+
+def test_repeated_zero_and_coarse_dms():
+    band = (1400.0, 0.5, 1e-4)
+    kc = oracle.dedisp_channel_factors(96, *band)
+    check(96, 3000, [0.0, 0.0, 0.0], band, seed=7)
+    check(96, 3000, np.repeat(np.linspace(0, 200 / kc[-1], 9), 3), band, seed=8)
+    # trials 16 apart differ by ~1,100 samples at the bottom channel: a smaller channel chunk
+    plan = check(40, 9000, np.arange(40) * (70.0 / kc[:40][-1] if kc[39] > 0 else 1.0), (1400.0, 0.5, 1e-4), seed=9)
+    assert plan.span16 > 500
+
+
+def test_saturated_sums_exact():
+    C, S = 4096, 2048
+    band = SKA_BAND
+    kc = oracle.dedisp_channel_factors(C, *band)
+    dm = np.arange(20) / kc[-1]                                   # one sample per trial at the bottom
+    fb = torch.full((C, S), 255, dtype=torch.uint8, device=DEV)
+    plan, y = run(fb, band, dm)
+    assert plan.max_delay == 19
+    assert torch.all(y == 255.0 * C)                              # 1,044,480 in every output
+
+
+def test_full_size_sampled_trials():
+    C, S, n_dm = 4096, 1 << 20, 6000
+    kc = oracle.dedisp_channel_factors(C, *SKA_BAND)
+    dm = np.arange(n_dm) / kc[-1]
+    fb = synth.filterbank(C, S, seed=1611097050, device=DEV)
+    print("dedisp full: generated", flush=True)
+    plan = B.DedispPlan(C, *SKA_BAND, dm)
+    n_out = S - plan.max_delay
+    y = plan.run(fb)
+    torch.cuda.synchronize()
+    assert y.shape == (n_dm, n_out)
+    rng = np.random.default_rng(12)
+    trials = sorted({0, n_dm - 1, n_dm // 2} | set(rng.choice(n_dm, 3, replace=False).tolist()))
+    for ta in (0, n_out // 2 - 700, n_out - 1500):
+        w = min(1500, n_out - ta)
+        sub = fb[:, ta:ta + w + plan.max_delay].cpu().numpy()
+        want = oracle.dedisperse(sub, dm[trials], kc)[:, :w]
+        got = y[trials, ta:ta + w].cpu().numpy().astype(np.float64)
+        assert np.array_equal(got, want), "window at %d differs" % ta
+    print("dedisp full: n_out=%d max_delay=%d trials=%s ok" % (n_out, plan.max_delay, trials), flush=True)
+    del y, fb
+    torch.cuda.empty_cache()
+
+
+def test_end_to_end_pulse_recovered_by_detection():
+    C, S, n_dm = 512, 60000, 96
+    band = (1550.0, 300.0 / C, 64e-6)
+    kc = oracle.dedisp_channel_factors(C, *band)
+    dm = np.arange(n_dm) / kc[-1]
+    fb = synth.filterbank(C, S, seed=77, device=DEV)
+    delays = oracle.dedisp_delays(dm, kc)
+    k, t_p, width = 61, 20000, 12
+    synth.inject_along(fb, delays[k], t_p, width, 12)
+    plan, y = run(fb, band, dm)
+    res = B.detect(y.contiguous(), list(range(1, 33)), 7.0, sigma_mode="sqrtn")
+    torch.cuda.synchronize()
+    c = res["cands"]
+    assert len(c) > 0
+    best = c[np.argmax(c["snr"])]
+    assert abs(int(best["row"]) - k) <= 1 and abs(int(best["t"]) - t_p) <= width, best
+    print("dedisp e2e: best candidate row %d t %d snr %.1f width %d" % (best["row"], best["t"], best["snr"],
+                                                                        best["width"]), flush=True)
