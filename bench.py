@@ -683,7 +683,9 @@ def run_dedisp(args, dev, n_chan=4096, n_samp=1 << 20, n_dm=6000, n_pulses=40):
                    "detection": "msd_compute + boxcar_snr, AUTO sigma_N, threshold 7, candidates only"},
         "roofline": {"bound": "lds", "achieved": round(tadds, 3), "peak": round(LDS_PEAK_ADDS, 2),
                      "unit": "T adds/s", "frac": round(tadds / LDS_PEAK_ADDS, 4), "traffic": load_traffic("dedisp"),
-                     "kernel": "dedisp_u8_kernel", "work_per_launch": "%d additions (trials x channels x starts)" % adds},
+                     "kernel": "dedisp_u8_kernel" if os.environ.get("SPD_DEDISP_FORM") == "generic"
+                     else "dedisp_u8_pf_kernel",
+                     "work_per_launch": "%d additions (trials x channels x starts)" % adds},
         "end_to_end": out,
         "value_note": "value counts de-dispersed samples (trials x starts) per second through the whole step",
     }

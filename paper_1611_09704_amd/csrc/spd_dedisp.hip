@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <new>
@@ -78,6 +79,72 @@ __device__ inline uint32_t dd_load4(const uint8_t* row, int64_t g, int64_t n_sam
     return v;
 }
 
+// The chunk's accumulation: for each staged channel, the wave's 4 trials x
+// 4 entries per lane, all 16 reads in flight before the adds.  my_off (lane
+// cc < ncc) is channel cc's entry offset, my_dl (lane 4cc + j) trial j's
+// delay minus the group's first trial's; both are read as scalars.
+__device__ inline void dd_accumulate(const uint32_t* P, int ncc, int32_t my_off, int32_t my_dl, int lane,
+                                     uint32_t (&part)[kDdDmPerWave][4])
+{
+    for (int cc = 0; cc < ncc; ++cc) {
+        const int32_t off_c = __builtin_amdgcn_readlane(my_off, cc);
+        uint32_t v[kDdDmPerWave][4];
+#pragma unroll
+        for (int j = 0; j < kDdDmPerWave; ++j) {
+            const uint32_t* q = P + off_c + __builtin_amdgcn_readlane(my_dl, cc * kDdDmPerWave + j) + lane;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[j][i] = q[128 * i];
+        }
+#pragma unroll
+        for (int j = 0; j < kDdDmPerWave; ++j) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) part[j][i] += v[j][i];
+        }
+    }
+}
+
+// The 16-bit partial sums (fields: starts t and t + 64) into the 32-bit totals.
+__device__ inline void dd_flush(uint32_t (&part)[kDdDmPerWave][4], uint32_t (&tot)[kDdDmPerWave][8])
+{
+#pragma unroll
+    for (int j = 0; j < kDdDmPerWave; ++j) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            tot[j][2 * i] += part[j][i] & 0xffffu;
+            tot[j][2 * i + 1] += part[j][i] >> 16;
+            part[j][i] = 0;
+        }
+    }
+}
+
+__device__ inline void dd_store(const DedispArgs& a, int d0, int wv, int lane, int64_t t0,
+                                const uint32_t (&tot)[kDdDmPerWave][8])
+{
+#pragma unroll
+    for (int j = 0; j < kDdDmPerWave; ++j) {
+        const int d = d0 + wv * kDdDmPerWave + j;
+        if (d >= a.n_dm) continue;
+        float* orow = a.out + (int64_t)d * a.out_stride;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int64_t t = t0 + lane + 64 * k;
+            if (t < a.n_out) orow[t] = (float)tot[j][k];
+        }
+    }
+}
+
+// Entries 4q..4q+3 of a channel from the bytes A = x[g..g+3], B = x[g+64..g+67].
+__device__ inline uint4 dd_pack(uint32_t A, uint32_t B)
+{
+    uint4 v;
+    v.x = (A & 0xffu) | ((B & 0xffu) << 16);
+    v.y = ((A >> 8) & 0xffu) | (((B >> 8) & 0xffu) << 16);
+    v.z = ((A >> 16) & 0xffu) | (((B >> 16) & 0xffu) << 16);
+    v.w = (A >> 24) | ((B >> 24) << 16);
+    return v;
+}
+
+// Any chunk size and span: delays through LDS, staging between barriers.
 __global__ __launch_bounds__(64 * kDdWaves) void dedisp_u8_kernel(DedispArgs a)
 {
     extern __shared__ __align__(16) uint32_t dd_smem[];
@@ -88,15 +155,8 @@ __global__ __launch_bounds__(64 * kDdWaves) void dedisp_u8_kernel(DedispArgs a)
     const int64_t t0 = (int64_t)(blockIdx.x / (uint32_t)a.n_dm_tiles) * kDdOut;
     const int d0 = (int)(blockIdx.x % (uint32_t)a.n_dm_tiles) * kDdDms;
 
-    uint32_t part[kDdDmPerWave][4];
-    uint32_t tot[kDdDmPerWave][8];
-#pragma unroll
-    for (int j = 0; j < kDdDmPerWave; ++j) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) part[j][i] = 0;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) tot[j][k] = 0;
-    }
+    uint32_t part[kDdDmPerWave][4] = {};
+    uint32_t tot[kDdDmPerWave][8] = {};
     int since = 0;
     const int nq = a.entries / 4;
     for (int c0 = 0; c0 < a.n_chan; c0 += a.chunk) {
@@ -115,63 +175,104 @@ __global__ __launch_bounds__(64 * kDdWaves) void dedisp_u8_kernel(DedispArgs a)
             const uint8_t* row = a.fb + (int64_t)(c0 + cc) * a.stride;
             const int64_t g0 = (t0 + base[cc]) & ~(int64_t)3;
             uint32_t* pc = P + cc * a.entries;
-            for (int q = lane; q < nq; q += 64) {
-                const int64_t g = g0 + 4 * q;
-                const uint32_t A = dd_load4(row, g, a.n_samp), B = dd_load4(row, g + 64, a.n_samp);
-                uint4 v;
-                v.x = (A & 0xffu) | ((B & 0xffu) << 16);
-                v.y = ((A >> 8) & 0xffu) | (((B >> 8) & 0xffu) << 16);
-                v.z = ((A >> 16) & 0xffu) | (((B >> 16) & 0xffu) << 16);
-                v.w = (A >> 24) | ((B >> 24) << 16);
-                *(uint4*)(pc + 4 * q) = v;
-            }
+            for (int q = lane; q < nq; q += 64)
+                *(uint4*)(pc + 4 * q) = dd_pack(dd_load4(row, g0 + 4 * q, a.n_samp),
+                                               dd_load4(row, g0 + 4 * q + 64, a.n_samp));
         }
         __syncthreads();
-        // Per lane, one of this wave's 64 (channel, trial) delays and one
-        // channel's entry offset; the loop takes them as scalars (readlane),
-        // so every LDS access below is one of the accumulating reads.
         const int32_t my_dl = (lane >> 2) < ncc ? dl[(lane >> 2) * kDdDms + wv * kDdDmPerWave + (lane & 3)] : 0;
         const int32_t my_off = lane < ncc ? lane * a.entries + (int)((t0 + base[lane]) & 3) : 0;
-        for (int cc = 0; cc < ncc; ++cc) {
-            const int32_t off_c = __builtin_amdgcn_readlane(my_off, cc);
-            uint32_t v[kDdDmPerWave][4];                     // all reads of the channel in flight at once
-#pragma unroll
-            for (int j = 0; j < kDdDmPerWave; ++j) {
-                const uint32_t* q = P + off_c + __builtin_amdgcn_readlane(my_dl, cc * kDdDmPerWave + j) + lane;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) v[j][i] = q[128 * i];
-            }
-#pragma unroll
-            for (int j = 0; j < kDdDmPerWave; ++j) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) part[j][i] += v[j][i];
-            }
-        }
+        dd_accumulate(P, ncc, my_off, my_dl, lane, part);
         since += ncc;
         if (since + a.chunk > kDdFlush || c0 + a.chunk >= a.n_chan) {
-#pragma unroll
-            for (int j = 0; j < kDdDmPerWave; ++j) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    tot[j][2 * i] += part[j][i] & 0xffffu;
-                    tot[j][2 * i + 1] += part[j][i] >> 16;
-                    part[j][i] = 0;
-                }
-            }
+            dd_flush(part, tot);
             since = 0;
         }
     }
+    dd_store(a, d0, wv, lane, t0, tot);
+}
+
+// The common case (16-channel chunks, at most 512 entries per channel): the
+// next chunk's bytes are loaded into registers before the current chunk is
+// accumulated, so the global-load latency hides behind the LDS work, and the
+// delays are evaluated per lane instead of through LDS.
+constexpr int kPfRounds = 2;                                  // q = lane, lane + 64
+constexpr int kPfChan = kDdMaxChunk / kDdWaves;               // channels staged per wave
+
+__global__ __launch_bounds__(64 * kDdWaves) void dedisp_u8_pf_kernel(DedispArgs a)
+{
+    extern __shared__ __align__(16) uint32_t dd_smem[];
+    uint32_t* P = dd_smem;                                   // [16][entries]
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t t0 = (int64_t)(blockIdx.x / (uint32_t)a.n_dm_tiles) * kDdOut;
+    const int d0 = (int)(blockIdx.x % (uint32_t)a.n_dm_tiles) * kDdDms;
+    const int nq = a.entries / 4;
+    const double dm0 = a.dm[d0];
+    const double dmj = a.dm[min(d0 + wv * kDdDmPerWave + (lane & 3), a.n_dm - 1)];
+
+    uint32_t A[kPfChan][kPfRounds], B[kPfChan][kPfRounds];
+    // loads of chunk c0's bytes for the channels this wave stages
+    auto fetch = [&](int c0) {
 #pragma unroll
-    for (int j = 0; j < kDdDmPerWave; ++j) {
-        const int d = d0 + wv * kDdDmPerWave + j;
-        if (d >= a.n_dm) continue;
-        float* orow = a.out + (int64_t)d * a.out_stride;
+        for (int m = 0; m < kPfChan; ++m) {
+            const int c = min(c0 + wv + kDdWaves * m, a.n_chan - 1);
+            const uint8_t* row = a.fb + (int64_t)c * a.stride;
+            const int64_t g0 = (t0 + dd_delay(dm0, a.kc[c])) & ~(int64_t)3;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int64_t t = t0 + lane + 64 * k;
-            if (t < a.n_out) orow[t] = (float)tot[j][k];
+            for (int r = 0; r < kPfRounds; ++r) {
+                const int q = min(lane + 64 * r, nq - 1);
+                A[m][r] = dd_load4(row, g0 + 4 * q, a.n_samp);
+                B[m][r] = dd_load4(row, g0 + 4 * q + 64, a.n_samp);
+            }
+        }
+    };
+    auto store = [&](int ncc) {
+#pragma unroll
+        for (int m = 0; m < kPfChan; ++m) {
+            const int cc = wv + kDdWaves * m;
+#pragma unroll
+            for (int r = 0; r < kPfRounds; ++r) {
+                const int q = lane + 64 * r;
+                if (cc < ncc && q < nq) *(uint4*)(P + cc * a.entries + 4 * q) = dd_pack(A[m][r], B[m][r]);
+            }
+        }
+    };
+
+    uint32_t part[kDdDmPerWave][4] = {};
+    uint32_t tot[kDdDmPerWave][8] = {};
+    int since = 0;
+    fetch(0);
+    store(min(kDdMaxChunk, a.n_chan));
+    __syncthreads();
+    for (int c0 = 0; c0 < a.n_chan; c0 += kDdMaxChunk) {
+        const int ncc = min(kDdMaxChunk, a.n_chan - c0);
+        const double kd = a.kc[min(c0 + (lane >> 2), a.n_chan - 1)];
+        const double ko = a.kc[min(c0 + lane, a.n_chan - 1)];
+        const int32_t my_dl = dd_delay(dmj, kd) - dd_delay(dm0, kd);
+        const int32_t my_off = lane * a.entries + (int)((t0 + dd_delay(dm0, ko)) & 3);
+        const bool more = c0 + kDdMaxChunk < a.n_chan;
+        if (more) fetch(c0 + kDdMaxChunk);
+        dd_accumulate(P, ncc, my_off, my_dl, lane, part);
+        since += ncc;
+        if (since + kDdMaxChunk > kDdFlush || !more) {
+            dd_flush(part, tot);
+            since = 0;
+        }
+        if (more) {
+            __syncthreads();                                 // every wave is done with this chunk
+            store(min(kDdMaxChunk, a.n_chan - c0 - kDdMaxChunk));
+            __syncthreads();
         }
     }
+    dd_store(a, d0, wv, lane, t0, tot);
+}
+
+// SPD_DEDISP_FORM=generic selects the chunk-by-chunk kernel for any plan
+// (the two kernels give identical sums).
+bool dd_force_generic()
+{
+    const char* e = getenv("SPD_DEDISP_FORM");
+    return e && strcmp(e, "generic") == 0;
 }
 
 }  // namespace
@@ -361,9 +462,13 @@ spd_status spd_dedisperse(const spd_dedisp_plan* plan, const spd_plane* fb, floa
     a.n_dm_tiles = (int32_t)n_dm_tiles;
     a.entries = plan->entries;
     a.chunk = plan->chunk;
-    const size_t lds = (size_t)plan->chunk * ((size_t)plan->entries * 4 + kDdDms * 4 + 4);
-    hipLaunchKernelGGL(dedisp_u8_kernel, dim3((uint32_t)(n_dm_tiles * n_t_tiles)), dim3(64 * kDdWaves), lds,
-                       (hipStream_t)stream, a);
+    const dim3 grid((uint32_t)(n_dm_tiles * n_t_tiles));
+    if (plan->chunk == kDdMaxChunk && plan->entries <= 4 * 64 * kPfRounds && !dd_force_generic())
+        hipLaunchKernelGGL(dedisp_u8_pf_kernel, grid, dim3(64 * kDdWaves),
+                           (size_t)kDdMaxChunk * plan->entries * 4, (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(dedisp_u8_kernel, grid, dim3(64 * kDdWaves),
+                           (size_t)plan->chunk * ((size_t)plan->entries * 4 + kDdDms * 4 + 4), (hipStream_t)stream, a);
     return device_status(hipGetLastError(), "de-dispersion launch");
 }
 
