@@ -684,7 +684,7 @@ def run_dedisp(args, dev, n_chan=4096, n_samp=1 << 20, n_dm=6000, n_pulses=40):
         "roofline": {"bound": "lds", "achieved": round(tadds, 3), "peak": round(LDS_PEAK_ADDS, 2),
                      "unit": "T adds/s", "frac": round(tadds / LDS_PEAK_ADDS, 4), "traffic": load_traffic("dedisp"),
                      "kernel": "dedisp_u8_kernel" if os.environ.get("SPD_DEDISP_FORM") == "generic"
-                     else "dedisp_u8_pf_kernel",
+                     else "dedisp_u8_wide_kernel",
                      "work_per_launch": "%d additions (trials x channels x starts)" % adds},
         "end_to_end": out,
         "value_note": "value counts de-dispersed samples (trials x starts) per second through the whole step",
@@ -692,8 +692,8 @@ def run_dedisp(args, dev, n_chan=4096, n_samp=1 << 20, n_dm=6000, n_pulses=40):
     if not args.no_cpu_baseline:
         import oracle
         kc = oracle.dedisp_channel_factors(n_chan, *band)
-        trials = np.linspace(0, n_dm - 1, 4).astype(np.int64)
-        wcols = 20000
+        trials = np.linspace(0, n_dm - 1, 8).astype(np.int64)
+        wcols = 400000
         sub = fb[:, :wcols + plan.max_delay].cpu().numpy()
         t0 = time.perf_counter()
         oracle.dedisperse(sub, dm[trials], kc)

@@ -12,16 +12,19 @@
 //
 // Kernel layout (gfx950).  A work-group owns 16 consecutive trials x 512
 // consecutive starts; each of its 4 waves owns 4 trials, and lane l the
-// starts t0 + l + 64k (k < 8).  Channels come in chunks of up to 16.  For
-// each channel of a chunk the group stages, in LDS, the entries
-//     P[e] = x[g + e] | x[g + e + 64] << 16,   g = (t0 + delay(d0, c)) & ~3,
-// so one 32-bit LDS read gives a lane two of its starts (t and t + 64) for a
-// trial, and one 32-bit integer add accumulates both: two 16-bit sums per
-// register, flushed into 32-bit totals every 256 channels (256 * 255 <
-// 65536).  Lanes read consecutive entries, so the reads are free of bank
-// conflicts; the trials' delays differ per channel by at most the span
-// staged.  Each add is two of the definition's additions, and the LDS read
-// per add is the binding resource.
+// starts t0 + l + 64k (k < 8).  Channels come in chunks of up to 16, staged
+// in LDS relative to g = (t0 + delay of the group's first trial) & ~3:
+//  * wide layout (dedisp_u8_wide_kernel, the common case): entry e is 16
+//    bytes holding x[g + e + 64k], k < 8, as 16-bit fields, so one 16-byte
+//    LDS read gives a lane all 8 of its starts for a trial; the next chunk's
+//    bytes are loaded into registers while the current one accumulates;
+//  * narrow layout (dedisp_u8_kernel, any span of delays): entry e is 4
+//    bytes holding x[g + e] and x[g + e + 64]; staging between barriers.
+// Either way one 32-bit integer add accumulates two starts as 16-bit fields,
+// flushed into 32-bit totals every 256 channels (256 * 255 < 65536).  Lanes
+// read consecutive entries, so the reads are free of bank conflicts.  Each
+// 4 bytes read from LDS carry two of the definition's additions, and the LDS
+// read bandwidth is the binding resource.
 //
 // The delays are evaluated where they are used, in FP64, with the product and
 // the sum rounded separately (no fused multiply-add), the same way the host
@@ -58,6 +61,8 @@ struct DedispArgs {
     float* out;
     int64_t out_stride, n_out;
     int32_t n_chan, n_dm, n_dm_tiles, entries, chunk;
+    int32_t groups;          // wide layout: groups of 4 entries staged per channel
+    int32_t max_delay;
 };
 
 // floor(dm * k + 0.5) with the product and the sum each rounded to FP64.
@@ -192,49 +197,94 @@ __global__ __launch_bounds__(64 * kDdWaves) void dedisp_u8_kernel(DedispArgs a)
     dd_store(a, d0, wv, lane, t0, tot);
 }
 
-// The common case (16-channel chunks, at most 512 entries per channel): the
-// next chunk's bytes are loaded into registers before the current chunk is
-// accumulated, so the global-load latency hides behind the LDS work, and the
-// delays are evaluated per lane instead of through LDS.
-constexpr int kPfRounds = 2;                                  // q = lane, lane + 64
-constexpr int kPfChan = kDdMaxChunk / kDdWaves;               // channels staged per wave
+// ---------------------------------------------------------------------------
+// Wide layout: entry e of a channel is 16 bytes holding x[g + e + 64k] for
+// k < 8 as 16-bit fields (k = 2p, 2p+1 in dword p), so one 16-byte LDS read
+// gives a lane all 8 of its starts for a trial, and the 4 dwords add into
+// the same partial sums as above.  A channel needs 67 + span entries.
+// ---------------------------------------------------------------------------
+constexpr int kWideRounds = 2;              // staging items per thread per chunk (prefetching kernel)
 
-__global__ __launch_bounds__(64 * kDdWaves) void dedisp_u8_pf_kernel(DedispArgs a)
+// Entries 4m..4m+3 of a channel (dst = entry 4m) from D[k] = x[g + 4m + 64k
+// .. +3], k < 8.  Entry 4m + b, dword p, is byte b of D[2p] | byte b of
+// D[2p+1] << 16: one v_perm_b32 (selector bytes 0-3 pick from its second
+// operand, 4-7 from its first, 0x0c gives zero).  The four 16-byte writes go
+// out in the order b = (i + item/4) mod 4, i = 0..3, so that in each write
+// instruction 16 consecutive items (lanes) hit 16 different 16-byte bank
+// groups instead of four.
+__device__ inline void dd_pack_wide(const uint32_t (&D)[8], int item, uint4* dst)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t b = (uint32_t)(i + (item >> 2)) & 3u;
+        const uint32_t sel = 0x0c040c00u + b * 0x00010001u;
+        dst[b] = make_uint4(__builtin_amdgcn_perm(D[1], D[0], sel), __builtin_amdgcn_perm(D[3], D[2], sel),
+                            __builtin_amdgcn_perm(D[5], D[4], sel), __builtin_amdgcn_perm(D[7], D[6], sel));
+    }
+}
+
+__device__ inline void dd_load_group(const uint8_t* row, int64_t g, int64_t n_samp, bool interior, uint32_t (&D)[8])
+{
+    if (interior) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) D[k] = *(const uint32_t*)(row + g + 64 * k);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) D[k] = dd_load4(row, g + 64 * k, n_samp);
+    }
+}
+
+__device__ inline void dd_accumulate_wide(const uint4* P4, int ncc, int32_t my_off, int32_t my_dl, int lane,
+                                          uint32_t (&part)[kDdDmPerWave][4])
+{
+    for (int cc = 0; cc < ncc; ++cc) {
+        const int32_t off_c = __builtin_amdgcn_readlane(my_off, cc);
+        uint4 v[kDdDmPerWave];
+#pragma unroll
+        for (int j = 0; j < kDdDmPerWave; ++j)
+            v[j] = P4[off_c + __builtin_amdgcn_readlane(my_dl, cc * kDdDmPerWave + j) + lane];
+#pragma unroll
+        for (int j = 0; j < kDdDmPerWave; ++j) {
+            part[j][0] += v[j].x;
+            part[j][1] += v[j].y;
+            part[j][2] += v[j].z;
+            part[j][3] += v[j].w;
+        }
+    }
+}
+
+// Wide layout, next chunk prefetched into registers (16-channel chunks, at
+// most 2 * 256 staging groups per chunk).
+__global__ __launch_bounds__(64 * kDdWaves) void dedisp_u8_wide_kernel(DedispArgs a)
 {
     extern __shared__ __align__(16) uint32_t dd_smem[];
-    uint32_t* P = dd_smem;                                   // [16][entries]
+    uint4* P4 = (uint4*)dd_smem;                             // [16][4 * groups]
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t t0 = (int64_t)(blockIdx.x / (uint32_t)a.n_dm_tiles) * kDdOut;
     const int d0 = (int)(blockIdx.x % (uint32_t)a.n_dm_tiles) * kDdDms;
-    const int nq = a.entries / 4;
+    const int G = a.groups, E4 = 4 * a.groups;
     const double dm0 = a.dm[d0];
     const double dmj = a.dm[min(d0 + wv * kDdDmPerWave + (lane & 3), a.n_dm - 1)];
+    // every byte this group stages lies inside the rows (the last tiles take the checked loads)
+    const bool interior = t0 + a.max_delay + 4 * G + 64 * 8 <= a.n_samp;
 
-    uint32_t A[kPfChan][kPfRounds], B[kPfChan][kPfRounds];
-    // loads of chunk c0's bytes for the channels this wave stages
+    uint32_t D[kWideRounds][8];
     auto fetch = [&](int c0) {
 #pragma unroll
-        for (int m = 0; m < kPfChan; ++m) {
-            const int c = min(c0 + wv + kDdWaves * m, a.n_chan - 1);
-            const uint8_t* row = a.fb + (int64_t)c * a.stride;
-            const int64_t g0 = (t0 + dd_delay(dm0, a.kc[c])) & ~(int64_t)3;
-#pragma unroll
-            for (int r = 0; r < kPfRounds; ++r) {
-                const int q = min(lane + 64 * r, nq - 1);
-                A[m][r] = dd_load4(row, g0 + 4 * q, a.n_samp);
-                B[m][r] = dd_load4(row, g0 + 4 * q + 64, a.n_samp);
-            }
+        for (int r = 0; r < kWideRounds; ++r) {
+            const int item = min(tid + 64 * kDdWaves * r, kDdMaxChunk * G - 1);
+            const int cc = item / G, m = item - cc * G;
+            const int c = min(c0 + cc, a.n_chan - 1);
+            const int64_t g = ((t0 + dd_delay(dm0, a.kc[c])) & ~(int64_t)3) + 4 * m;
+            dd_load_group(a.fb + (int64_t)c * a.stride, g, a.n_samp, interior, D[r]);
         }
     };
     auto store = [&](int ncc) {
 #pragma unroll
-        for (int m = 0; m < kPfChan; ++m) {
-            const int cc = wv + kDdWaves * m;
-#pragma unroll
-            for (int r = 0; r < kPfRounds; ++r) {
-                const int q = lane + 64 * r;
-                if (cc < ncc && q < nq) *(uint4*)(P + cc * a.entries + 4 * q) = dd_pack(A[m][r], B[m][r]);
-            }
+        for (int r = 0; r < kWideRounds; ++r) {
+            const int item = tid + 64 * kDdWaves * r;
+            const int cc = item / G, m = item - cc * G;
+            if (cc < ncc) dd_pack_wide(D[r], item, P4 + cc * E4 + 4 * m);
         }
     };
 
@@ -249,17 +299,17 @@ __global__ __launch_bounds__(64 * kDdWaves) void dedisp_u8_pf_kernel(DedispArgs 
         const double kd = a.kc[min(c0 + (lane >> 2), a.n_chan - 1)];
         const double ko = a.kc[min(c0 + lane, a.n_chan - 1)];
         const int32_t my_dl = dd_delay(dmj, kd) - dd_delay(dm0, kd);
-        const int32_t my_off = lane * a.entries + (int)((t0 + dd_delay(dm0, ko)) & 3);
+        const int32_t my_off = lane * E4 + (int)((t0 + dd_delay(dm0, ko)) & 3);
         const bool more = c0 + kDdMaxChunk < a.n_chan;
         if (more) fetch(c0 + kDdMaxChunk);
-        dd_accumulate(P, ncc, my_off, my_dl, lane, part);
+        dd_accumulate_wide(P4, ncc, my_off, my_dl, lane, part);
         since += ncc;
         if (since + kDdMaxChunk > kDdFlush || !more) {
             dd_flush(part, tot);
             since = 0;
         }
         if (more) {
-            __syncthreads();                                 // every wave is done with this chunk
+            __syncthreads();
             store(min(kDdMaxChunk, a.n_chan - c0 - kDdMaxChunk));
             __syncthreads();
         }
@@ -267,8 +317,8 @@ __global__ __launch_bounds__(64 * kDdWaves) void dedisp_u8_pf_kernel(DedispArgs 
     dd_store(a, d0, wv, lane, t0, tot);
 }
 
-// SPD_DEDISP_FORM=generic selects the chunk-by-chunk kernel for any plan
-// (the two kernels give identical sums).
+// SPD_DEDISP_FORM=generic selects the chunk-by-chunk kernel for any plan (the
+// two kernels give identical sums).
 bool dd_force_generic()
 {
     const char* e = getenv("SPD_DEDISP_FORM");
@@ -286,7 +336,7 @@ struct spd_dedisp_plan {
     std::vector<double> dm, kc;
     double* d_dm = nullptr;
     double* d_kc = nullptr;
-    int32_t max_delay = 0, span = 0, entries = 0, chunk = 0;
+    int32_t max_delay = 0, span = 0, entries = 0, chunk = 0, groups = 0;
     int device = 0;
 };
 
@@ -376,6 +426,8 @@ spd_status spd_dedisp_plan_create(const spd_band* band, const double* dm, int32_
     P->chunk = 0;
     for (int cc = kDdMaxChunk; cc >= 1; cc >>= 1)
         if ((size_t)cc * per_chan <= kDdLdsMax) { P->chunk = cc; break; }
+    // wide layout: the largest entry read is 3 + 63 + span
+    P->groups = (67 + span + 3) / 4;
     if (!P->chunk) {
         delete P;
         return fail(SPD_E_UNSUPPORTED, "trials 16 apart differ by %d samples of delay; at most about %d fit the LDS",
@@ -462,10 +514,12 @@ spd_status spd_dedisperse(const spd_dedisp_plan* plan, const spd_plane* fb, floa
     a.n_dm_tiles = (int32_t)n_dm_tiles;
     a.entries = plan->entries;
     a.chunk = plan->chunk;
+    a.groups = plan->groups;
+    a.max_delay = plan->max_delay;
     const dim3 grid((uint32_t)(n_dm_tiles * n_t_tiles));
-    if (plan->chunk == kDdMaxChunk && plan->entries <= 4 * 64 * kPfRounds && !dd_force_generic())
-        hipLaunchKernelGGL(dedisp_u8_pf_kernel, grid, dim3(64 * kDdWaves),
-                           (size_t)kDdMaxChunk * plan->entries * 4, (hipStream_t)stream, a);
+    const size_t wide_lds = (size_t)kDdMaxChunk * plan->groups * 64;
+    if (!dd_force_generic() && kDdMaxChunk * plan->groups <= 64 * kDdWaves * kWideRounds && wide_lds <= kDdLdsMax)
+        hipLaunchKernelGGL(dedisp_u8_wide_kernel, grid, dim3(64 * kDdWaves), wide_lds, (hipStream_t)stream, a);
     else
         hipLaunchKernelGGL(dedisp_u8_kernel, grid, dim3(64 * kDdWaves),
                            (size_t)plan->chunk * ((size_t)plan->entries * 4 + kDdDms * 4 + 4), (hipStream_t)stream, a);

@@ -120,7 +120,7 @@ def _short(name: str, with_args: bool = False) -> str:
         targs = "<" + name.split("(")[0].split("<", 1)[1]
     for key in ("batch_boxcar_win_grid_kernel", "batch_boxcar_grid_kernel", "batch_boxcar_kernel", "batch_msd_kernel",
                 "batch_finalize_kernel", "boxcar_dit_kernel", "boxcar_win_kernel", "boxcar_kernel", "msd_xy_kernel", "msd_x_kernel", "msd_finalize_kernel",
-                "select_kernel", "cluster_kernel", "dedisp_u8_pf_kernel", "dedisp_u8_kernel",
+                "select_kernel", "cluster_kernel", "dedisp_u8_wide_kernel", "dedisp_u8_kernel",
                 "fill_i64_kernel"):
         if key in name:
             return key + targs
@@ -227,7 +227,7 @@ def summarize(args):
             d["cluster"] = {"kernel_sha": kernel_source_sha(CLUSTER_SOURCES), **traffic.get("cluster_kernel", {})}
         elif args.workload == "dedisp":
             d["dedisp"] = {"kernel_sha": kernel_source_sha(DEDISP_SOURCES),
-                           **(traffic.get("dedisp_u8_pf_kernel") or traffic.get("dedisp_u8_kernel") or {})}
+                           **(traffic.get("dedisp_u8_wide_kernel") or traffic.get("dedisp_u8_kernel") or {})}
         else:
             box = (traffic.get("boxcar_dit_kernel") or traffic.get("boxcar_win_kernel")
                    or traffic.get("boxcar_kernel") or {})

@@ -129,21 +129,21 @@ def test_end_to_end_pulse_recovered_by_detection():
                                                                         best["width"]), flush=True)
 
 
-def test_generic_and_prefetching_kernels_agree():
-    """SPD_DEDISP_FORM=generic forces the chunk-by-chunk kernel; the default
-    (16-channel chunks, small span) prefetches the next chunk into registers.
-    Both must give the same sums, and the oracle's."""
+def test_kernel_forms_agree():
+    """The default kernel (16-byte entries holding 8 starts, next chunk
+    prefetched) and SPD_DEDISP_FORM=generic (4-byte entries, chunk by chunk
+    between barriers) must give the same sums, and the oracle's."""
     import os
     for C, S, n_dm in [(48, 5000, 40), (1030, 3000, 19)]:
         band = (1500.0, 100.0 / C, 64e-6)
         kc = oracle.dedisp_channel_factors(C, *band)
         dm = np.arange(n_dm) / kc[-1]
         fb = synth.filterbank(C, S, seed=300 + C, device=DEV)
-        _, y_pf = run(fb, band, dm)
+        _, y_default = run(fb, band, dm)
         os.environ["SPD_DEDISP_FORM"] = "generic"
         try:
-            _, y_gen = run(fb, band, dm)
+            _, y = run(fb, band, dm)
         finally:
             del os.environ["SPD_DEDISP_FORM"]
-        assert torch.equal(y_pf, y_gen)
-        assert np.array_equal(y_pf.cpu().numpy().astype(np.float64), oracle.dedisperse(fb.cpu().numpy(), dm, kc))
+        assert torch.equal(y_default, y)
+        assert np.array_equal(y_default.cpu().numpy().astype(np.float64), oracle.dedisperse(fb.cpu().numpy(), dm, kc))
