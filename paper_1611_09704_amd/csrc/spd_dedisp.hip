@@ -7,8 +7,8 @@
 // with delay(d, c) = floor(dm[d] * k_c + 0.5) and
 // k_c = KDM * (1/f_c^2 - 1/f_top^2) / t_samp, the cold-plasma delay law.  The
 // sums are of whole 8-bit counts, so they are exact in every form below and
-// the output (float) holds them exactly (below 2^24 for up to 65,793
-// channels).
+// the output (float) holds them exactly (below 2^24 for the up to 65,536
+// channels a plan accepts).
 //
 // Kernel layout (gfx950).  A work-group owns 16 consecutive trials x 512
 // consecutive starts; each of its 4 waves owns 4 trials, and lane l the
