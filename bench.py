@@ -344,6 +344,7 @@ def run_batch(args, dev):
     table = plan.tune_table()
     plan.close()
     tops = evals * OPS_PER_EVAL / t_batch / 1e12
+    small = batch_small_beams(args, dev, B, synth)
     return {
         "metric": METRIC, "value": round(samples / t_batch / 1e9, 3), "unit": "GSamples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_batch * 1e3, 3),
@@ -358,7 +359,60 @@ def run_batch(args, dev):
                            "ms_per_step": round(t_plain * 1e3, 3)},
         "speedup_vs_plain": round(t_plain / t_batch, 4),
         "schedule": info, "autotune_table": table, "plan_create_s": round(t_create, 3), "n_candidates": n_cand,
+        "small_beams": small,
     }
+
+
+def batch_small_beams(args, dev, B, synth, n_beams=256, rows=64, cols=32768, wmax=32):
+    """Where batching pays: many small beams (256 x 64 rows x 32,768 samples,
+    widths 1..32), whose per-beam launches cost more than their work.  The
+    batched plan (one graph replay per step) against per-beam plain launches
+    of the same kernels; both must find the same number of candidates."""
+    import torch
+    cfg = synth.batch(device=dev, shapes=[(rows, cols)] * n_beams, seed=1611097070, pulses_per_beam=2, wmax=wmax)
+    planes = [pl.x for pl in cfg["planes"]]
+    p = B.Params(cfg["widths"], cfg["threshold"])
+    cand = B.new_candidates(1 << 20, dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    stats = [torch.empty((x.shape[0], B.STATS_FIELDS), dtype=torch.float64, device=dev) for x in planes]
+    wss = [torch.empty(B.workspace_bytes(x, p), dtype=torch.uint8, device=dev) for x in planes]
+
+    def plain_step():
+        total = 0
+        for x, st, ws in zip(planes, stats, wss):
+            B.msd_compute(x, p, stats=st, workspace=ws, stream=stream)
+            B.boxcar_snr(x, p, st, cand=cand, cand_count=count, stream=stream)
+            total += int(count.item()) if plain_step.count_it else 0
+        return total
+
+    plain_step.count_it = True
+    n_plain = plain_step()
+    plain_step.count_it = False
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain_step()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / args.steps
+    plan = B.BatchPlan(planes, p, autotune=True)
+    for _ in range(max(1, args.warmup)):
+        plan.run(cand, count, use_graph=True, stream=stream)
+    torch.cuda.synchronize()
+    n_batch = int(count.item())
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run(cand, count, use_graph=True, stream=stream)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    plan.close()
+    if n_batch != n_plain:
+        raise RuntimeError("batched and per-beam candidate counts differ (%d vs %d)" % (n_batch, n_plain))
+    samples = n_beams * rows * cols
+    return {"beams": n_beams, "shape": [rows, cols], "widths": "1..%d" % wmax, "n_candidates": n_batch,
+            "batched": {"GSamples/s": round(samples / t_batch / 1e9, 3), "ms_per_step": round(t_batch * 1e3, 3)},
+            "plain_per_beam": {"GSamples/s": round(samples / t_plain / 1e9, 3), "ms_per_step": round(t_plain * 1e3, 3)},
+            "speedup_vs_plain": round(t_plain / t_batch, 3)}
 
 
 def run_dit(args, dev, levels=4):
