@@ -454,6 +454,21 @@ size_t spd_server_device_bytes(const spd_server_config* cfg, const spd_params* p
  * be any mode (the widest-boxcar statistics are streamed as well).         */
 spd_status spd_server_create(const spd_server_config* cfg, const spd_params* p, spd_server** server);
 
+/* A server with the de-dispersion step in front: each beam streams 8-bit
+ * filterbank chunks (cfg->dtype = SPD_U8, cfg->n_rows = the plan's channels,
+ * chunk_cols new samples each, chunk_cols > the plan's largest delay plus the
+ * widest boxcar; widest boxcar >= 4).  Per beam the server also keeps the
+ * last max-delay filterbank columns (rounded up to 4) on the device,
+ * de-disperses [filterbank halo | chunk] as spd_dedisperse does into the
+ * beam's DM-trial x time plane (the plan's n_dm rows) and runs the detection
+ * stream above on it.  Chunk 0 yields chunk_cols - max_delay new starts,
+ * chunk k >= 1 chunk_cols starting at global start k*chunk_cols - max_delay;
+ * results' t_offset and candidates' t use that global start, rows are trial
+ * indices.  The plan must stay alive until the server is destroyed and
+ * belong to the current device.                                            */
+spd_status spd_server_create_dedisp(const spd_server_config* cfg, const spd_params* p, const spd_dedisp_plan* plan,
+                                    spd_server** server);
+
 /* Queue chunk `seq` of `beam` ([host] n_rows x chunk_cols elements of the
  * configured dtype, pinned memory recommended).  seq must be the beam's next
  * chunk number (0, 1, 2, ...).  The buffer must stay valid and unchanged

@@ -137,6 +137,8 @@ def load():
         lib.spd_server_device_bytes.argtypes = [P(SpdServerConfig), P(SpdParams)]
         lib.spd_server_device_bytes.restype = ctypes.c_size_t
         lib.spd_server_create.argtypes = [P(SpdServerConfig), P(SpdParams), P(vp)]
+        lib.spd_server_create_dedisp.argtypes = [P(SpdServerConfig), P(SpdParams), vp, P(vp)]
+        lib.spd_server_create_dedisp.restype = ctypes.c_int
         lib.spd_server_create.restype = ctypes.c_int
         lib.spd_server_submit.argtypes = [vp, i32, i64, vp, ctypes.c_double]
         lib.spd_server_submit.restype = ctypes.c_int
@@ -552,17 +554,28 @@ class Server:
     carried halo and running statistics; results are polled as they finish."""
 
     def __init__(self, n_beams: int, n_rows: int, chunk_cols: int, params: Params, dtype=torch.float16,
-                 cand_capacity: int = 1 << 16, slots_per_beam: int = 2, hbm_budget_bytes: int = 0):
+                 cand_capacity: int = 1 << 16, slots_per_beam: int = 2, hbm_budget_bytes: int = 0,
+                 dedisp: Optional["DedispPlan"] = None):
+        """With ``dedisp`` (a DedispPlan, kept alive by the server) the beams
+        stream uint8 filterbank chunks [n_chan][chunk_cols], de-dispersed on
+        the device in front of the detection stream."""
         lib = load()
-        dt = {torch.float32: SPD_F32, torch.float16: SPD_F16}[dtype]
+        if dedisp is not None:
+            dtype = torch.uint8
+        dt = {torch.float32: SPD_F32, torch.float16: SPD_F16, torch.uint8: SPD_U8}[dtype]
         self.params = params
+        self.dedisp = dedisp
         self.cfg = SpdServerConfig(n_beams, dt, n_rows, chunk_cols, cand_capacity, slots_per_beam, 0,
                                    hbm_budget_bytes)
         self.cap = cand_capacity
         self._buf = np.empty(cand_capacity, dtype=CANDIDATE_DTYPE)
         self._keep = {}
         h = ctypes.c_void_p()
-        _check(lib.spd_server_create(ctypes.byref(self.cfg), ctypes.byref(params.c), ctypes.byref(h)))
+        if dedisp is None:
+            _check(lib.spd_server_create(ctypes.byref(self.cfg), ctypes.byref(params.c), ctypes.byref(h)))
+        else:
+            _check(lib.spd_server_create_dedisp(ctypes.byref(self.cfg), ctypes.byref(params.c), dedisp._h,
+                                                ctypes.byref(h)))
         self._h = h
 
     def device_bytes(self) -> int:

@@ -41,5 +41,6 @@ spd_status enqueue_boxcar(const spd_plane* x, const spd_row_stats* stats, const 
                           int64_t rows, hipStream_t s);
 spd_plane row_slice(const spd_plane* x, int64_t r0, int64_t rows);
 spd_status detect_events(hipEvent_t** out);
+void dedisp_plan_shape(const spd_dedisp_plan* plan, int32_t* n_chan, int32_t* n_dm, int32_t* max_delay, int* device);
 
 }  // namespace spd

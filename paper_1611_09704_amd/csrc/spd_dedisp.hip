@@ -448,6 +448,22 @@ spd_status spd_dedisp_plan_create(const spd_band* band, const double* dm, int32_
     return SPD_OK;
 }
 
+}  // extern "C"
+
+namespace spd {
+
+void dedisp_plan_shape(const spd_dedisp_plan* plan, int32_t* n_chan, int32_t* n_dm, int32_t* max_delay, int* device)
+{
+    *n_chan = plan->band.n_chan;
+    *n_dm = plan->n_dm;
+    *max_delay = plan->max_delay;
+    *device = plan->device;
+}
+
+}  // namespace spd
+
+extern "C" {
+
 void spd_dedisp_plan_destroy(spd_dedisp_plan* plan)
 {
     if (!plan) return;

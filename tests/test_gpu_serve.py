@@ -143,3 +143,59 @@ def test_server_full_size_chunks_sampled_rows():
             cs = c[np.isin(c["row"], rows)]
             C.check_candidates(cs, oc, 7.0, lambda row, t: snr[rows.index(row), t - toff])
         print("beam %d rows %s ok" % (b, rows), flush=True)
+
+
+def test_server_with_dedisp_matches_streaming_oracle():
+    """Beams stream 8-bit filterbank chunks; the server de-disperses them with
+    a carried filterbank halo in front of the detection stream.  Per chunk,
+    the candidates must match the streaming oracle run over the oracle's
+    de-dispersion of the whole series, cut where the server cuts it (chunk 0:
+    chunk_cols - max_delay starts, then chunk_cols each)."""
+    C_ch, Lc, K, nb = 32, 3000, 4, 2
+    band = (1500.0, 40.0 / C_ch, 64e-6)
+    kc = oracle.dedisp_channel_factors(C_ch, *band)
+    n_dm = 10
+    dm = np.arange(n_dm) * (15.0 / kc[-1])                   # 15 samples of delay per trial at the bottom
+    W, thr = list(range(1, 33)), 6.0
+    H = W[-1] - 1
+    plan = B.DedispPlan(C_ch, *band, dm)
+    md = plan.max_delay
+    assert md % 4 != 0                                        # the view after chunk 0 starts early
+    delays = oracle.dedisp_delays(dm, kc)
+    rng = np.random.default_rng(31)
+    fulls, chunks = [], []
+    for b in range(nb):
+        fb = synth.filterbank(C_ch, K * Lc, seed=500 + b, device="cuda")
+        for k in range(1, K):                                 # pulses whose de-dispersed start straddles a cut
+            trial = int(rng.integers(0, n_dm))
+            synth.inject_along(fb, delays[trial], k * Lc - md - 5, 12, 25)
+        fulls.append(fb.cpu().numpy())
+        chunks.append([fb[:, k * Lc:(k + 1) * Lc].contiguous().cpu().pin_memory() for k in range(K)])
+    srv = B.Server(nb, C_ch, Lc, B.Params(W, thr), cand_capacity=8192, dedisp=plan)
+    for k in range(K):
+        for b in range(nb):
+            srv.submit(b, k, chunks[b][k])
+    results = _drain(srv, nb * K)
+    srv.close()
+    by = {(r["beam"], r["seq"]): (r, c) for r, c in results}
+    for b in range(nb):
+        y = oracle.dedisperse(fulls[b], dm, kc)
+        assert y.shape[1] == K * Lc - md
+        state, prev = None, None
+        n_found = 0
+        for k in range(K):
+            s0 = 0 if k == 0 else k * Lc - md
+            seg = y[:, s0:(k + 1) * Lc - md]
+            if k == 0:
+                view, ncb, toff = seg, 0, 0
+            else:
+                view, ncb, toff = np.concatenate([prev[:, -H:], seg], axis=1), H, s0 - H
+            state, st, snr, widx = oracle.stream_step(view, W, new_col_begin=ncb, state=state, sigma_mode="sqrtn")
+            oc = oracle.select(snr, widx, W, thr, t_offset=toff)
+            r, c = by[(b, k)]
+            assert r["status"] == 0 and r["t_offset"] == toff, (b, k, r["t_offset"], toff)
+            C.check_candidates(c, oc, thr, lambda row, t: snr[row, t - toff])
+            n_found += len(c)
+            prev = np.concatenate([prev, seg], axis=1) if prev is not None else seg
+        assert n_found > 0
+    print("serve dedisp: beams=%d chunks=%d max_delay=%d ok" % (nb, K, md), flush=True)
