@@ -199,3 +199,36 @@ def test_server_with_dedisp_matches_streaming_oracle():
             prev = np.concatenate([prev, seg], axis=1) if prev is not None else seg
         assert n_found > 0
     print("serve dedisp: beams=%d chunks=%d max_delay=%d ok" % (nb, K, md), flush=True)
+
+
+def test_server_with_dedisp_same_alone_and_in_a_mix():
+    """A filterbank beam gives the same candidates, bit for bit, served alone
+    and served beside another beam (whose chunks interleave with its own)."""
+    C_ch, Lc, K = 24, 2500, 3
+    band = (1450.0, 30.0 / C_ch, 64e-6)
+    kc = oracle.dedisp_channel_factors(C_ch, *band)
+    dm = np.arange(8) * (9.0 / kc[-1])
+    W = list(range(1, 17))
+    plan = B.DedispPlan(C_ch, *band, dm)
+    delays = oracle.dedisp_delays(dm, kc)
+    streams = []
+    for b in range(2):
+        fb = synth.filterbank(C_ch, K * Lc, seed=700 + b, device="cuda")
+        synth.inject_along(fb, delays[3 + b], Lc - plan.max_delay - 3, 8, 30)
+        streams.append([fb[:, k * Lc:(k + 1) * Lc].contiguous().cpu().pin_memory() for k in range(K)])
+
+    def serve(beams):
+        srv = B.Server(len(beams), C_ch, Lc, B.Params(W, 6.0), cand_capacity=4096, dedisp=plan)
+        for k in range(K):
+            for i, b in enumerate(beams):
+                srv.submit(i, k, streams[b][k])
+        got = _drain(srv, len(beams) * K)
+        srv.close()
+        return {(beams[r["beam"]], r["seq"]): sorted((int(c["row"]), int(c["t"]), int(c["width"]), float(c["snr"]))
+                                                   for c in cs) for r, cs in got}
+
+    alone = serve([0])
+    mix = serve([1, 0])
+    for k in range(K):
+        assert alone[(0, k)] == mix[(0, k)], "chunk %d differs" % k
+    assert sum(len(v) for v in alone.values()) > 0
