@@ -54,7 +54,8 @@ def oracle_set(plane, thr, dr, dt):
 
 @pytest.mark.parametrize("R,L,pad", [(7, 3000, 0), (1, 1, 0), (3, 5, 2), (2, 63, 1), (2, 65, 0), (40, 777, 3),
                                      (5, 4096 + 17, 0)])
-@pytest.mark.parametrize("dr,dt", [(0, 0), (1, 3), (2, 64), (0, 300), (5, 1), (3, 1000), (1, 40), (0, 31), (1, 33)])
+@pytest.mark.parametrize("dr,dt", [(0, 0), (1, 3), (2, 64), (0, 300), (5, 1), (3, 1000), (1, 40), (0, 31), (1, 33),
+                                   (4096, 1 << 20)])
 def test_peaks_equal_oracle_on_seeded_planes(R, L, pad, dr, dt):
     print("case: cluster plane %dx%d pad=%d radii=(%d,%d)" % (R, L, pad, dr, dt), flush=True)
     plane = synth.snr_plane(R, L, seed=1000 + R * 7 + L, n_bumps=max(1, R * L // 2000), n_plateaus=2)
@@ -72,6 +73,8 @@ def test_peaks_equal_oracle_on_seeded_planes(R, L, pad, dr, dt):
         assert c["width"] == 1 and c["beam"] == 0 and c["snr"] == plane[c["row"], c["t"]]
     if dr == 0 and dt == 0:
         assert n == n_c
+    if dr >= R and dt >= L and n_c:                           # the whole plane is every window: one peak
+        assert n == 1
     print("cluster: candidates=%d peaks=%d" % (n_c, n), flush=True)
 
 

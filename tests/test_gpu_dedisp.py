@@ -83,6 +83,21 @@ def test_saturated_sums_exact():
     plan, y = run(fb, band, dm)
     assert plan.max_delay == 19
     assert torch.all(y == 255.0 * C)                              # 1,044,480 in every output
+    # the most channels a plan takes: sums up to 65,536 * 255 = 16,711,680, still exact in FP32
+    C = 65536
+    band = (1550.0, 300.0 / C, 64e-6)
+    kc = oracle.dedisp_channel_factors(C, *band)
+    fb = torch.full((C, 700), 255, dtype=torch.uint8, device=DEV)
+    fb[7, 3] = 0                                                  # one sample below full scale
+    dm = np.array([0.0, 1.0 / kc[-1], 2.0 / kc[-1]])
+    plan, y = run(fb, band, dm)
+    assert plan.max_delay == 2
+    want = torch.full_like(y, 255.0 * C)
+    d = oracle.dedisp_delays(dm, kc)[:, 7]
+    for j in range(3):
+        if 3 - d[j] < y.shape[1] and 3 - d[j] >= 0:
+            want[j, 3 - d[j]] -= 255.0
+    assert torch.equal(y, want)
 
 
 def test_full_size_sampled_trials():
