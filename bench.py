@@ -270,11 +270,11 @@ def main():
             oracle.stream_step(x64, W, sigma_mode="auto", kappa=1.0, nthreads=cores)
             return time.perf_counter() - t0
 
-        # a short pilot sizes the sample to about 10 s of oracle work
+        # a short pilot sizes the sample to 10-20 s of oracle work
         nrows = max(2, min(R, cores))
         dt = oracle_rows(nrows)
         if dt < 5.0:
-            nrows = int(min(R, max(nrows, nrows * 10.0 / max(dt, 1e-3))))
+            nrows = int(min(R, max(nrows, nrows * 14.0 / max(dt, 1e-3))))
             dt = oracle_rows(nrows)
         out["cpu_baseline"] = {"value": round(nrows * L / dt / 1e9, 5), "unit": "GSamples/s", "cores": cores,
                                "kind": "oracle",
