@@ -142,7 +142,7 @@ def read_counters(d):
 
 
 def summarize(args):
-    sha = kernel_source_sha()
+    sha = kernel_source_sha({"cluster": CLUSTER_SOURCES, "dedisp": DEDISP_SOURCES}.get(args.workload, BOXCAR_SOURCES))
     lines = []
     stats = _csvs(args.trace, "kernel_stats.csv") if args.trace else []
     if stats:
@@ -224,9 +224,9 @@ def summarize(args):
         except (OSError, ValueError):
             d = {}
         if args.workload == "cluster":
-            d["cluster"] = {"kernel_sha": kernel_source_sha(CLUSTER_SOURCES), **traffic.get("cluster_kernel", {})}
+            d["cluster"] = {"kernel_sha": sha, **traffic.get("cluster_kernel", {})}
         elif args.workload == "dedisp":
-            d["dedisp"] = {"kernel_sha": kernel_source_sha(DEDISP_SOURCES),
+            d["dedisp"] = {"kernel_sha": sha,
                            **(traffic.get("dedisp_u8_wide_kernel") or traffic.get("dedisp_u8_kernel") or {})}
         else:
             box = (traffic.get("boxcar_dit_kernel") or traffic.get("boxcar_win_kernel")
