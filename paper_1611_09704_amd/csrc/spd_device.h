@@ -335,11 +335,14 @@ __device__ void msd_block_xy(const PlaneArg& pl, bool vec, int64_t r, int64_t b,
         const bool x_whole = u0 >= xlo && u0 + TSW <= c1;
         const bool y_whole = u0 + TSW <= yhi;
         float carry = 0.f;
-        // one row of 256 samples: raw statistics (edge sub-tiles), then its share of the prefix E
+        float xb[16];                                       // the lane's raw samples of rows 0..3
+        auto keep = [&](int j, float4 v) {
+            xb[4 * j] = v.x; xb[4 * j + 1] = v.y; xb[4 * j + 2] = v.z; xb[4 * j + 3] = v.w;
+        };
+        // one row of 256 samples: its share of the prefix E (no branches, so the
+        // scans of neighbouring rows can interleave)
         auto row = [&](int m, float4 v) {
             const int p = 256 * m + 4 * lane;
-            const int64_t c = u0 + p;
-            if (p < TSW && !x_whole) msd_add4_clipped(sx, v, c, xlo, u1);
             const float l0 = v.x, l1 = l0 + v.y, l2 = l1 + v.z, l3 = l2 + v.w;
             const float inc = wave_inclusive_scan(l3);
             const float ex = (inc - l3) + carry;
@@ -357,39 +360,63 @@ __device__ void msd_block_xy(const PlaneArg& pl, bool vec, int64_t r, int64_t b,
                 for (int j = 0; j < 4; ++j) {
                     v[j].x -= K; v[j].y -= K; v[j].z -= K; v[j].w -= K;
                 }
-                if (m0 == 0 && x_whole) {                       // rows 0..3 are the sub-tile's raw samples
-                    const float b[16] = {v[0].x, v[0].y, v[0].z, v[0].w, v[1].x, v[1].y, v[1].z, v[1].w,
-                                         v[2].x, v[2].y, v[2].z, v[2].w, v[3].x, v[3].y, v[3].z, v[3].w};
-                    msd_add16(sx, b);
+                if (m0 == 0) {                                  // rows 0..3 hold the sub-tile's raw samples
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) keep(j, v[j]);
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     if (m0 + j < nrow) row(m0 + j, v[j]);
             }
         } else {
-            float b[16];
-            for (int m = 0; m < nrow; ++m) {
+#pragma unroll
+            for (int m = 0; m < TSW / 256; ++m) {               // nrow > TSW / 256 for every nmax >= 1
                 const float4 v = load4_shifted<DT>(ld, u0 + 256 * m + 4 * lane, pl.n_cols, vec, K, 0.f);
-                if (m < TSW / 256) {
-                    b[4 * m] = v.x; b[4 * m + 1] = v.y; b[4 * m + 2] = v.z; b[4 * m + 3] = v.w;
-                }
+                keep(m, v);
                 row(m, v);
             }
-            if (x_whole) msd_add16(sx, b);
+            for (int m = TSW / 256; m < nrow; ++m)
+                row(m, load4_shifted<DT>(ld, u0 + 256 * m + 4 * lane, pl.n_cols, vec, K, 0.f));
+        }
+        // raw statistics: one batch of 16 per lane, or group by group at the edges
+        if (x_whole) {
+            msd_add16(sx, xb);
+        } else {
+#pragma unroll
+            for (int m = 0; m < TSW / 256; ++m)
+                msd_add4_clipped(sx, make_float4(xb[4 * m], xb[4 * m + 1], xb[4 * m + 2], xb[4 * m + 3]),
+                                 u0 + 256 * m + 4 * lane, xlo, u1);
         }
         wave_sync();
+        // widest-boxcar values y(t) = E[t+nmax] - E[t]; with nmax a multiple of 4 the
+        // shifted reads are aligned 16-byte reads (four dword reads 16 bytes apart
+        // per lane would share banks)
         float yb[16];
+        auto ydiff = [&](int m, float4 e, float4 f) {
+            yb[4 * m] = f.x - e.x; yb[4 * m + 1] = f.y - e.y; yb[4 * m + 2] = f.z - e.z; yb[4 * m + 3] = f.w - e.w;
+        };
+        if ((nmax & 3) == 0) {
 #pragma unroll
-        for (int m = 0; m < TSW / 256; ++m) {
-            const int p = 256 * m + 4 * lane;
-            const int64_t t = u0 + p;
-            const float4 e = *(const float4*)(E + p);
-            const float4 y = make_float4(E[p + nmax] - e.x, E[p + 1 + nmax] - e.y, E[p + 2 + nmax] - e.z,
-                                         E[p + 3 + nmax] - e.w);
-            yb[4 * m] = y.x; yb[4 * m + 1] = y.y; yb[4 * m + 2] = y.z; yb[4 * m + 3] = y.w;
-            if (!y_whole) msd_add4_clipped(sy, y, t, u0, yhi);
+            for (int m = 0; m < TSW / 256; ++m) {
+                const int p = 256 * m + 4 * lane;
+                ydiff(m, *(const float4*)(E + p), *(const float4*)(E + p + nmax));
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < TSW / 256; ++m) {
+                const int p = 256 * m + 4 * lane;
+                ydiff(m, *(const float4*)(E + p),
+                      make_float4(E[p + nmax], E[p + 1 + nmax], E[p + 2 + nmax], E[p + 3 + nmax]));
+            }
         }
-        if (y_whole) msd_add16(sy, yb);
+        if (y_whole) {
+            msd_add16(sy, yb);
+        } else {
+#pragma unroll
+            for (int m = 0; m < TSW / 256; ++m)
+                msd_add4_clipped(sy, make_float4(yb[4 * m], yb[4 * m + 1], yb[4 * m + 2], yb[4 * m + 3]),
+                                 u0 + 256 * m + 4 * lane, u0, yhi);
+        }
         wave_sync();
     }
     Msd tx = block_merge(sx, sh.part);
