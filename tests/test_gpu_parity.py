@@ -83,19 +83,23 @@ def test_width_lists(widths):
     run_and_check(x, widths, 6.0)
 
 
-def test_ragged_and_edge_shapes():
+# the widest-boxcar statistics (AUTO, LINEAR) take their own load and edge paths
+@pytest.mark.parametrize("mode", ["sqrtn", "auto", "linear"])
+def test_ragged_and_edge_shapes(mode):
     rng = np.random.default_rng(3)
     for R, L, W in [(1, 64, list(range(1, 65))), (3, 65, [1, 2, 3]), (2, 1, [1]), (7, 4099, [1, 5, 9]),
-                    (1, 300, [300])]:
+                    (1, 300, [300]), (2, 70000, [1, 2, 3, 4, 5, 6, 7]), (3, 5000, list(range(1, 17)))]:
         x = torch.from_numpy(rng.standard_normal((R, L)).astype(np.float32)).to(DEV)
-        run_and_check(x, W, 2.5)
+        run_and_check(x, W, 2.5, mode=mode)
 
 
-def test_unaligned_views_and_strides():
+@pytest.mark.parametrize("mode", ["sqrtn", "auto", "linear"])
+def test_unaligned_views_and_strides(mode):
     base = synth.make_plane(6, 12003, seed=11, device=DEV, n_pulses=3, pulse_widths=[3, 9, 20],
                             snr_range=(10, 20), t_margin=40).x
-    run_and_check(base[:, 1:], list(range(1, 33)), 6.0)          # data pointer off by one element
-    run_and_check(base[:, 3:11000], [1, 2, 4, 8, 16, 32], 6.0)    # odd stride and length
+    run_and_check(base[:, 1:], list(range(1, 33)), 6.0, mode=mode)          # data pointer off by one element
+    run_and_check(base[:, 3:11000], [1, 2, 4, 8, 16, 32], 6.0, mode=mode)    # odd stride and length
+    run_and_check(base[:, 2:], [1, 3, 5, 7, 9, 11, 13], 6.0, mode=mode)     # Nmax not a multiple of 4
 
 
 def test_zero_variance_row_and_canary():
