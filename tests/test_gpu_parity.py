@@ -83,6 +83,16 @@ def test_width_lists(widths):
     run_and_check(x, widths, 6.0)
 
 
+# the widest boxcar the library takes (4,096 samples): 21 rows of 256 per statistics
+# sub-tile, fewer waves per work-group to fit the LDS, and a boxcar window of 4,607 samples
+@pytest.mark.parametrize("mode", ["sqrtn", "auto"])
+@pytest.mark.parametrize("widths", [[1 << k for k in range(13)], [4096]])
+def test_largest_widest_boxcar(widths, mode):
+    x = synth.make_plane(3, 20011, seed=17, device=DEV, n_pulses=3, pulse_widths=[1, 300, 2500],
+                         snr_range=(10, 25), gap=4200, t_margin=4096).x
+    run_and_check(x, widths, 6.0, mode=mode)
+
+
 # the widest-boxcar statistics (AUTO, LINEAR) take their own load and edge paths
 @pytest.mark.parametrize("mode", ["sqrtn", "auto", "linear"])
 def test_ragged_and_edge_shapes(mode):
