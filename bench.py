@@ -84,6 +84,35 @@ def cpu_model() -> str:
     return "unknown"
 
 
+def oracle_rows_baseline(x, widths, sigma_mode, target_s, *, strides=None, label=""):
+    """The FP64 oracle as it stands, on evenly spaced rows of the device plane x
+    with all host cores: a pilot of one row per core sizes the sample to about
+    target_s seconds.  Rows are independent under per-row statistics, so the
+    rate of a row sample is the rate of the plane."""
+    import numpy as np
+    import torch
+
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    R, L = x.shape
+
+    def run(nrows):
+        rows = np.linspace(0, R - 1, nrows).astype(np.int64)
+        x64 = x[torch.as_tensor(rows, device=x.device)].cpu().double().numpy()
+        t0 = time.perf_counter()
+        oracle.stream_step(x64, widths, sigma_mode=sigma_mode, kappa=1.0, nthreads=cores, strides=strides)
+        return time.perf_counter() - t0
+
+    nrows = max(2, min(R, cores))
+    dt = run(nrows)
+    if dt < target_s / 2:
+        nrows = int(min(R, max(nrows, nrows * target_s / max(dt, 1e-3))))
+        dt = run(nrows)
+    return {"value": round(nrows * L / dt / 1e9, 5), "unit": "GSamples/s", "cores": cores, "kind": "oracle",
+            "sample": "%d of %d rows x %d samples%s, FP64, %.1f s wall" % (nrows, R, L, label, dt),
+            "cpu_model": cpu_model(), "rows": nrows, "seconds": round(dt, 3)}
+
+
 def boxcar_kernel_name() -> str:
     """The one-plane boxcar kernel the library launches for the SKA and 1..16 lists."""
     return "boxcar_kernel" if os.environ.get("SPD_BOXCAR_FORM") == "strided" else "boxcar_win_kernel"
@@ -261,26 +290,8 @@ def main():
 
     if not args.no_cpu_baseline:
         import oracle
-        cores = len(os.sched_getaffinity(0))
-
-        def oracle_rows(nrows):
-            rows = np.linspace(0, R - 1, nrows).astype(np.int64)
-            x64 = x[torch.as_tensor(rows, device=dev)].cpu().double().numpy()
-            t0 = time.perf_counter()
-            oracle.stream_step(x64, W, sigma_mode="auto", kappa=1.0, nthreads=cores)
-            return time.perf_counter() - t0
-
-        # a short pilot sizes the sample to 10-20 s of oracle work
-        nrows = max(2, min(R, cores))
-        dt = oracle_rows(nrows)
-        if dt < 5.0:
-            nrows = int(min(R, max(nrows, nrows * 14.0 / max(dt, 1e-3))))
-            dt = oracle_rows(nrows)
-        out["cpu_baseline"] = {"value": round(nrows * L / dt / 1e9, 5), "unit": "GSamples/s", "cores": cores,
-                               "kind": "oracle",
-                               "sample": "%d of %d rows x %d samples, same widths / AUTO sigma_N, FP64, "
-                                         "%.1f s wall" % (nrows, R, L, dt),
-                               "cpu_model": cpu_model()}
+        # 10-20 s of oracle work
+        out["cpu_baseline"] = oracle_rows_baseline(x, W, "auto", 14.0, label=", same widths / AUTO sigma_N")
         # one thread on the small plane (64 x 65,536, widths 1..32, sqrt(N) sigma_N)
         small = synth.tiny(device="cpu")["plane"].x.double().numpy()
         t0 = time.perf_counter()
@@ -348,6 +359,18 @@ def run_batch(args, dev):
     plan.close()
     tops = evals * OPS_PER_EVAL / t_batch / 1e12
     small = batch_small_beams(args, dev, B, synth)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # rows of the first, middle and last beam, about 4 s each
+        picks = sorted({0, len(planes) // 2, len(planes) - 1})
+        legs = [oracle_rows_baseline(planes[i], W, "sqrtn", 4.0) for i in picks]
+        n_s = sum(leg["rows"] * planes[i].shape[1] for leg, i in zip(legs, picks))
+        secs = sum(leg["seconds"] for leg in legs)
+        cpu = {"value": round(n_s / secs / 1e9, 5), "unit": "GSamples/s", "cores": legs[0]["cores"],
+               "kind": "oracle", "cpu_model": legs[0]["cpu_model"],
+               "sample": "rows of beams %s (%s), widths 1..128, sqrt(N) sigma_N, FP64, %.1f s wall" % (
+                   picks, "; ".join("%d of %d rows x %d" % (leg["rows"], planes[i].shape[0], planes[i].shape[1])
+                                    for leg, i in zip(legs, picks)), secs)}
     return {
         "metric": METRIC, "value": round(samples / t_batch / 1e9, 3), "unit": "GSamples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_batch * 1e3, 3),
@@ -362,7 +385,7 @@ def run_batch(args, dev):
                            "ms_per_step": round(t_plain * 1e3, 3)},
         "speedup_vs_plain": round(t_plain / t_batch, 4),
         "schedule": info, "autotune_table": table, "plan_create_s": round(t_create, 3), "n_candidates": n_cand,
-        "small_beams": small,
+        "small_beams": small, "cpu_baseline": cpu,
     }
 
 
@@ -521,7 +544,18 @@ def run_dit(args, dev, levels=4):
                         "best_snr_ratio_p05": round(float(np.percentile(r, 5)), 4),
                         "best_snr_ratio_min": round(float(r.min()), 4),
                         "detected_dit": int(found_d), "detected_exhaustive": int(found_e)},
+        "cpu_baseline": dit_cpu_baseline(args, x, levels),
     }
+
+
+def dit_cpu_baseline(args, x, levels):
+    """The oracle's decimated search (same widths and start grids) on sampled rows."""
+    if args.no_cpu_baseline:
+        return None
+    import oracle
+    widths, strides = oracle.dit_widths(levels)
+    return oracle_rows_baseline(x, widths, "auto", 8.0, strides=strides,
+                                label=", decimated search (%d widths), AUTO sigma_N" % len(widths))
 
 
 def run_cluster(args, dev, dm_radius=2, t_radius=256):
@@ -932,6 +966,13 @@ def run_serve(args, dev):
     cnt = srv.counters()
     srv.close()
     fastest = out_runs[-1]
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the streaming oracle on sampled rows of beam 0's first chunk, scaled to the whole chunk
+        cpu = oracle_rows_baseline(payloads[0][0], W, "sqrtn", 6.0, label=" of beam 0's chunk 0, widths 1..256")
+        per_chunk = R * C / (cpu["value"] * 1e9)
+        cpu["per_chunk_s"] = round(per_chunk, 3)
+        cpu["x_real_time_one_beam"] = round(chunk_sky / per_chunk, 4)
     return {
         "metric": METRIC, "value": fastest["GSamples_per_s"], "unit": "GSamples/s", "n_gpus": 1,
         "steps": sum(r["chunks"] for r in out_runs), "warmup": 0, "ms_per_step": None,
@@ -941,6 +982,7 @@ def run_serve(args, dev):
                    "sigma_mode": "sqrtn", "halo": 255, "slots_per_beam": 2, "chunk_sky_s": round(chunk_sky, 6)},
         "p50_chunk_latency_ms": out_runs[0]["p50_ms"], "p99_chunk_latency_ms": out_runs[0]["p99_ms"],
         "max_real_time_factor": fastest["achieved_x_real_time"], "runs": out_runs, "counters": cnt,
+        "cpu_baseline": cpu,
     }
 
 
