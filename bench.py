@@ -235,6 +235,23 @@ def main():
     wall, msd_ms, box_ms = timed(p, args.steps, args.warmup)
     step_ms = timed.step_ms
     n_cand = int(count.item())
+
+    # the standalone threshold (select_candidates over the planes the last step
+    # wrote), timed on its own after the steps: it is not part of a step, whose
+    # threshold is fused into the boxcar pass
+    s_out = snr_flat[:R * nout].view(R, nout)
+    w_out = widx_flat[:R * nout].view(R, nout)
+    sel_count = torch.zeros(1, dtype=torch.int64, device=dev)
+    B.select_candidates(s_out, w_out, p, cand=cand, cand_count=sel_count, stream=stream)
+    sev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    for k in range(5):
+        sev[k].record(stream)
+        B.select_candidates(s_out, w_out, p, cand=cand, cand_count=sel_count, stream=stream)
+    sev[5].record(stream)
+    torch.cuda.synchronize()
+    sel_ms = sum(sev[k].elapsed_time(sev[k + 1]) for k in range(5)) / 5
+    sel_n = int(sel_count.item())
+    sel_bytes = R * nout * 4 + min(sel_n, cap) * (1 + 24)
     if n_cand > cap:
         print("warning: %d candidates exceed the list capacity %d" % (n_cand, cap), file=sys.stderr)
     samples = R * L
@@ -267,6 +284,10 @@ def main():
                            "GB/s": round(box_bytes / box_ms / 1e6, 1),
                            "hbm_frac": round(box_bytes / box_ms / 1e6 / HBM_PEAK_GBS, 4),
                            "valu_frac": round(box_tops / VALU_PEAK_TOPS, 4)},
+            "select_candidates": {"ms": round(sel_ms, 4), "GB/s": round(sel_bytes / sel_ms / 1e6, 1),
+                                  "hbm_frac": round(sel_bytes / sel_ms / 1e6 / HBM_PEAK_GBS, 4),
+                                  "n_candidates": sel_n, "same_count_as_fused": sel_n == n_cand,
+                                  "note": "standalone threshold over the stored planes, outside the step"},
         },
         "measured_stream_GB/s": {"copy": round(copy_gbs, 1), "sum_read": round(read_gbs, 1)},
         "n_candidates": n_cand,

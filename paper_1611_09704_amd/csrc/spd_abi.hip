@@ -508,7 +508,7 @@ spd_status select_candidates(const float* snr, const uint8_t* widx, int64_t n_ro
     if (out_stride < n_out_cols) return fail(SPD_E_INVALID, "out_stride < n_out_cols");
     if (!cand || !cand_count || cand_capacity < 0)
         return fail(SPD_E_INVALID, "candidate list needs cand, cand_count and capacity >= 0");
-    if ((uint64_t)n_rows * (uint64_t)((n_out_cols + 1023) / 1024) * 256u > kMaxGridItems)
+    if ((uint64_t)n_rows * (uint64_t)((n_out_cols + kSelCols - 1) / kSelCols) * 256u > kMaxGridItems)
         return fail(SPD_E_UNSUPPORTED, "output too large for one launch");
     SelectArgs sa;
     memset(&sa, 0, sizeof sa);

@@ -17,6 +17,7 @@ constexpr int kOutPerLane = 8;      // boxcar outputs per lane (strided by 64)
 constexpr int kMaxWidthsPadded = SPD_MAX_WIDTHS + kGroup;
 constexpr int kMaxGroups = kMaxWidthsPadded / kGroup;
 constexpr int kWinX = 8;           // consecutive starts per lane in the register-window form
+constexpr int kSelCols = 4096;     // columns per work-group of the standalone threshold (16 per lane)
 constexpr int kWinTableFloats = (kMaxWidthsPadded + 2 * kMaxGroups + 63) / 64 * 64;
 
 // Register-window form: logical element m of a wave's LDS array is stored at
