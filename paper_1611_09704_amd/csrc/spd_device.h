@@ -43,6 +43,7 @@ template <> struct Loader<SPD_F32> {
     __device__ Loader(const PlaneArg& p, int64_t r) : row((const float*)p.data + r * p.stride) {}
     __device__ __forceinline__ float at(int64_t c) const { return row[c]; }
     __device__ __forceinline__ float4 vec(int64_t c) const { return *(const float4*)(row + c); }
+    __device__ __forceinline__ int mis4() const { return (int)(((uintptr_t)row / sizeof(*row)) & 3); }
 };
 
 template <> struct Loader<SPD_F16> {
@@ -55,6 +56,7 @@ template <> struct Loader<SPD_F16> {
         float2 a = __half22float2(h0), b = __half22float2(h1);
         return make_float4(a.x, a.y, b.x, b.y);
     }
+    __device__ __forceinline__ int mis4() const { return (int)(((uintptr_t)row / sizeof(*row)) & 3); }
 };
 
 // x = scale_r * (q - zero_r), evaluated in FP32.
@@ -69,6 +71,7 @@ template <> struct Loader<SPD_U8> {
         uint32_t u = *(const uint32_t*)(row + c);
         return make_float4(deq(u & 255u), deq((u >> 8) & 255u), deq((u >> 16) & 255u), deq(u >> 24));
     }
+    __device__ __forceinline__ int mis4() const { return (int)((uintptr_t)row & 3); }
 };
 
 // Four consecutive samples from column c, all inside the row.  `vec`
@@ -249,21 +252,26 @@ __device__ void msd_block_x(const PlaneArg& pl, bool vec, int64_t r, int64_t b, 
     const int64_t lo = max(b * bc, ncb), hi = min((b + 1) * bc, pl.n_cols);
     Msd s{0.f, 0.f, 0.f};
     if (lo < hi) {
-        const int64_t a = min((lo + 3) & ~(int64_t)3, hi);
-        const int64_t e = max(a, hi & ~(int64_t)3);
+        // vector loads need an address that is a multiple of four elements: the
+        // columns c with (row offset + c) % 4 == 0, for any data pointer and
+        // row stride (the element alignment of the pointer is checked on the host)
+        (void)vec;
+        const int64_t q = (4 - ld.mis4()) & 3;
+        const int64_t a = min(lo + ((q - lo) & 3), hi);
+        const int64_t e = max(a, hi - ((hi - q) & 3));
         if (tid < a - lo) msd_add1(s, ld.at(lo + tid) - K);
         if (tid < hi - e) { Msd t{0.f, 0.f, 0.f}; msd_add1(t, ld.at(e + tid) - K); s = msd_merge(s, t); }
         int64_t c = a + 4 * (int64_t)tid;
         const int64_t step = 4 * (int64_t)nt;
         for (; c + 3 * step < e; c += 4 * step) {
-            const float4 v0 = load4<DT>(ld, c, vec), v1 = load4<DT>(ld, c + step, vec);
-            const float4 v2 = load4<DT>(ld, c + 2 * step, vec), v3 = load4<DT>(ld, c + 3 * step, vec);
+            const float4 v0 = ld.vec(c), v1 = ld.vec(c + step);
+            const float4 v2 = ld.vec(c + 2 * step), v3 = ld.vec(c + 3 * step);
             const float v[16] = {v0.x - K, v0.y - K, v0.z - K, v0.w - K, v1.x - K, v1.y - K, v1.z - K, v1.w - K,
                                  v2.x - K, v2.y - K, v2.z - K, v2.w - K, v3.x - K, v3.y - K, v3.z - K, v3.w - K};
             msd_add16(s, v);
         }
         for (; c < e; c += step) {
-            float4 v = load4<DT>(ld, c, vec);
+            float4 v = ld.vec(c);
             msd_add4(s, v.x - K, v.y - K, v.z - K, v.w - K);
         }
     }
