@@ -83,9 +83,11 @@ typedef enum {
 /* A DM-trial x time plane.  Element [r][t] lives at
  * (const char*)data + (r*row_stride + t)*elem_size, elem_size 4/2/1 for
  * F32/F16/U8.  For U8 the value is x = row_scale[r]*(q - row_zero[r]).
- * Vector loads are used when data is aligned to 4 elements and row_stride
- * is a multiple of 4; other planes are read with element loads, which costs
- * the statistics pass about a quarter more time (pad row_stride to avoid it). */
+ * Any element-aligned pointer and stride work.  With data aligned to 4
+ * elements and row_stride a multiple of 4, every kernel uses vector loads;
+ * otherwise the statistics of the widest boxcar (AUTO and LINEAR sigma_N)
+ * read element by element and take about a fifth more time (pad row_stride
+ * to avoid it).                                                             */
 typedef struct {
     const void* data;
     int32_t dtype;           /* spd_dtype */
