@@ -14,8 +14,10 @@
 // earlier chunk of the beam has been admitted (continuous batching: nothing
 // waits for a batch to fill).  Each beam has its own compute stream, so chunks
 // of different beams run concurrently on the device while chunks of one beam
-// stay in order; copies run on per-beam copy streams.  A worker thread admits
-// requests and detects completions; spd_server_poll hands finished chunks out.
+// stay in order; copies run on per-beam copy streams, a chunk in row groups
+// whose statistics and boxcars start as soon as their rows have arrived.  A
+// worker thread admits requests and detects completions; spd_server_poll
+// hands finished chunks out.
 //
 // With a de-dispersion plan in front (spd_server_create_dedisp) a beam streams
 // 8-bit filterbank chunks instead.  The server also keeps the beam's last
@@ -29,6 +31,7 @@
 #include <string.h>
 
 #include <chrono>
+#include <algorithm>
 #include <condition_variable>
 #include <deque>
 #include <mutex>
@@ -39,6 +42,12 @@
 #include "spd_kernels.h"
 
 namespace spd {
+
+// A chunk without de-dispersion in front is copied in this many row groups;
+// each group's statistics and boxcars start as soon as its rows have arrived
+// (rows are independent under per-row statistics), so a chunk's latency is
+// close to its copy time plus the work of one group.
+constexpr int kServeRowGroups = 4;
 
 static double now_s()
 {
@@ -70,7 +79,8 @@ struct ServeBeam {
     std::vector<int64_t*> d_count;
     std::vector<spd_candidate*> h_cand;    // pinned
     std::vector<int64_t*> h_count;
-    std::vector<hipEvent_t> h2d_done, free_ev, done_ev;
+    std::vector<hipEvent_t> h2d_done;      // [slots][kServeRowGroups]: a row group of the chunk is on the device
+    std::vector<hipEvent_t> free_ev, done_ev;
     spd_msd_state* state = nullptr;
     spd_row_stats* stats = nullptr;
     void* ws = nullptr;
@@ -187,27 +197,55 @@ static spd_status launch_chunk(spd_server* S, ServeReq& r)
     hipError_t e;
     // the slot's previous chunk has handed its halo on and is finished
     if ((e = hipStreamWaitEvent(b.copy, b.free_ev[slot], 0)) != hipSuccess) return device_status(e, "wait free");
-    // one contiguous host-to-device copy (full link speed), then a pitched
-    // device-to-device copy behind the halo columns
-    e = hipMemcpyAsync(b.stage[slot], r.host, (size_t)R * C * S->in_esize, hipMemcpyHostToDevice, b.copy);
-    if (e != hipSuccess) return device_status(e, "chunk copy-in");
-    if ((e = hipEventRecord(b.h2d_done[slot], b.copy)) != hipSuccess) return device_status(e, "record h2d");
-    if ((e = hipStreamWaitEvent(b.stream, b.h2d_done[slot], 0)) != hipSuccess) return device_status(e, "wait h2d");
     spd_status st;
-    if (S->dd) {
-        if ((st = dedisperse_chunk(S, b, slot, r.seq))) return st;
-    } else {
-        e = hipMemcpy2DAsync(base + H * S->esize, pitch_b, b.stage[slot], (size_t)C * S->esize, (size_t)C * S->esize,
-                             (size_t)R, hipMemcpyDeviceToDevice, b.stream);
-        if (e != hipSuccess) return device_status(e, "chunk re-pitch");
-    }
     const spd_plane x = view_plane(S, b, slot, r.seq);
-    st = msd_compute(&x, &S->params, r.seq == 0 ? 0 : H, r.seq == 0 ? 0 : 1, b.state, b.stats, b.ws, b.ws_bytes,
-                     b.stream);
-    if (st) return st;
-    st = boxcar_snr(&x, &S->params, b.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq), b.d_cand[slot],
-                    S->cfg.cand_capacity, b.d_count[slot], b.stream);
-    if (st) return st;
+    if (S->dd) {
+        // de-dispersion needs every channel: one contiguous host-to-device copy
+        e = hipMemcpyAsync(b.stage[slot], r.host, (size_t)R * C * S->in_esize, hipMemcpyHostToDevice, b.copy);
+        if (e != hipSuccess) return device_status(e, "chunk copy-in");
+        hipEvent_t h2d = b.h2d_done[(size_t)slot * kServeRowGroups];
+        if ((e = hipEventRecord(h2d, b.copy)) != hipSuccess) return device_status(e, "record h2d");
+        if ((e = hipStreamWaitEvent(b.stream, h2d, 0)) != hipSuccess) return device_status(e, "wait h2d");
+        if ((st = dedisperse_chunk(S, b, slot, r.seq))) return st;
+        st = msd_compute(&x, &S->params, r.seq == 0 ? 0 : H, r.seq == 0 ? 0 : 1, b.state, b.stats, b.ws, b.ws_bytes,
+                         b.stream);
+        if (st) return st;
+        st = boxcar_snr(&x, &S->params, b.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq), b.d_cand[slot],
+                        S->cfg.cand_capacity, b.d_count[slot], b.stream);
+        if (st) return st;
+    } else {
+        // row groups: each is one contiguous host-to-device copy (full link speed), then a
+        // pitched device-to-device copy behind the halo columns, its statistics (the whole
+        // view's block layout, so the partials fit the workspace) and its boxcars
+        const MsdLayout m = msd_layout(&x);
+        if ((st = check_msd_workspace(&x, m, b.ws, b.ws_bytes))) return st;
+        BoxcarPlan bp;
+        if ((st = plan_boxcar(&x, &S->params, b.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq), b.d_cand[slot],
+                              S->cfg.cand_capacity, b.d_count[slot], bp)))
+            return st;
+        if ((e = launch_zero_count(b.d_count[slot], b.stream)) != hipSuccess) return device_status(e, "count reset");
+        const int64_t per = (R + kServeRowGroups - 1) / kServeRowGroups;
+        for (int g = 0; g < kServeRowGroups; ++g) {
+            const int64_t r0 = (int64_t)g * per, rows = std::min<int64_t>(per, R - r0);
+            if (rows <= 0) break;
+            const size_t in_off = (size_t)r0 * (size_t)C * S->in_esize;
+            e = hipMemcpyAsync((char*)b.stage[slot] + in_off, (const char*)r.host + in_off,
+                               (size_t)rows * (size_t)C * S->in_esize, hipMemcpyHostToDevice, b.copy);
+            if (e != hipSuccess) return device_status(e, "chunk copy-in");
+            hipEvent_t h2d = b.h2d_done[(size_t)slot * kServeRowGroups + g];
+            if ((e = hipEventRecord(h2d, b.copy)) != hipSuccess) return device_status(e, "record h2d");
+            if ((e = hipStreamWaitEvent(b.stream, h2d, 0)) != hipSuccess) return device_status(e, "wait h2d");
+            e = hipMemcpy2DAsync(base + (size_t)r0 * pitch_b + H * S->esize, pitch_b, (char*)b.stage[slot] + in_off,
+                                 (size_t)C * S->esize, (size_t)C * S->esize, (size_t)rows, hipMemcpyDeviceToDevice,
+                                 b.stream);
+            if (e != hipSuccess) return device_status(e, "chunk re-pitch");
+            const spd_plane sub = row_slice(&x, r0, rows);
+            if ((st = enqueue_msd(&sub, &S->params, r.seq == 0 ? 0 : H, r.seq != 0, b.state + r0, b.stats + r0,
+                                  (double*)b.ws, m, b.stream)))
+                return st;
+            if ((st = enqueue_boxcar(&sub, b.stats + r0, bp, r0, rows, b.stream))) return st;
+        }
+    }
     if (H > 0) {                                    // last H columns become the next chunk's halo
         char* next = (char*)b.buf[(slot + 1) % slots];
         e = hipMemcpy2DAsync(next, pitch_b, base + new_cols(S, r.seq) * S->esize, pitch_b, (size_t)H * S->esize,
@@ -430,7 +468,7 @@ static spd_status create_server(const spd_server_config* cfg, const spd_params* 
         b.d_count.assign(slots, nullptr);
         b.h_cand.assign(slots, nullptr);
         b.h_count.assign(slots, nullptr);
-        b.h2d_done.assign(slots, nullptr);
+        b.h2d_done.assign((size_t)slots * kServeRowGroups, nullptr);
         b.free_ev.assign(slots, nullptr);
         b.done_ev.assign(slots, nullptr);
         const size_t bytes = (size_t)D * (size_t)(S->halo + cfg->chunk_cols) * S->esize;
@@ -442,7 +480,8 @@ static spd_status create_server(const spd_server_config* cfg, const spd_params* 
             if (e == hipSuccess) e = hipMalloc((void**)&b.d_count[s], sizeof(int64_t));
             if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_cand[s], sizeof(spd_candidate) * cfg->cand_capacity, 0);
             if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_count[s], sizeof(int64_t), 0);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&b.h2d_done[s], hipEventDisableTiming);
+            for (int g = 0; g < kServeRowGroups && e == hipSuccess; ++g)
+                e = hipEventCreateWithFlags(&b.h2d_done[(size_t)s * kServeRowGroups + g], hipEventDisableTiming);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&b.free_ev[s], hipEventDisableTiming);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&b.done_ev[s], hipEventDisableTiming);
         }
