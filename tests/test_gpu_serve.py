@@ -46,9 +46,12 @@ def _oracle_stream(chunks, W, thr, mode="sqrtn"):
     return res
 
 
-@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
-def test_server_matches_streaming_oracle(dtype):
-    R, Lc, K, nb = 6, 4096, 4, 3
+# chunks are copied and processed in row groups: 6 rows leave the last group
+# empty, 7 make it short, 1 and 3 are fewer rows than groups
+@pytest.mark.parametrize("dtype,R", [(torch.float32, 6), (torch.float16, 6), (torch.float32, 7),
+                                     (torch.float16, 1), (torch.float32, 3)])
+def test_server_matches_streaming_oracle(dtype, R):
+    Lc, K, nb = 4096, 4, 3
     W = list(range(1, 65))
     thr = 6.0
     streams = _streams(nb, K, R, Lc, 64, dtype)
