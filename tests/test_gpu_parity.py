@@ -54,6 +54,41 @@ def test_tiny_plane_scope_and_separate_select():
     run_and_check(x, cfg["widths"], cfg["threshold"], fused=False)
 
 
+# select_candidates reads 4,096 columns per work-group: 16-byte loads where the
+# rows are aligned and the whole chunk is inside the row, element loads otherwise
+@pytest.mark.parametrize("pad", [0, 4, 1])
+def test_standalone_select_load_paths(pad):
+    W = list(range(1, 33))
+    x = synth.make_plane(5, 20031, seed=23, device=DEV, n_pulses=6, pulse_widths=[1, 4, 16, 32],
+                         snr_range=(7, 20), t_margin=32).x
+    p = B.Params(W, 3.0)                                       # a low threshold: many candidates
+    nout = x.shape[1] - 31                                     # 20,000: 4 whole chunks and a tail
+    stride = nout + pad
+    print("case: select stride=%d" % stride, flush=True)
+    stats = B.msd_compute(x, p)
+    snr = torch.full((5, stride), -1.0, device=DEV)
+    widx = torch.zeros((5, stride), dtype=torch.uint8, device=DEV)
+    fused = B.new_candidates(1 << 16, DEV)
+    n_fused = torch.zeros(1, dtype=torch.int64, device=DEV)
+    B.boxcar_snr(x, p, stats, snr=snr[:, :nout], widx=widx[:, :nout], out_stride=stride, cand=fused,
+                 cand_count=n_fused)
+    alone = B.new_candidates(1 << 16, DEV)
+    n_alone = torch.zeros(1, dtype=torch.int64, device=DEV)
+    B.select_candidates(snr[:, :nout], widx[:, :nout], p, t_offset=17, cand=alone, cand_count=n_alone)
+    torch.cuda.synchronize()
+    nf, na = int(n_fused.item()), int(n_alone.item())
+    assert nf == na and 0 < na < (1 << 16)
+    key = lambda c: (int(c["row"]), int(c["t"]), int(c["width"]), float(c["snr"]))
+    fused_set = {key(c) for c in B.candidates_to_numpy(fused, nf)}
+    alone_set = {(r, t - 17, w, v) for r, t, w, v in (key(c) for c in B.candidates_to_numpy(alone, na))}
+    assert alone_set == fused_set
+    o = oracle.detect(x.cpu().double().numpy(), W, 3.0)
+    ok = set(zip(o["cands"]["row"].tolist(), o["cands"]["t"].tolist()))
+    got = {(r, t) for r, t, _, _ in alone_set}
+    for k in got ^ ok:
+        assert abs(o["snr"][k] - 3.0) <= C.TOL_SNR, "candidate mismatch at %s" % (k,)
+
+
 @pytest.mark.parametrize("mode", ["linear", "auto", "linear_literal"])
 def test_sigma_modes_with_signal_dominated_rows(mode):
     cfg = synth.ska(device=DEV, R=12, L=30000, n_pulses=6, n_bright=3)
