@@ -191,15 +191,21 @@ def test_determinism():
     assert ka == kb
 
 
-@pytest.mark.parametrize("form", ["f16", "u8"])
+# "+1": the plane viewed from its second column, so no row starts on a
+# 4-element boundary and the statistics align their vector loads per row
+@pytest.mark.parametrize("form", ["f16", "u8", "f16+1", "u8+1"])
 def test_precision_forms_parity(form):
     cfg = synth.tiny(device=DEV, R=16, L=30000)
     x32 = cfg["plane"].x
-    if form == "f16":
+    if form.startswith("f16"):
         x, scale, zero = synth.quantize_f16(x32), None, None
     else:
         x, scale, zero = synth.quantize_u8(x32, cfg["plane"].row_sigma)
+    if form.endswith("+1"):
+        x = x[:, 1:]
     run_and_check(x, cfg["widths"], cfg["threshold"], scale=scale, zero=zero)
+    if form.endswith("+1"):
+        run_and_check(x, cfg["widths"], cfg["threshold"], scale=scale, zero=zero, mode="auto")
 
 
 @pytest.mark.parametrize("mode", ["sqrtn", "linear"])
