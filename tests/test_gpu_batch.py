@@ -69,6 +69,36 @@ def test_batch_matches_plain_and_oracle(widths, mode):
     plan.close()
 
 
+@pytest.mark.parametrize("form", ["f16", "u8"])
+def test_batch_precision_forms(form):
+    """FP16 and per-row U8 beams (uneven, mostly unaligned rows) in one plan:
+    every beam against the oracle on the values stored, and against plain
+    launches of the same beam."""
+    print("case: batch form=%s" % form, flush=True)
+    widths, thr = list(range(1, 33)), 5.0
+    cfg = synth.batch(device=DEV, shapes=SHAPES, pulses_per_beam=3, wmax=widths[-1])
+    beams = []
+    for pl in cfg["planes"]:
+        if form == "f16":
+            beams.append((synth.quantize_f16(pl.x), None, None))
+        else:
+            beams.append(synth.quantize_u8(pl.x, pl.row_sigma))
+    p = B.Params(widths, thr, "row", "auto", 1.0)
+    plan = B.BatchPlan([b if form == "u8" else b[0] for b in beams], p, autotune=False)
+    got = _cands_by_beam(_batch_run(plan))
+    for b, (x, sc, z) in enumerate(beams):
+        x64 = C.plane_f64(x, sc, z)
+        o = oracle.detect(x64, widths, thr, sigma_mode="auto", kappa=1.0)
+        C.check_stats(plan.stats(b).cpu().numpy(), o["stats"], True)
+        gb = got.get(b, np.zeros(0, dtype=B.CANDIDATE_DTYPE))
+        C.check_candidates(gb, o["cands"], thr, lambda r, t: o["snr"][r, t])
+        plain = B.detect(x, widths, thr, sigma_mode="auto", kappa=1.0, scale=sc, zero=z)
+        C.check_candidates(gb, {"row": plain["cands"]["row"], "t": plain["cands"]["t"],
+                                "snr": plain["cands"]["snr"], "width": plain["cands"]["width"]},
+                           thr, lambda r, t: o["snr"][r, t])
+    plan.close()
+
+
 def test_batch_graph_replays_match_eager():
     cfg = synth.batch(device=DEV, shapes=SHAPES, pulses_per_beam=4, wmax=64)
     planes = [pl.x for pl in cfg["planes"]]
