@@ -47,15 +47,18 @@ def _oracle_stream(chunks, W, thr, mode="sqrtn"):
 
 
 # chunks are copied and processed in row groups: 6 rows leave the last group
-# empty, 7 make it short, 1 and 3 are fewer rows than groups
-@pytest.mark.parametrize("dtype,R", [(torch.float32, 6), (torch.float16, 6), (torch.float32, 7),
-                                     (torch.float16, 1), (torch.float32, 3)])
-def test_server_matches_streaming_oracle(dtype, R):
+# empty, 7 make it short, 1 and 3 are fewer rows than groups; AUTO and LINEAR
+# carry the widest-boxcar statistics from chunk to chunk as well
+@pytest.mark.parametrize("dtype,R,mode", [(torch.float32, 6, "sqrtn"), (torch.float16, 6, "sqrtn"),
+                                          (torch.float32, 7, "sqrtn"), (torch.float16, 1, "sqrtn"),
+                                          (torch.float32, 3, "sqrtn"), (torch.float32, 7, "linear"),
+                                          (torch.float16, 6, "auto")])
+def test_server_matches_streaming_oracle(dtype, R, mode):
     Lc, K, nb = 4096, 4, 3
     W = list(range(1, 65))
     thr = 6.0
     streams = _streams(nb, K, R, Lc, 64, dtype)
-    srv = B.Server(nb, R, Lc, B.Params(W, thr), dtype=dtype, cand_capacity=4096)
+    srv = B.Server(nb, R, Lc, B.Params(W, thr, "row", mode, 1.0), dtype=dtype, cand_capacity=4096)
     for k in range(K):                       # interleave beams chunk by chunk
         for b in range(nb):
             srv.submit(b, k, streams[b][0][k])
@@ -63,7 +66,7 @@ def test_server_matches_streaming_oracle(dtype, R):
     srv.close()
     by = {(r["beam"], r["seq"]): (r, c) for r, c in results}
     for b in range(nb):
-        orc = _oracle_stream(streams[b][0], W, thr)
+        orc = _oracle_stream(streams[b][0], W, thr, mode)
         seqs = [r["seq"] for r, _ in results if r["beam"] == b]
         assert seqs == sorted(seqs), "beam %d completed out of order" % b
         found = set()
