@@ -5,10 +5,12 @@
  *
  * The path runs over a plane of de-dispersed time series, one row per DM
  * trial, time contiguous (Sec. 1, Sec. 2.3):
- *   1. msd_compute       mean and standard deviation per unit (Sec. 2.1,
- *                        Eq. MSD03 inside a block, Eq. MSD04 across blocks),
- *                        plus sigma of the widest boxcar when the linear
- *                        approximation of Sec. 2.2 Eq. (sd03) is in use;
+ *   1. msd_compute       mean and standard deviation per unit (Sec. 2.1:
+ *                        inside a block, FP32 mini-batches of 16 samples
+ *                        merged with Eq. MSD04 and Eq. MSD03 at the edges;
+ *                        Eq. MSD04 in FP64 across blocks), plus sigma of the
+ *                        widest boxcar when the linear approximation of
+ *                        Sec. 2.2 Eq. (sd03) is in use;
  *   2. boxcar_snr        boxcars of every listed width at every sample, their
  *                        SNR with sigma_N from Eq. (sd02) or Eq. (sd03), and
  *                        the highest SNR with its width (Sec. 2.3,
