@@ -207,8 +207,9 @@ def main():
         wall seconds and the mean duration of each call (HIP events on the
         launch stream)."""
         no = L - params.nmax + 1
-        s_out = snr_flat[:R * no].view(R, no)
-        w_out = widx_flat[:R * no].view(R, no)
+        po = (no + 15) // 16 * 16                 # output rows padded to 64-byte multiples
+        s_out = snr_flat[:R * po].view(R, po)[:, :no]
+        w_out = widx_flat[:R * po].view(R, po)[:, :no]
 
         def one(evs=None):
             if evs: evs[0].record(stream)
@@ -239,8 +240,9 @@ def main():
     # the standalone threshold (select_candidates over the planes the last step
     # wrote), timed on its own after the steps: it is not part of a step, whose
     # threshold is fused into the boxcar pass
-    s_out = snr_flat[:R * nout].view(R, nout)
-    w_out = widx_flat[:R * nout].view(R, nout)
+    po = (nout + 15) // 16 * 16
+    s_out = snr_flat[:R * po].view(R, po)[:, :nout]
+    w_out = widx_flat[:R * po].view(R, po)[:, :nout]
     sel_count = torch.zeros(1, dtype=torch.int64, device=dev)
     B.select_candidates(s_out, w_out, p, cand=cand, cand_count=sel_count, stream=stream)
     sev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]

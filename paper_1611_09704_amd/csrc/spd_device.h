@@ -1086,13 +1086,16 @@ __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t
             }
         }
     }
-    // per-start outputs.  Rows that allow vector stores take each lane's 8 starts
-    // directly; otherwise the wave transposes them through its LDS region (done
-    // with the window by now) and lane l stores starts tw + l + 64i, so every
-    // store instruction covers consecutive addresses.
+    // per-start outputs.  In the grouped form (long width lists, bound by the ALU)
+    // rows that allow vector stores take each lane's 8 starts directly, which
+    // saves the transpose's work.  Otherwise -- and always for the short lists,
+    // whose stores weigh more -- the wave transposes them through its LDS region
+    // (done with the window by now) and lane l stores starts tw + l + 64i, so
+    // every store instruction covers consecutive addresses; measured faster
+    // for those lists even where vector stores are allowed.
     if (!ba.snr && !ba.widx) return;
     const uint32_t need_vec = (ba.snr ? 1u : 0u) | (ba.widx ? 2u : 0u);
-    if ((ba.out_vec & need_vec) == need_vec) {
+    if (SMALLN == 0 && (ba.out_vec & need_vec) == need_vec) {
         if (ba.snr) {
             float* dst = ba.snr + r * ba.out_stride + t0;
             if (nvalid == X) {

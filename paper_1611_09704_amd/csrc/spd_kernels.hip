@@ -94,38 +94,26 @@ __global__ __launch_bounds__(256) void boxcar_dit_kernel(PlaneArg pl, bool vec, 
 }
 
 // Sec. 2.4 over stored snr / width-index arrays.  A work-group covers kSelCols
-// columns of one row, 16 per lane: four 16-byte loads 1,024 columns apart when
-// the rows are aligned, otherwise sixteen dword loads 256 columns apart (each
-// load instruction then reads 256 consecutive bytes per wave).  A wave with no
-// SNR at the threshold stops there; the others compact with one ballot per
-// value and one atomic per wave that has candidates.
+// columns of one row, 16 per lane in dword loads 256 columns apart: every load
+// instruction reads 256 consecutive bytes per wave, and sixteen loads per lane
+// are in flight (measured faster than four 16-byte loads per lane, even on
+// aligned rows).  A wave with no SNR at the threshold stops there; the others
+// compact with one ballot per value and one atomic per wave that has
+// candidates.
 __global__ __launch_bounds__(256) void select_kernel(const float* snr, const uint8_t* widx,
                                                      int64_t ncols, int64_t stride, int64_t chunks,
-                                                     SelectArgs sa, bool vec)
+                                                     SelectArgs sa)
 {
     const int lane = threadIdx.x & 63, tid = threadIdx.x;
     const uint64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t r = (int64_t)(blk / (uint64_t)chunks), ch = (int64_t)(blk % (uint64_t)chunks);
     const float* row = snr + r * stride;
-    const int64_t p0 = ch * kSelCols;
-    const bool vload = vec && p0 + kSelCols <= ncols;
-    // column of v[i] in either layout
-    auto col = [&](int i) -> int64_t {
-        return vload ? p0 + 4 * tid + 1024 * (i >> 2) + (i & 3) : p0 + tid + 256 * i;
-    };
+    const int64_t p0 = ch * kSelCols + tid;                         // column of v[i] is p0 + 256i
     float v[16];
-    if (vload) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float4 q = *(const float4*)(row + p0 + 4 * tid + 1024 * j);
-            v[4 * j] = q.x; v[4 * j + 1] = q.y; v[4 * j + 2] = q.z; v[4 * j + 3] = q.w;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int64_t t = p0 + tid + 256 * i;
-            v[i] = t < ncols ? row[t] : -INFINITY;                 // never at a finite threshold
-        }
+    for (int i = 0; i < 16; ++i) {
+        const int64_t t = p0 + 256 * i;
+        v[i] = t < ncols ? row[t] : -INFINITY;                     // never at a finite threshold
     }
     float m = v[0];
 #pragma unroll
@@ -144,7 +132,7 @@ __global__ __launch_bounds__(256) void select_kernel(const float* snr, const uin
         if (pred) {
             const unsigned long long k = base + (unsigned long long)before;
             if (k < (unsigned long long)sa.cand_capacity) {
-                const int64_t t = col(i);
+                const int64_t t = p0 + 256 * i;
                 spd_candidate cd;
                 cd.row = (int32_t)r;
                 cd.width = sa.width[widx[r * stride + t]];
@@ -272,8 +260,7 @@ hipError_t launch_select(const float* snr, const uint8_t* widx, int64_t nrows, i
     const int64_t chunks = (ncols + kSelCols - 1) / kSelCols;
     const uint64_t nb = (uint64_t)nrows * (uint64_t)chunks;
     if (nb == 0) return hipSuccess;
-    const bool vec = ((uintptr_t)snr % 16) == 0 && (stride % 4) == 0;
-    hipLaunchKernelGGL(select_kernel, dim3(nb), dim3(256), 0, s, snr, widx, ncols, stride, chunks, sa, vec);
+    hipLaunchKernelGGL(select_kernel, dim3(nb), dim3(256), 0, s, snr, widx, ncols, stride, chunks, sa);
     return hipGetLastError();
 }
 

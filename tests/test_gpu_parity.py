@@ -54,8 +54,8 @@ def test_tiny_plane_scope_and_separate_select():
     run_and_check(x, cfg["widths"], cfg["threshold"], fused=False)
 
 
-# select_candidates reads 4,096 columns per work-group: 16-byte loads where the
-# rows are aligned and the whole chunk is inside the row, element loads otherwise
+# select_candidates reads 4,096 columns per work-group, 16 per lane: whole
+# chunks and a ragged tail, on aligned and unaligned row strides
 @pytest.mark.parametrize("pad", [0, 4, 1])
 def test_standalone_select_load_paths(pad):
     W = list(range(1, 33))
