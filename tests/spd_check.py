@@ -4,7 +4,8 @@
 * width index equal, or the oracle's SNR at the GPU's width within ``tol`` of
   the oracle's maximum (near-ties may resolve either way);
 * candidate sets equal except entries whose oracle SNR is within ``tol`` of
-  the threshold;
+  the threshold, and every listed width equal to the oracle's or a near-tie
+  by the rule above (the list's four fields of Sec. 2.4);
 * statistics: mean and sigma to 1e-6 relative (sigma_Nmax too when used), the
   same flags.
 """
@@ -53,10 +54,37 @@ def check_snr_widx(x64, widths, snr_g, widx_g, snr_o, widx_o, ora_stats, scope="
     return worst, len(mism)
 
 
-def check_candidates(cands_g: np.ndarray, cands_o: dict, threshold: float, snr_o_lookup, tol=TOL_SNR,
-                     widths=None, width_ok=None):
-    """Candidate sets equal except within ``tol`` of the threshold.
-    ``snr_o_lookup(row, t)`` returns the oracle's SNR there."""
+def width_rule(x64, widths, stats, scope="row", rows=None, t_offset=0, strides=None):
+    """The oracle's SNR of candidate (row, t) at a given width, in candidate
+    coordinates: ``row`` a plane row (``rows`` lists the plane rows that
+    ``x64`` holds when only a sample was checked), ``t`` a window start plus
+    ``t_offset``.  The width must be one of ``widths`` and, where ``strides``
+    (one per width) are given, evaluated at that start."""
+    wl = [int(w) for w in widths]
+    stride_of = dict(zip(wl, [int(s) for s in strides])) if strides is not None else None
+
+    def snr_w(row, t, width):
+        assert width in wl, "candidate (%d, %d): width %d is not in the list" % (row, t, width)
+        i = rows.index(row) if rows is not None else row
+        tt = t - t_offset
+        if stride_of is not None:
+            assert tt % stride_of[width] == 0, "candidate (%d, %d): width %d is not evaluated there" % (
+                row, t, width)
+        return oracle.snr_at(x64[i], tt, width, stats[0 if scope == "plane" else i])
+    return snr_w
+
+
+def check_candidates(cands_g: np.ndarray, cands_o: dict, threshold: float, snr_o_lookup, snr_at_width,
+                     tol=TOL_SNR):
+    """A candidate list against the oracle's, every field of Sec. 2.4.
+
+    * sets of (row, t) equal except entries whose oracle SNR is within ``tol``
+      of the threshold;
+    * the SNR of every common entry within ``tol`` of the oracle's;
+    * the width of every GPU entry equal to the oracle's, or one whose oracle
+      SNR at that start is within ``tol`` of the oracle maximum (a near-tie).
+    ``snr_o_lookup(row, t)`` returns the oracle's highest SNR there and
+    ``snr_at_width(row, t, width)`` its SNR at one width (``width_rule``)."""
     g = {(int(c["row"]), int(c["t"])): (float(c["snr"]), int(c["width"])) for c in cands_g}
     o = {(int(r), int(t)): (float(s), int(w)) for r, t, s, w in
          zip(cands_o["row"], cands_o["t"], cands_o["snr"], cands_o["width"])}
@@ -64,8 +92,12 @@ def check_candidates(cands_g: np.ndarray, cands_o: dict, threshold: float, snr_o
     for k in set(g) ^ set(o):
         s = snr_o_lookup(*k)
         assert abs(s - threshold) <= tol, "candidate %s only on one side (oracle snr %g)" % (k, s)
-    for k in set(g) & set(o):
-        assert abs(g[k][0] - o[k][0]) <= tol
-        if g[k][1] != o[k][1] and width_ok is not None:
-            assert width_ok(k, g[k][1]), "candidate %s width %d vs %d" % (k, g[k][1], o[k][1])
+    for k, (gs, gw) in g.items():
+        if k in o:
+            assert abs(gs - o[k][0]) <= tol, "candidate %s snr %g vs %g" % (k, gs, o[k][0])
+            if gw == o[k][1]:
+                continue
+        smax = snr_o_lookup(*k)
+        s = snr_at_width(k[0], k[1], gw)
+        assert s >= smax - tol, "candidate %s width %d gives oracle snr %g < max %g" % (k, gw, s, smax)
     return len(g), len(o)

@@ -62,10 +62,11 @@ def test_batch_matches_plain_and_oracle(widths, mode):
         o = oracle.detect(x64, widths, 5.0, sigma_mode=mode, kappa=0.5)
         C.check_stats(st_b, o["stats"], mode != "sqrtn")
         gb = got.get(b, np.zeros(0, dtype=B.CANDIDATE_DTYPE))
-        C.check_candidates(gb, o["cands"], 5.0, lambda r, t: o["snr"][r, t])
+        wr = C.width_rule(x64, widths, o["stats"])
+        C.check_candidates(gb, o["cands"], 5.0, lambda r, t: o["snr"][r, t], wr)
         C.check_candidates(gb, {"row": plain["cands"]["row"], "t": plain["cands"]["t"],
                                 "snr": plain["cands"]["snr"], "width": plain["cands"]["width"]},
-                           5.0, lambda r, t: o["snr"][r, t])
+                           5.0, lambda r, t: o["snr"][r, t], wr)
     plan.close()
 
 
@@ -91,11 +92,12 @@ def test_batch_precision_forms(form):
         o = oracle.detect(x64, widths, thr, sigma_mode="auto", kappa=1.0)
         C.check_stats(plan.stats(b).cpu().numpy(), o["stats"], True)
         gb = got.get(b, np.zeros(0, dtype=B.CANDIDATE_DTYPE))
-        C.check_candidates(gb, o["cands"], thr, lambda r, t: o["snr"][r, t])
+        wr = C.width_rule(x64, widths, o["stats"])
+        C.check_candidates(gb, o["cands"], thr, lambda r, t: o["snr"][r, t], wr)
         plain = B.detect(x, widths, thr, sigma_mode="auto", kappa=1.0, scale=sc, zero=z)
         C.check_candidates(gb, {"row": plain["cands"]["row"], "t": plain["cands"]["t"],
                                 "snr": plain["cands"]["snr"], "width": plain["cands"]["width"]},
-                           thr, lambda r, t: o["snr"][r, t])
+                           thr, lambda r, t: o["snr"][r, t], wr)
     plan.close()
 
 
@@ -161,7 +163,8 @@ def test_batch_full_size_sampled_rows():
         oc["row"] = np.asarray(rows)[oc["row"]]
         gb = cands.get(b, np.zeros(0, dtype=B.CANDIDATE_DTYPE))
         gb = gb[np.isin(gb["row"], rows)]
-        C.check_candidates(gb, oc, cfg["threshold"], lambda r, t: osnr[rows.index(r), t])
+        C.check_candidates(gb, oc, cfg["threshold"], lambda r, t: osnr[rows.index(r), t],
+                           C.width_rule(x64, W, ost, rows=rows))
         print("beam %d rows %s: %d candidates ok" % (b, rows, len(gb)), flush=True)
     plan.close()
     del planes, cfg

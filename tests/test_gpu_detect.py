@@ -109,7 +109,7 @@ def test_detect_matches_oracle():
     C.check_stats(st.cpu().numpy(), o["stats"], True)
     C.check_snr_widx(x64, W, snr.cpu().numpy(), widx.cpu().numpy(), o["snr"], o["widx"], o["stats"])
     C.check_candidates(B.candidates_to_numpy(cand, int(cnt.item())), o["cands"], thr,
-                       lambda r, t: o["snr"][r, t])
+                       lambda r, t: o["snr"][r, t], C.width_rule(x64, W, o["stats"]))
 
 
 def test_detect_graph_replays():

@@ -54,7 +54,8 @@ def check_against_oracle(x, levels, thr, mode="sqrtn", scope="row", scale=None, 
     t = np.arange(g_snr.shape[1])
     assert np.all(t[None, :] % strides[g_idx] == 0), "a reported width is not evaluated at its start"
     worst, nmis = C.check_snr_widx(x64, o["widths"], g_snr, g_idx, o["snr"], o["widx"], o["stats"], scope=scope)
-    C.check_candidates(cands, o["cands"], thr, lambda r, tt: o["snr"][r, tt])
+    C.check_candidates(cands, o["cands"], thr, lambda r, tt: o["snr"][r, tt],
+                       C.width_rule(x64, o["widths"], o["stats"], scope=scope, strides=o["strides"]))
     print("dit: max|dSNR|=%.3g width mismatches=%d candidates=%d" % (worst, nmis, len(cands)), flush=True)
     return p, snr, widx, cands
 

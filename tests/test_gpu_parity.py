@@ -31,7 +31,8 @@ def run_and_check(x, widths, thr, *, scope="row", mode="sqrtn", kappa=1.0, scale
     worst, nmis = C.check_snr_widx(x64, widths, g["snr"].cpu().numpy(), g["widx"].cpu().numpy(),
                                    o["snr"], o["widx"], o["stats"], scope=scope)
     if check_cands:
-        C.check_candidates(g["cands"], o["cands"], thr, lambda r, t: o["snr"][r, t])
+        C.check_candidates(g["cands"], o["cands"], thr, lambda r, t: o["snr"][r, t],
+                           C.width_rule(x64, widths, o["stats"], scope=scope))
     return g, o, worst, nmis
 
 
@@ -263,6 +264,7 @@ def test_ska_full_size_sampled_rows():
     oc["row"] = np.asarray(rows)[oc["row"]]
     rset = set(rows)
     gc = np.array([c for c in g["cands"] if int(c["row"]) in rset], dtype=B.CANDIDATE_DTYPE)
-    C.check_candidates(gc, oc, cfg["threshold"], lambda r, t: osnr[rows.index(r), t])
+    C.check_candidates(gc, oc, cfg["threshold"], lambda r, t: osnr[rows.index(r), t],
+                       C.width_rule(x64, W, ost, rows=rows))
     del g, x
     torch.cuda.empty_cache()

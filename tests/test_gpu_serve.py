@@ -30,8 +30,10 @@ def _drain(srv, n, timeout_ms=20000):
     return got
 
 
-def _oracle_stream(chunks, W, thr, mode="sqrtn"):
-    """Per chunk: oracle candidates of the view [halo | chunk] with the running state."""
+def _oracle_stream(chunks, W, thr, mode="sqrtn", rows=None):
+    """Per chunk: oracle candidates of the view [halo | chunk] with the running
+    state, its SNR plane, t_offset and the width rule of its candidates
+    (``rows``: the plane rows the chunks hold, when only a sample is checked)."""
     nmax = W[-1]
     state, prev, res = None, None, []
     for k, c in enumerate(chunks):
@@ -41,7 +43,8 @@ def _oracle_stream(chunks, W, thr, mode="sqrtn"):
         else:
             view, ncb, toff = np.concatenate([prev[:, -(nmax - 1):], x], axis=1), nmax - 1, k * x.shape[1] - (nmax - 1)
         state, st, snr, widx = oracle.stream_step(view, W, new_col_begin=ncb, state=state, sigma_mode=mode)
-        res.append((oracle.select(snr, widx, W, thr, t_offset=toff), snr, toff))
+        res.append((oracle.select(snr, widx, W, thr, t_offset=toff), snr, toff,
+                    C.width_rule(view, W, st, rows=rows, t_offset=toff)))
         prev = x
     return res
 
@@ -72,9 +75,9 @@ def test_server_matches_streaming_oracle(dtype, R, mode):
         found = set()
         for k in range(K):
             r, c = by[(b, k)]
-            oc, snr, toff = orc[k]
+            oc, snr, toff, wr = orc[k]
             assert r["status"] == 0 and r["t_offset"] == toff
-            C.check_candidates(c, oc, thr, lambda row, t: snr[row, t - toff])
+            C.check_candidates(c, oc, thr, lambda row, t: snr[row, t - toff], wr)
             found |= {(int(x["row"]), int(x["t"])) for x in c}
         for p in streams[b][1]:             # every bright boundary-straddling pulse is seen
             if p.snr >= 10.0:
@@ -97,7 +100,10 @@ def test_server_same_result_alone_and_in_a_mix():
             mix.submit(b, k, streams[b][0][k])
     rm = sorted([r for r in _drain(mix, 4 * K) if r[0]["beam"] == 0], key=lambda r: r[0]["seq"])
     mix.close()
+    orc = _oracle_stream(streams[0][0], W, 5.5)
     for (a, ca), (m, cm) in zip(ra, rm):
+        oc, snr, toff, wr = orc[a["seq"]]
+        C.check_candidates(ca, oc, 5.5, lambda row, t: snr[row, t - toff], wr)
         assert a["n_cands"] == m["n_cands"]
         ka = sorted((int(x["row"]), int(x["t"]), float(x["snr"]), int(x["width"])) for x in ca)
         km = sorted((int(x["row"]), int(x["t"]), float(x["snr"]), int(x["width"])) for x in cm)
@@ -140,14 +146,14 @@ def test_server_full_size_chunks_sampled_rows():
     for b in range(nb):
         rows = sorted(set([p.row for p in streams[b][1]] + rng.choice(R, 3, replace=False).tolist()))
         sub = [c[rows] for c in streams[b][0]]
-        orc = _oracle_stream(sub, W, 7.0)
+        orc = _oracle_stream(sub, W, 7.0, rows=rows)
         for k in range(K):
             r, c = next(x for x in res if x[0]["beam"] == b and x[0]["seq"] == k)
-            oc, snr, toff = orc[k]
+            oc, snr, toff, wr = orc[k]
             oc = dict(oc)
             oc["row"] = np.asarray(rows)[oc["row"]]
             cs = c[np.isin(c["row"], rows)]
-            C.check_candidates(cs, oc, 7.0, lambda row, t: snr[rows.index(row), t - toff])
+            C.check_candidates(cs, oc, 7.0, lambda row, t: snr[rows.index(row), t - toff], wr)
         print("beam %d rows %s ok" % (b, rows), flush=True)
 
 
@@ -200,7 +206,7 @@ def test_server_with_dedisp_matches_streaming_oracle():
             oc = oracle.select(snr, widx, W, thr, t_offset=toff)
             r, c = by[(b, k)]
             assert r["status"] == 0 and r["t_offset"] == toff, (b, k, r["t_offset"], toff)
-            C.check_candidates(c, oc, thr, lambda row, t: snr[row, t - toff])
+            C.check_candidates(c, oc, thr, lambda row, t: snr[row, t - toff], C.width_rule(view, W, st, t_offset=toff))
             n_found += len(c)
             prev = np.concatenate([prev, seg], axis=1) if prev is not None else seg
         assert n_found > 0

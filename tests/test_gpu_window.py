@@ -116,4 +116,5 @@ def test_window_matches_oracle_ska_widths():
     o = oracle.detect(x64, W, thr, sigma_mode="auto", kappa=1.0)
     C.check_stats(g["stats"].cpu().numpy(), o["stats"], True)
     C.check_snr_widx(x64, W, g["snr"].cpu().numpy(), g["widx"].cpu().numpy(), o["snr"], o["widx"], o["stats"])
-    C.check_candidates(g["cands"], o["cands"], thr, lambda r, t: o["snr"][r, t])
+    C.check_candidates(g["cands"], o["cands"], thr, lambda r, t: o["snr"][r, t],
+                       C.width_rule(x64, W, o["stats"]))
