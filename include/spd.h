@@ -28,7 +28,8 @@
  *     and the call returns without synchronising.  A launch failure reported
  *     by the HIP runtime returns SPD_E_DEVICE.
  *   - None of these entry points allocates device memory.  Scratch space is
- *     the caller's `workspace`, sized by spd_workspace_bytes().
+ *     the caller's `workspace`, sized by spd_workspace_bytes(), or for
+ *     spd_detect_static a fixed array inside the library.
  *   - Calls are re-entrant; calls on different streams may overlap as long as
  *     they do not share output or workspace buffers.
  *   - Readings of the paper (all shared with the CPU oracle):
@@ -258,6 +259,27 @@ spd_status spd_detect(const spd_plane* x, const spd_params* p, spd_row_stats* st
                       spd_candidate* cand, int64_t cand_capacity, int64_t* cand_count,
                       void* workspace, size_t workspace_bytes, int32_t row_chunks,
                       void* stream, void* aux_stream);
+
+/*
+ * spd_detect_static -- spd_detect without a workspace, for callers that cannot
+ *   allocate device memory: code under HIP graph capture, tight serving loops,
+ *   harnesses that forbid allocation.  The statistics pass keeps its block
+ *   partials in a fixed device array inside the library (4 MiB per device,
+ *   enough for 87,381 (row, block) partials; a 4,096 x 2^20 plane uses
+ *   65,536) instead of a caller workspace.  Results equal those of
+ *   spd_detect(x, p, stats, ..., row_chunks = 1) with the same arguments.
+ *   The call allocates nothing: the first call on a device looks up that
+ *   device's copy of the array and keeps its address.
+ *   Arguments as in spd_detect, minus workspace, row_chunks and aux_stream;
+ *   both steps run on `stream`.  A plane whose partials exceed the array
+ *   returns SPD_E_UNSUPPORTED (use spd_detect with a workspace).
+ *   Every call on one device shares that device's array and leaves its
+ *   partials there: calls that overlap on one GPU (other streams or threads)
+ *   race and must be serialised by the caller.
+ */
+spd_status spd_detect_static(const spd_plane* x, const spd_params* p, spd_row_stats* stats,
+                             float* snr_out, uint8_t* widx_out, int64_t out_stride, int64_t t_offset,
+                             spd_candidate* cand, int64_t cand_capacity, int64_t* cand_count, void* stream);
 
 /*
  * cluster_candidates -- peak-finding over a candidate list, a step after

@@ -108,6 +108,8 @@ def load():
         lib.spd_detect.argtypes = [P(SpdPlane), P(SpdParams), vp, vp, vp, i64, i64, vp, i64, vp, vp,
                                    ctypes.c_size_t, i32, vp, vp]
         lib.spd_detect.restype = ctypes.c_int
+        lib.spd_detect_static.argtypes = [P(SpdPlane), P(SpdParams), vp, vp, vp, i64, i64, vp, i64, vp, vp]
+        lib.spd_detect_static.restype = ctypes.c_int
         lib.boxcar_snr_dit.argtypes = [P(SpdPlane), P(SpdParams), i32, vp, vp, vp, i64, i64, vp, i64, vp, vp]
         lib.cluster_candidates.argtypes = [vp, i64, i64, i64, i64, vp, i64, vp, i32, i32, vp, i64, vp, vp]
         lib.cluster_candidates.restype = ctypes.c_int
@@ -379,6 +381,30 @@ def spd_detect(x: torch.Tensor, params: Params, *, scale=None, zero=None, stats:
                           cand_count.data_ptr() if cand_count is not None else None,
                           workspace.data_ptr(), workspace.numel() * workspace.element_size(), int(row_chunks),
                           _stream(stream), aux))
+    return stats
+
+
+def spd_detect_static(x: torch.Tensor, params: Params, *, scale=None, zero=None,
+                      stats: Optional[torch.Tensor] = None, snr: Optional[torch.Tensor] = None,
+                      widx: Optional[torch.Tensor] = None, out_stride: Optional[int] = None, t_offset: int = 0,
+                      cand: Optional[torch.Tensor] = None, cand_count: Optional[torch.Tensor] = None,
+                      stream=None) -> torch.Tensor:
+    """spd_detect with the statistics pass's partials in the library's fixed
+    device array: the call itself allocates nothing (pass ``stats`` to keep
+    the wrapper from allocating it).  Calls that overlap on one device race.
+    Returns stats."""
+    lib = load()
+    pl = plane_struct(x, scale, zero)
+    if stats is None:
+        stats = torch.empty((params.n_units(x.shape[0]), STATS_FIELDS), dtype=torch.float64, device=x.device)
+    if out_stride is None:
+        out_stride = snr.stride(0) if snr is not None else (widx.stride(0) if widx is not None else 0)
+    cap = cand.shape[0] if cand is not None else 0
+    _check(lib.spd_detect_static(ctypes.byref(pl), ctypes.byref(params.c), stats.data_ptr(),
+                                 snr.data_ptr() if snr is not None else None,
+                                 widx.data_ptr() if widx is not None else None, int(out_stride), int(t_offset),
+                                 cand.data_ptr() if cand is not None else None, int(cap),
+                                 cand_count.data_ptr() if cand_count is not None else None, _stream(stream)))
     return stats
 
 

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -348,6 +349,38 @@ spd_status detect_events(hipEvent_t** out)
     return SPD_OK;
 }
 
+// Scratch of spd_detect_static: the statistics pass's block partials, in a
+// device array of fixed size instead of a caller workspace.  Each device that
+// runs the entry point holds its own copy until the process ends.  In host
+// code `scratch` names a host-side stand-in, so kernels only ever receive the
+// device address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchBytes = (size_t)4 << 20;
+static __device__ __align__(256) double scratch[kStaticScratchBytes / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];
+
+// Device address of the current device's scratch array, looked up once per
+// device (with that device current) and kept.
+spd_status static_scratch(double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return device_status(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(SPD_E_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return device_status(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr || ((uintptr_t)ptr) % 256) return fail(SPD_E_DEVICE, "scratch address %p not 256-byte aligned", ptr);
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (double*)g_scratch_ptr[dev];
+    return SPD_OK;
+}
+
 }  // namespace spd
 
 using namespace spd;
@@ -446,6 +479,35 @@ spd_status spd_detect(const spd_plane* x, const spd_params* p, spd_row_stats* st
         if ((st = enqueue_boxcar(&sub, stats + r0, bp, r0, rc, s))) return st;
     }
     return SPD_OK;
+}
+
+spd_status spd_detect_static(const spd_plane* x, const spd_params* p, spd_row_stats* stats, float* snr_out,
+                             uint8_t* widx_out, int64_t out_stride, int64_t t_offset, spd_candidate* cand,
+                             int64_t cand_capacity, int64_t* cand_count, void* stream)
+{
+    clear_error();
+    spd_status st;
+    if ((st = check_params(p)) || (st = check_plane(x, p))) return st;
+    if (!stats) return fail(SPD_E_INVALID, "stats is NULL");
+    const MsdLayout m = msd_layout(x);
+    if (m.ws_bytes > kStaticScratchBytes)
+        return fail(SPD_E_UNSUPPORTED,
+                    "plane needs %zu bytes of block partials, more than the %zu-byte static scratch "
+                    "(%lld rows x %lld blocks); use spd_detect with a workspace",
+                    m.ws_bytes, kStaticScratchBytes, (long long)x->n_rows, (long long)m.nblk);
+    if ((uint64_t)x->n_rows * (uint64_t)m.nblk * 256u > kMaxGridItems)
+        return fail(SPD_E_UNSUPPORTED, "plane too large for one launch");
+    BoxcarPlan bp;
+    if ((st = plan_boxcar(x, p, stats, snr_out, widx_out, out_stride, t_offset, cand, cand_capacity, cand_count,
+                          bp)))
+        return st;
+    double* part = nullptr;
+    if ((st = static_scratch(&part))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e;
+    if (cand && (e = launch_zero_count(cand_count, s)) != hipSuccess) return device_status(e, "count reset launch");
+    if ((st = enqueue_msd(x, p, 0, false, nullptr, stats, part, m, s))) return st;
+    return enqueue_boxcar(x, stats, bp, 0, x->n_rows, s);
 }
 
 spd_status boxcar_snr_dit(const spd_plane* x, const spd_params* p, int32_t levels, const spd_row_stats* stats,

@@ -127,6 +127,34 @@ def test_detect_validation(lib):
         assert msg in _err(lib), (kw, _err(lib))
 
 
+def test_detect_static_validation(lib):
+    """The allocation-free spd_detect rejects, before any HIP call, what
+    spd_detect rejects, and planes whose block partials exceed its 4 MiB
+    device array (87,381 partials of 48 bytes)."""
+    p = B.Params([1, 2, 4, 8], 5.0)
+    pl = _plane()
+
+    def call(stats=FAKE, snr=FAKE, stride=1000, cand=None, cap=0, count=None, params=p, plane=pl):
+        return lib.spd_detect_static(ctypes.byref(plane), ctypes.byref(params.c), stats, snr, None, stride, 0,
+                                     cand, cap, count, FAKE)
+
+    for kw, code, msg in [(dict(stats=None), 1, "stats"), (dict(snr=None), 1, "no output"),
+                          (dict(stride=10), 1, "out_stride"), (dict(snr=None, cand=FAKE, cap=5), 1, "cand_count"),
+                          (dict(plane=_plane(cols=1000, stride=999)), 1, "row_stride"),
+                          (dict(params=B.Params([1, 3, 2], 5.0)), 1, "strictly")]:
+        assert call(**kw) == code, kw
+        assert msg in _err(lib), (kw, _err(lib))
+    # 8,192 rows x 2^20 columns: 16 blocks of 65,536 per row, 131,072 partials = 6 MiB
+    big = _plane(rows=8192, cols=1 << 20, stride=1 << 20)
+    assert lib.spd_workspace_bytes(ctypes.byref(big), ctypes.byref(p.c)) == 8192 * 16 * 48
+    assert call(plane=big, stride=1 << 20) == 2
+    assert "static scratch" in _err(lib)
+    # 4,096 rows x 2^20 (65,536 partials, 3 MiB) passes the size check; with
+    # stats missing it still stops on the host
+    ok = _plane(rows=4096, cols=1 << 20, stride=1 << 20)
+    assert call(plane=ok, stride=1 << 20, stats=None) == 1 and "stats" in _err(lib)
+
+
 def test_dit_validation(lib):
     import oracle
     for lv in range(5):
