@@ -278,6 +278,12 @@ spd_status plan_boxcar(const spd_plane* x, const spd_params* p, const spd_row_st
     ba.scope = p->scope;
     ba.nout = nout;
     ba.tiles_per_row = (nout + (int64_t)bp.waves * 64 * X - 1) / ((int64_t)bp.waves * 64 * X);
+    // the list 1..n (n <= 16): streaming form ("window": the register-window tiles)
+    if (bp.wp.win == 2 && !(form && strcmp(form, "window") == 0)) {
+        bp.wp.win = 4;
+        bp.waves = 4;
+        ba.tiles_per_row = (nout + bp.waves * kStreamRun - 1) / (bp.waves * kStreamRun);
+    }
     ba.snr = snr_out;
     ba.widx = widx_out;
     ba.out_stride = out_stride;
@@ -287,7 +293,8 @@ spd_status plan_boxcar(const spd_plane* x, const spd_params* p, const spd_row_st
     ba.cand_count = cand_count;
     ba.threshold = p->threshold;
     ba.out_vec = ((snr_out && (uintptr_t)snr_out % 16 == 0 && out_stride % 4 == 0) ? 1u : 0u) |
-                 ((widx_out && (uintptr_t)widx_out % 8 == 0 && out_stride % 8 == 0) ? 2u : 0u);
+                 ((widx_out && (uintptr_t)widx_out % 8 == 0 && out_stride % 8 == 0) ? 2u : 0u) |
+                 ((widx_out && (uintptr_t)widx_out % 4 == 0 && out_stride % 4 == 0) ? 4u : 0u);
     const uint64_t ntiles = (uint64_t)x->n_rows * (uint64_t)ba.tiles_per_row;
     if (ntiles * 64u * (uint64_t)bp.waves > kMaxGridItems) return fail(SPD_E_UNSUPPORTED, "plane too large for one launch");
     return SPD_OK;

@@ -1153,4 +1153,276 @@ __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Sec. 2.3 / Algorithm 1, streaming form of the short lists 1..n (n <= 16)
+// ---------------------------------------------------------------------------
+//
+// A wave owns a run of kStreamRun consecutive starts of one row and walks it
+// in steps of kStreamStep.  Lane l takes the 4 consecutive starts 4l..4l+3 of
+// a step (block 0) and 256+4l..256+4l+3 (block 1), so its outputs are one
+// 16-byte SNR store and one 4-byte width-index store per block, and a store
+// instruction of the wave covers consecutive addresses.  A block needs the
+// samples 4l .. 4l+n+2 of its step: five aligned 16-byte LDS reads.
+//
+// The wave's LDS holds two buffers of kStreamBuf floats: x' = x - mean of one
+// step and the first 16 samples of the next.  While a step is evaluated the
+// samples of the step after next are in flight from HBM; the step in
+// registers is written to the other buffer before the evaluation starts, so
+// no work-group barrier is needed and every sample is read from HBM once.
+// The coefficients 1/sigma_w are wave-uniform (scalar registers).
+
+template <int DT> struct RawT;
+template <> struct RawT<SPD_F32> { using T = float4; };
+template <> struct RawT<SPD_F16> { using T = uint2; };
+template <> struct RawT<SPD_U8> { using T = uint32_t; };
+
+// Four samples from column c as stored; past the end of the row the value is
+// unspecified (those samples only reach windows that start past the last
+// valid start).  `vec`: the row allows aligned vector loads at c.
+template <int DT>
+__device__ __forceinline__ typename RawT<DT>::T raw4(const Loader<DT>& ld, int64_t c, int64_t ncols, bool vec)
+{
+    using T = typename RawT<DT>::T;
+    if (vec && c + 3 < ncols) return *(const T*)(ld.row + c);
+    if constexpr (DT == SPD_F32) {
+        float4 v;
+        v.x = c < ncols ? ld.row[c] : 0.f;
+        v.y = c + 1 < ncols ? ld.row[c + 1] : 0.f;
+        v.z = c + 2 < ncols ? ld.row[c + 2] : 0.f;
+        v.w = c + 3 < ncols ? ld.row[c + 3] : 0.f;
+        return v;
+    } else if constexpr (DT == SPD_F16) {
+        const uint16_t* h = (const uint16_t*)ld.row;
+        uint32_t e[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) e[k] = c + k < ncols ? (uint32_t)h[c + k] : 0u;
+        return make_uint2(e[0] | (e[1] << 16), e[2] | (e[3] << 16));
+    } else {
+        uint32_t u = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u |= (c + k < ncols ? (uint32_t)ld.row[c + k] : 0u) << (8 * k);
+        return u;
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ float4 cvt4(const Loader<DT>& ld, typename RawT<DT>::T u)
+{
+    if constexpr (DT == SPD_F32) {
+        return u;
+    } else if constexpr (DT == SPD_F16) {
+        const float2 a = __half22float2(*reinterpret_cast<const __half2*>(&u.x));
+        const float2 b = __half22float2(*reinterpret_cast<const __half2*>(&u.y));
+        return make_float4(a.x, a.y, b.x, b.y);
+    } else {
+        return make_float4(ld.deq(u & 255u), ld.deq((u >> 8) & 255u), ld.deq((u >> 16) & 255u), ld.deq(u >> 24));
+    }
+}
+
+__device__ __forceinline__ void put_shifted(float* d, float4 v, float mu_hi, float mu_lo)
+{
+    *(float4*)d = make_float4((v.x - mu_hi) - mu_lo, (v.y - mu_hi) - mu_lo, (v.z - mu_hi) - mu_lo,
+                              (v.w - mu_hi) - mu_lo);
+}
+
+// The 4 starts of one block: SNR of widths 1..NS (entries j >= n carry a NaN
+// coefficient, which max ignores and which never compares equal), their
+// highest value and the index of the first width reaching it.  `src` points
+// at the block's first start in LDS.  `nomatch` is the index reported when no
+// SNR equals the maximum (NaN input only): n-1 for the caller's n.
+template <int NS>
+__device__ __forceinline__ void short_block(const float* src, const float (&a)[NS], int nomatch, float (&sv)[4],
+                                            uint32_t& packed)
+{
+    constexpr int NV = 4 + NS - 1;
+    constexpr int NR = (NV + 3) / 4;
+    float v[4 * NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        const float4 f = *(const float4*)(src + 4 * q);
+        v[4 * q] = f.x; v[4 * q + 1] = f.y; v[4 * q + 2] = f.z; v[4 * q + 3] = f.w;
+    }
+    packed = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        float b = v[i], s[NS];
+        s[0] = __fmul_rn(b, a[0]);
+#pragma unroll
+        for (int j = 1; j < NS; ++j) {
+            b = __fadd_rn(b, v[i + j]);
+            s[j] = __fmul_rn(b, a[j]);
+        }
+        uint32_t idx;
+        float m;
+        if constexpr (NS == 16) {
+            // the half holding the first maximiser, then a chain over its 8 SNRs;
+            // with no match (NaN) the upper half is taken and the chain's start
+            // value nomatch - 8 gives nomatch
+            float mlo = s[0], mhi = s[8];
+#pragma unroll
+            for (int j = 1; j < 8; ++j) { mlo = fmaxf(mlo, s[j]); mhi = fmaxf(mhi, s[8 + j]); }
+            m = fmaxf(mlo, mhi);
+            const bool hi = !(mlo == m);
+            int c = nomatch - 8;
+#pragma unroll
+            for (int j = 7; j >= 0; --j) c = ((hi ? s[8 + j] : s[j]) == m) ? j : c;
+            idx = (uint32_t)(c + (hi ? 8 : 0));
+        } else {
+            m = s[0];
+#pragma unroll
+            for (int j = 1; j < NS; ++j) m = fmaxf(m, s[j]);
+            int c = nomatch;
+#pragma unroll
+            for (int j = NS - 1; j >= 0; --j) c = (s[j] == m) ? j : c;
+            idx = (uint32_t)c;
+        }
+        sv[i] = m;
+        packed |= idx << (8 * i);
+    }
+}
+
+// One candidate per (start, lane) with snr >= threshold among the lane's
+// `cnt` starts beginning at t: one ballot per start index, one atomic per
+// wave and start index that has candidates.
+__device__ __forceinline__ void emit_block_cands(const BoxcarArgs& ba, const WidthPlan& wp, int64_t r, int64_t t,
+                                                 int cnt, const float (&sv)[4], uint32_t packed)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool pred = i < cnt && sv[i] >= ba.threshold;
+        const uint64_t mask = __ballot(pred);
+        if (!mask) continue;
+        const int cntw = __popcll(mask);
+        const int before = __popcll(mask & ((1ull << lane) - 1ull));
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd((unsigned long long*)ba.cand_count, (unsigned long long)cntw);
+        base = __shfl(base, 0);
+        if (pred) {
+            const unsigned long long k = base + (unsigned long long)before;
+            if (k < (unsigned long long)ba.cand_capacity) {
+                spd_candidate cd;
+                cd.row = (int32_t)r + ba.row0;
+                cd.width = wp.width[(packed >> (8 * i)) & 255u];
+                cd.t = t + i + ba.t_offset;
+                cd.snr = sv[i];
+                cd.beam = ba.beam;
+                ba.cand[k] = cd;
+            }
+        }
+    }
+}
+
+// Starts [t_begin, min(t_begin + kStreamRun, nout)) of row r by one wave; buf
+// is the wave's 2*kStreamBuf floats of LDS (16-byte aligned).  FAST: the row
+// allows aligned vector loads and every sample the run reads lies inside it,
+// so loads need no bounds (the other runs take raw4's checked path).
+template <int DT, int NS, bool FAST>
+__device__ void boxcar_run_short(const PlaneArg& pl, bool vec, int64_t r, int64_t t_begin, const spd_row_stats& st,
+                                 const BoxcarArgs& ba, const WidthPlan& wp, float* buf)
+{
+    using Raw = typename RawT<DT>::T;
+    const int lane = threadIdx.x & 63;
+    const int64_t nout = ba.nout;
+    const int64_t t_end = min(t_begin + kStreamRun, nout);
+    const int steps = (int)((t_end - t_begin + kStreamStep - 1) / kStreamStep);
+
+    // coefficients 1/sigma_w (Eq. sd02 / sd03): lane j computes width j+1 in FP64
+    float a[NS];
+    {
+        const bool zero_var = (st.flags & SPD_FLAG_ZERO_VAR) != 0;
+        float cf = __int_as_float(0x7fc00000);
+        if (lane < wp.n) {
+            const double w = (double)(lane + 1);
+            const double sw = sqrt(w) * st.sigma + (w - 1.0) * st.lin_coef;
+            cf = (zero_var || !(sw > 0.0)) ? 0.f : (float)(1.0 / sw);
+        }
+#pragma unroll
+        for (int j = 0; j < NS; ++j) a[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cf), j));
+    }
+    const int nomatch = wp.n - 1;
+    const float mu_hi = (float)st.mean;
+    const float mu_lo = (float)(st.mean - (double)mu_hi);
+    const Loader<DT> ld(pl, r);
+    const int64_t ncols = pl.n_cols;
+    // lane l's two loads of the step at column c: c + 4l and c + 256 + 4l
+    const auto* rowp = ld.row + t_begin;                    // wave-uniform
+    const int lo = 4 * lane;
+    auto load = [&](int64_t off) -> Raw {                   // columns t_begin + off .. + 3
+        if constexpr (FAST) return *(const Raw*)(rowp + off);
+        else return raw4<DT>(ld, t_begin + off, ncols, vec);
+    };
+
+    float* A = buf;
+    float* Bv = buf + kStreamBuf;
+    // prologue: step 0 into A, step 1 in registers, its first 16 samples into A's tail
+    {
+        const Raw s0 = load(lo), s1 = load(lo + 256);
+        put_shifted(A + lo, cvt4<DT>(ld, s0), mu_hi, mu_lo);
+        put_shifted(A + 256 + lo, cvt4<DT>(ld, s1), mu_hi, mu_lo);
+    }
+    Raw r0{}, r1{};
+    if (steps > 1) {
+        r0 = load(kStreamStep + lo);
+        r1 = load(kStreamStep + 256 + lo);
+    } else if (lane < 4) {
+        r0 = load(kStreamStep + lo);
+    }
+    if (lane < 4) put_shifted(A + kStreamStep + lo, cvt4<DT>(ld, r0), mu_hi, mu_lo);
+    wave_sync();
+
+    float* so = ba.snr ? ba.snr + r * ba.out_stride + t_begin : nullptr;     // wave-uniform bases
+    uint8_t* wo = ba.widx ? ba.widx + r * ba.out_stride + t_begin : nullptr;
+    const bool vs = (ba.out_vec & 1u) != 0, vw = (ba.out_vec & 4u) != 0;
+    for (int k = 0; k < steps; ++k) {
+        const int ks = k * kStreamStep;
+        // step k+1 (in registers) into the other buffer; step k+2 in flight
+        if (k + 1 < steps) {
+            put_shifted(Bv + lo, cvt4<DT>(ld, r0), mu_hi, mu_lo);
+            put_shifted(Bv + 256 + lo, cvt4<DT>(ld, r1), mu_hi, mu_lo);
+        }
+        if (k + 2 < steps) {
+            r0 = load(ks + 2 * kStreamStep + lo);
+            r1 = load(ks + 2 * kStreamStep + 256 + lo);
+        } else if (k + 2 == steps && lane < 4) {
+            r0 = load(ks + 2 * kStreamStep + lo);
+        }
+        // step k from A, one block after the other
+        const bool whole = t_begin + ks + kStreamStep <= t_end;           // wave-uniform
+#pragma unroll
+        for (int blk = 0; blk < 2; ++blk) {
+            float sv[4];
+            uint32_t pk;
+            short_block<NS>(A + 256 * blk + lo, a, nomatch, sv, pk);
+            const int off = ks + 256 * blk + lo;                            // start t_begin + off
+            int cnt = 4;
+            if (!whole) {
+                const int64_t left = t_end - (t_begin + off);
+                cnt = left <= 0 ? 0 : (left >= 4 ? 4 : (int)left);
+            }
+            if (ba.cand && __ballot(fmaxf(fmaxf(sv[0], sv[1]), fmaxf(sv[2], sv[3])) >= ba.threshold))
+                emit_block_cands(ba, wp, r, t_begin + off, cnt, sv, pk);
+            if (whole && vs && so) {
+                *(float4*)(so + off) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+            } else if (so) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (i < cnt) so[off + i] = sv[i];
+            }
+            if (whole && vw && wo) {
+                *(uint32_t*)(wo + off) = pk;
+            } else if (wo) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (i < cnt) wo[off + i] = (uint8_t)(pk >> (8 * i));
+            }
+        }
+        // the next step's tail: the first 16 samples of step k+2
+        if (k + 1 < steps && lane < 4) put_shifted(Bv + kStreamStep + lo, cvt4<DT>(ld, r0), mu_hi, mu_lo);
+        wave_sync();
+        float* tmp = A; A = Bv; Bv = tmp;
+    }
+}
+
 }  // namespace spd

@@ -20,6 +20,15 @@ constexpr int kWinX = 8;           // consecutive starts per lane in the registe
 constexpr int kSelCols = 4096;     // columns per work-group of the standalone threshold (16 per lane)
 constexpr int kWinTableFloats = (kMaxWidthsPadded + 2 * kMaxGroups + 63) / 64 * 64;
 
+// Streaming form of the short lists 1..n (n <= 16): a wave walks a run of
+// kStreamSteps steps of kStreamStep consecutive starts of one row; lane l
+// takes starts 4l..4l+3 and 256+4l..256+4l+3 of each step.  Its LDS holds two
+// buffers of one step's samples plus the next 16.
+constexpr int kStreamStep = 512;
+constexpr int kStreamSteps = 16;
+constexpr int64_t kStreamRun = (int64_t)kStreamStep * kStreamSteps;
+constexpr int kStreamBuf = kStreamStep + 16;
+
 // Register-window form: logical element m of a wave's LDS array is stored at
 // m + m/8 (one pad float after every 8).
 __host__ __device__ constexpr int win_phys(int m) { return m + (m >> 3); }
@@ -58,7 +67,8 @@ struct WidthPlan {
     int32_t arr_gap[kMaxArrays];
     int32_t unit_counts;    // 1 when every cnt_i == 1
     int32_t win;            // register-window form: 0 none, 1 groups of 8, 2 the list 1..n (n <= 16),
-                            // 3 the decimated search (1..16, then 2^l*(9..16))
+                            // 3 the decimated search (1..16, then 2^l*(9..16)),
+                            // 4 the list 1..n (n <= 16) in the streaming form
     uint32_t off[kMaxWidthsPadded];    // element offset of the first read: array base + w_{i-1}
     uint32_t cg[kMaxWidthsPadded];     // cnt | (gap << 16)
     int16_t width[kMaxWidthsPadded];   // w_i
@@ -92,7 +102,8 @@ struct BoxcarArgs {
     int64_t* cand_count;
     float threshold;
     uint32_t beam;          // stored in each candidate (batched runs)
-    uint32_t out_vec;       // bit 0: snr rows allow 16-byte stores; bit 1: widx rows allow 8-byte stores
+    uint32_t out_vec;       // bit 0: snr rows allow 16-byte stores; bit 1: widx rows allow 8-byte stores;
+                            // bit 2: widx rows allow 4-byte stores
     uint32_t reserved;
 };
 

@@ -1,11 +1,15 @@
 """The register-window form of the boxcar kernel (8 consecutive starts per
-lane, the group's reads held in registers) against the strided form (starts
-64 apart per lane, one LDS read per width and start).
+lane, the group's reads held in registers) and, for the lists 1..n with
+n <= 16, the streaming form (a wave walks a long run of one row, 4
+consecutive starts per lane per block) against the strided form (starts 64
+apart per lane, one LDS read per width and start).
 
-Both run the same running sums in the same order on the same staged values
+All run the same running sums in the same order on the same staged values
 and apply the same first-maximiser rule, so SNRs, width indices and the
-candidate set must agree bit for bit.  The form is chosen per call;
-SPD_BOXCAR_FORM=strided forces the strided one.
+candidate set must agree bit for bit.  The form is chosen per call (the
+default: streaming for 1..n, n <= 16, else register-window where the list
+allows it); SPD_BOXCAR_FORM=window forces the register-window tiles and
+SPD_BOXCAR_FORM=strided the strided one.
 """
 import os
 
@@ -33,14 +37,17 @@ def run_form(form, x, p, stats, stride_pad=0, scale=None, zero=None):
     cand = B.new_candidates(1 << 18, DEV)
     cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
     old = os.environ.get("SPD_BOXCAR_FORM")
-    os.environ["SPD_BOXCAR_FORM"] = form
+    if form is None:
+        os.environ.pop("SPD_BOXCAR_FORM", None)
+    else:
+        os.environ["SPD_BOXCAR_FORM"] = form
     try:
         B.boxcar_snr(x, p, stats, scale=scale, zero=zero, snr=snr[:, :nout], widx=widx[:, :nout],
                      out_stride=stride, cand=cand, cand_count=cnt)
         torch.cuda.synchronize()
     finally:
         if old is None:
-            del os.environ["SPD_BOXCAR_FORM"]
+            os.environ.pop("SPD_BOXCAR_FORM", None)
         else:
             os.environ["SPD_BOXCAR_FORM"] = old
     n = int(cnt.item())
@@ -55,14 +62,15 @@ def compare(x, widths, thr, *, mode="sqrtn", scope="row", stride_pad=0, scale=No
         tuple(x.shape), x.dtype, len(widths), widths[-1], mode, scope, stride_pad), flush=True)
     p = B.Params(widths, thr, scope, mode, 1.0)
     stats = B.msd_compute(x, p, scale=scale, zero=zero)
-    a = run_form("window", x, p, stats, stride_pad, scale, zero)
     b = run_form("strided", x, p, stats, stride_pad, scale, zero)
     nout = x.shape[1] - p.nmax + 1
-    assert torch.equal(a[0], b[0]), "snr differs"
-    assert torch.equal(a[1], b[1]), "width indices differ"
-    assert a[2] == b[2], "candidate sets differ (%d vs %d)" % (len(a[2]), len(b[2]))
-    if stride_pad:
-        assert torch.all(a[0][:, nout:] == -3.0) and torch.all(a[1][:, nout:] == 250)
+    for form in ("window", None):
+        a = run_form(form, x, p, stats, stride_pad, scale, zero)
+        assert torch.equal(a[0], b[0]), "snr differs (%s)" % form
+        assert torch.equal(a[1], b[1]), "width indices differ (%s)" % form
+        assert a[2] == b[2], "candidate sets differ (%s: %d vs %d)" % (form, len(a[2]), len(b[2]))
+        if stride_pad:
+            assert torch.all(a[0][:, nout:] == -3.0) and torch.all(a[1][:, nout:] == 250)
     return a
 
 
@@ -103,6 +111,29 @@ def test_window_ragged_edges_and_zero_variance():
     x[1] = 1.5
     a = compare(x, SKA, 3.0)
     assert torch.all(a[0][1] == 0) and torch.all(a[1][1] == 0)
+
+
+@pytest.mark.parametrize("L", [15, 16, 17, 511, 527, 528, 8192 + 15, 8192 + 16, 4 * 8192 + 15, 4 * 8192 + 16 + 700,
+                               5 * 8192 * 4 + 1234])
+@pytest.mark.parametrize("n", [1, 7, 8, 9, 16])
+def test_stream_runs_steps_and_row_ends(L, n):
+    """Row lengths around the streaming form's step (512 starts), run (8,192)
+    and work-group (32,768) boundaries, for every list length class."""
+    if L < n:
+        pytest.skip("row shorter than the widest boxcar")
+    rng = np.random.default_rng(1000 + L + n)
+    x = torch.from_numpy(rng.standard_normal((3, L)).astype(np.float32) * 2 + 0.5).to(DEV)
+    compare(x, list(range(1, n + 1)), 2.0)
+
+
+def test_stream_unaligned_plane_rows():
+    """Rows that do not start on a 4-element boundary take the checked loads."""
+    rng = np.random.default_rng(5)
+    base = torch.from_numpy(rng.standard_normal((4, 40001)).astype(np.float32)).to(DEV)
+    compare(base[:, 1:], list(range(1, 17)), 2.5)
+    compare(base[:, 3:], list(range(1, 9)), 2.5, mode="linear")
+    h = synth.quantize_f16(base)
+    compare(h[:, 1:], list(range(1, 17)), 2.5)
 
 
 def test_window_matches_oracle_ska_widths():
