@@ -26,15 +26,19 @@ sys.path.insert(0, ROOT)
 
 METRIC = "boxcar-SNR GSamples/s (DM×time) & % HBM roofline; p99 chunk latency"
 HBM_PEAK_GBS = 8000.0
-# FP32 vector issue: 256 CUs x 4 SIMDs, each issuing up to two wave64 VALU
-# instructions per 4 clocks (64 lanes over 16-lane units, dual issue), at
-# 2.4 GHz: 78.6 T lane-ops/s, the published 157.3 TFLOP/s FP32 vector peak
-# counted as one op per FMA.  This kernel's add, mul and max are one op each.
-VALU_PEAK_TOPS = 256 * 4 * 2 * 64 / 4 * 2.4e9 / 1e12
-OPS_PER_EVAL = 3          # boxcar add, SNR multiply, running-max compare per (t, w)
+# Published MI355X FP32 vector peak (an FMA counts as two flops).  The
+# boxcar/SNR work is 3 FP32 operations per (start, width): the boxcar add,
+# the SNR multiply and the compare against the running maximum.
+FP32_PEAK_TFLOPS = 157.3
+FLOPS_PER_EVAL = 3
+# VALU issue ceiling: 256 CUs x 4 SIMDs, each issuing at most two wave64 VALU
+# instructions per 4 clocks, at 2.4 GHz = 78.6 T lane-instructions/s.  Against
+# it the kernel's measured instructions per evaluation (rocprofv3
+# SQ_INSTS_VALU, committed under profiles/) are reported.
+ISSUE_CEILING_T = 256 * 4 * 2 * 64 / 4 * 2.4e9 / 1e12
 
 
-BOXCAR_SOURCES = ("spd_device.h", "spd_kernels.hip", "spd_kernels.h", "spd_internal.h")
+BOXCAR_SOURCES = ("spd_device.h", "spd_kernels.hip", "spd_kernels.h", "spd_internal.h", "spd_stream.hip")
 CLUSTER_SOURCES = ("spd_cluster.hip",)
 DEDISP_SOURCES = ("spd_dedisp.hip",)
 
@@ -113,9 +117,41 @@ def oracle_rows_baseline(x, widths, sigma_mode, target_s, *, strides=None, label
             "cpu_model": cpu_model(), "rows": nrows, "seconds": round(dt, 3)}
 
 
-def boxcar_kernel_name() -> str:
+def boxcar_kernel_name(workload: str = "ska") -> str:
     """The one-plane boxcar kernel the library launches for the SKA and 1..16 lists."""
-    return "boxcar_kernel" if os.environ.get("SPD_BOXCAR_FORM") == "strided" else "boxcar_win_kernel"
+    form = os.environ.get("SPD_BOXCAR_FORM")
+    if form == "strided":
+        return "boxcar_kernel"
+    return "boxcar_stream_fast_kernel" if workload == "ska16" and form != "window" else "boxcar_win_kernel"
+
+
+def load_valu(workload: str):
+    """Counter-measured VALU lane-instructions per evaluation of the workload's
+    boxcar kernel, if the committed counters were taken on the current sources."""
+    try:
+        e = json.load(open(os.path.join(ROOT, "profiles", "valu_counters.json"))).get(workload)
+    except (OSError, ValueError):
+        return None
+    if not e or e.get("kernel_sha") != kernel_source_sha():
+        return None
+    return e
+
+
+def alu_roofline(evals: int, ms: float, workload: str) -> dict:
+    """FP32 roofline of a boxcar launch against the published peak, with the
+    VALU issue ceiling beside it."""
+    achieved = evals * FLOPS_PER_EVAL / (ms * 1e-3) / 1e12
+    out = {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+           "frac": round(achieved / FP32_PEAK_TFLOPS, 4)}
+    v = load_valu(workload)
+    issue = {"peak": round(ISSUE_CEILING_T, 2), "unit": "T VALU lane-instructions/s",
+             "valu_lane_instr_per_eval": v["valu_lane_instr_per_eval"] if v else None}
+    if v:
+        a = v["valu_lane_instr_per_eval"] * evals / (ms * 1e-3) / 1e12
+        issue.update({"achieved": round(a, 3), "frac": round(a / ISSUE_CEILING_T, 4),
+                      "counter_clock_ghz": v.get("clock_ghz")})
+    out["issue_ceiling"] = issue
+    return out
 
 
 def load_traffic(workload: str):
@@ -259,7 +295,7 @@ def main():
     samples = R * L
     value = samples * args.steps / wall / 1e9
     evals = R * nout * len(W)
-    box_tops = evals * OPS_PER_EVAL / (box_ms * 1e-3) / 1e12
+    alu = alu_roofline(evals, box_ms, args.workload)
     box_bytes = R * L * 4 + R * nout * 5
     msd_bytes = R * L * 4
     out = {
@@ -271,10 +307,8 @@ def main():
                    "cols": L, "widths": "1..16,18..256/2" if args.workload == "ska" else "1..16",
                    "n_widths": len(W), "threshold": cfg["threshold"], "sigma_mode": "auto", "kappa": 1.0,
                    "scope": "row", "outputs": "snr f32 + width u8 per sample, fused candidate list"},
-        "roofline": {"bound": "alu", "achieved": round(box_tops, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                     "unit": "TFLOP/s", "frac": round(box_tops / VALU_PEAK_TOPS, 4),
-                     "traffic": load_traffic(args.workload), "kernel": boxcar_kernel_name(),
-                     "work_per_launch": "%d (t,w) evaluations x %d FP32 ops" % (evals, OPS_PER_EVAL)},
+        "roofline": dict(alu, traffic=load_traffic(args.workload), kernel=boxcar_kernel_name(args.workload),
+                         work_per_launch="%d (t,w) evaluations x %d FP32 flops" % (evals, FLOPS_PER_EVAL)),
         "step_ms_events": {"p10": round(float(np.percentile(step_ms, 10)), 3),
                            "p50": round(float(np.percentile(step_ms, 50)), 3),
                            "p90": round(float(np.percentile(step_ms, 90)), 3)},
@@ -285,7 +319,7 @@ def main():
             "boxcar_snr": {"ms": round(box_ms, 4), "GSamples/s": round(samples / box_ms / 1e6, 3),
                            "GB/s": round(box_bytes / box_ms / 1e6, 1),
                            "hbm_frac": round(box_bytes / box_ms / 1e6 / HBM_PEAK_GBS, 4),
-                           "valu_frac": round(box_tops / VALU_PEAK_TOPS, 4)},
+                           "fp32_frac": alu["frac"]},
             "select_candidates": {"ms": round(sel_ms, 4), "GB/s": round(sel_bytes / sel_ms / 1e6, 1),
                                   "hbm_frac": round(sel_bytes / sel_ms / 1e6 / HBM_PEAK_GBS, 4),
                                   "n_candidates": sel_n, "same_count_as_fused": sel_n == n_cand,
@@ -306,7 +340,8 @@ def main():
             "unit": "GSamples/s", "ms_per_step": round(w16 / args.steps * 1e3, 3),
             "roofline": {"bound": "hbm", "achieved": round(bb16 / b16 / 1e6, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(bb16 / b16 / 1e6 / HBM_PEAK_GBS, 4),
-                         "traffic": load_traffic("ska16"), "kernel": boxcar_kernel_name()},
+                         "traffic": load_traffic("ska16"), "kernel": boxcar_kernel_name("ska16"),
+                         "alu": alu_roofline(R * (L - 15) * 16, b16, "ska16")},
             "msd_ms": round(m16, 4), "boxcar_ms": round(b16, 4),
             "msd_hbm_frac": round(msd_bytes / m16 / 1e6 / HBM_PEAK_GBS, 4),
         }
@@ -380,7 +415,6 @@ def run_batch(args, dev):
     info = plan.describe()
     table = plan.tune_table()
     plan.close()
-    tops = evals * OPS_PER_EVAL / t_batch / 1e12
     small = batch_small_beams(args, dev, B, synth)
     cpu = None
     if not args.no_cpu_baseline:
@@ -401,9 +435,8 @@ def run_batch(args, dev):
         "config": {"workload": cfg["name"], "beams": len(planes), "samples": samples, "widths": "1..128",
                    "threshold": cfg["threshold"], "sigma_mode": "sqrtn", "outputs": "candidates only",
                    "shapes": cfg["shapes"]},
-        "roofline": {"bound": "alu", "achieved": round(tops, 3), "peak": round(VALU_PEAK_TOPS, 2),
-                     "unit": "TFLOP/s", "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": None,
-                     "kernel": "whole batched step (msd + finalize + boxcar) from wall time"},
+        "roofline": dict(alu_roofline(evals, t_batch * 1e3, "batch"), traffic=None,
+                         kernel="whole batched step (msd + finalize + boxcar) from wall time"),
         "plain_per_beam": {"value": round(samples / t_plain / 1e9, 3), "unit": "GSamples/s",
                            "ms_per_step": round(t_plain * 1e3, 3)},
         "speedup_vs_plain": round(t_plain / t_batch, 4),
@@ -516,7 +549,6 @@ def run_dit(args, dev, levels=4):
     t = torch.arange(nout, device=dev)
     per_start = 16 + 8 * sum(((t % (1 << lv)) == 0).sum().item() for lv in range(1, levels + 1)) / nout
     evals = R * nout * per_start
-    tops = evals * OPS_PER_EVAL / (box_ms * 1e-3) / 1e12
     # the exhaustive search on the same plane, for speed and sensitivity
     stats_e = torch.empty_like(stats)
     ws_e = torch.empty(B.workspace_bytes(x, pe), dtype=torch.uint8, device=dev)
@@ -553,10 +585,9 @@ def run_dit(args, dev, levels=4):
                    "widths": "1..16, 2^l*(9..16) at starts divisible by 2^l, l=1..4 (48 widths, up to 256)",
                    "threshold": thr, "sigma_mode": "auto", "kappa": 1.0,
                    "outputs": "snr f32 + width u8 per sample, fused candidate list"},
-        "roofline": {"bound": "alu", "achieved": round(tops, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
-                     "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": load_traffic("dit"), "kernel": "boxcar_dit_kernel",
-                     "work_per_launch": "%d (t,w) evaluations (%.3f per start) x %d FP32 ops" % (
-                         evals, per_start, OPS_PER_EVAL)},
+        "roofline": dict(alu_roofline(evals, box_ms, "dit"), traffic=load_traffic("dit"), kernel="boxcar_dit_kernel",
+                         work_per_launch="%d (t,w) evaluations (%.3f per start) x %d FP32 flops" % (
+                             evals, per_start, FLOPS_PER_EVAL)),
         "kernels": {"msd_compute": {"ms": round(msd_ms, 4)}, "boxcar_snr_dit": {"ms": round(box_ms, 4)}},
         "exhaustive_ska_list": {"value": round(R * L * max(2, args.steps // 2) / wall_e / 1e9, 3),
                                 "boxcar_ms": round(box_e, 4), "n_widths": len(cfg["widths"]),

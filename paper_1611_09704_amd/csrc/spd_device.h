@@ -1226,16 +1226,28 @@ __device__ __forceinline__ void put_shifted(float* d, float4 v, float mu_hi, flo
                               (v.w - mu_hi) - mu_lo);
 }
 
-// The 4 starts of one block: SNR of widths 1..NS (entries j >= n carry a NaN
-// coefficient, which max ignores and which never compares equal), their
-// highest value and the index of the first width reaching it.  `src` points
-// at the block's first start in LDS.  `nomatch` is the index reported when no
-// SNR equals the maximum (NaN input only): n-1 for the caller's n.
-template <int NS>
-__device__ __forceinline__ void short_block(const float* src, const float (&a)[NS], int nomatch, float (&sv)[4],
-                                            uint32_t& packed)
+// The highest SNR and its first width in one max: the key of width index j
+// is the double whose high word is the SNR's bit pattern and whose low word is
+// N-1-j.  Doubles and floats are both sign-magnitude, so keys order as their
+// SNRs do; between equal SNRs the larger low word, i.e. the smaller j, wins
+// when the SNR is positive (zero included), and the larger j when it is
+// negative.  The maximum key carries the highest SNR exactly in its high word.
+// v_max_f64 runs at the FP32 rate; written out so that no canonicalising max
+// is inserted for the keys, which are not arithmetic results.
+__device__ __forceinline__ double key_max(double a, double b)
 {
-    constexpr int NV = 4 + NS - 1;
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// The 4 starts of one block for the list 1..N: their highest SNR and the index
+// of the width reaching it (see key_max).  `src` points at the block's first
+// start in LDS.
+template <int N>
+__device__ __forceinline__ void short_block(const float* src, const float (&a)[N], float (&sv)[4], uint32_t& packed)
+{
+    constexpr int NV = 4 + N - 1;
     constexpr int NR = (NV + 3) / 4;
     float v[4 * NR];
 #pragma unroll
@@ -1246,39 +1258,15 @@ __device__ __forceinline__ void short_block(const float* src, const float (&a)[N
     packed = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        float b = v[i], s[NS];
-        s[0] = __fmul_rn(b, a[0]);
+        float b = v[i];
+        double m = __hiloint2double(__float_as_int(__fmul_rn(b, a[0])), N - 1);
 #pragma unroll
-        for (int j = 1; j < NS; ++j) {
+        for (int j = 1; j < N; ++j) {
             b = __fadd_rn(b, v[i + j]);
-            s[j] = __fmul_rn(b, a[j]);
+            m = key_max(m, __hiloint2double(__float_as_int(__fmul_rn(b, a[j])), N - 1 - j));
         }
-        uint32_t idx;
-        float m;
-        if constexpr (NS == 16) {
-            // the half holding the first maximiser, then a chain over its 8 SNRs;
-            // with no match (NaN) the upper half is taken and the chain's start
-            // value nomatch - 8 gives nomatch
-            float mlo = s[0], mhi = s[8];
-#pragma unroll
-            for (int j = 1; j < 8; ++j) { mlo = fmaxf(mlo, s[j]); mhi = fmaxf(mhi, s[8 + j]); }
-            m = fmaxf(mlo, mhi);
-            const bool hi = !(mlo == m);
-            int c = nomatch - 8;
-#pragma unroll
-            for (int j = 7; j >= 0; --j) c = ((hi ? s[8 + j] : s[j]) == m) ? j : c;
-            idx = (uint32_t)(c + (hi ? 8 : 0));
-        } else {
-            m = s[0];
-#pragma unroll
-            for (int j = 1; j < NS; ++j) m = fmaxf(m, s[j]);
-            int c = nomatch;
-#pragma unroll
-            for (int j = NS - 1; j >= 0; --j) c = (s[j] == m) ? j : c;
-            idx = (uint32_t)c;
-        }
-        sv[i] = m;
-        packed |= idx << (8 * i);
+        sv[i] = __int_as_float(__double2hiint(m));
+        packed |= (uint32_t)(N - 1 - __double2loint(m)) << (8 * i);
     }
 }
 
@@ -1314,11 +1302,91 @@ __device__ __forceinline__ void emit_block_cands(const BoxcarArgs& ba, const Wid
     }
 }
 
-// Starts [t_begin, min(t_begin + kStreamRun, nout)) of row r by one wave; buf
-// is the wave's 2*kStreamBuf floats of LDS (16-byte aligned).  FAST: the row
-// allows aligned vector loads and every sample the run reads lies inside it,
-// so loads need no bounds (the other runs take raw4's checked path).
-template <int DT, int NS, bool FAST>
+// Coefficients 1/sigma_w of widths 1..N (Eq. sd02 / sd03), wave-uniform: lane
+// j computes width j+1 in FP64 and the values are read into scalar registers.
+template <int N>
+__device__ __forceinline__ void short_coefs(const spd_row_stats& st, float (&a)[N])
+{
+    const int lane = threadIdx.x & 63;
+    const bool zero_var = (st.flags & SPD_FLAG_ZERO_VAR) != 0;
+    float cf = 0.f;
+    if (lane < N) {
+        const double w = (double)(lane + 1);
+        const double sw = sqrt(w) * st.sigma + (w - 1.0) * st.lin_coef;
+        cf = (zero_var || !(sw > 0.0)) ? 0.f : (float)(1.0 / sw);
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) a[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cf), j));
+}
+
+// One run of kStreamRun starts at t_begin whose every start is valid and
+// every sample it reads (its starts plus the 16 samples after them) lies
+// inside a row that allows vector loads.  OUT: both outputs are written with
+// 16-byte and 4-byte stores; otherwise candidates only.  Every step is whole,
+// so the stores are unconditional and a step's loads are waited for without
+// waiting for the previous step's stores.
+template <int DT, int N, bool OUT>
+__device__ void boxcar_run_fast(const PlaneArg& pl, int64_t r, int64_t t_begin, const spd_row_stats& st,
+                                const BoxcarArgs& ba, const WidthPlan& wp, float* buf)
+{
+    using Raw = typename RawT<DT>::T;
+    constexpr int S = kStreamSteps;
+    const int lane = threadIdx.x & 63, lo = 4 * lane;
+    float a[N];
+    short_coefs<N>(st, a);
+    const float mu_hi = (float)st.mean;
+    const float mu_lo = (float)(st.mean - (double)mu_hi);
+    const Loader<DT> ld(pl, r);
+    const Raw* rowp = (const Raw*)(ld.row + t_begin) + lane;      // one Raw per 4 samples
+    float* so = OUT ? ba.snr + r * ba.out_stride + t_begin + lo : nullptr;
+    uint8_t* wo = OUT ? ba.widx + r * ba.out_stride + t_begin + lo : nullptr;
+
+    float* A = buf;
+    float* Bv = buf + kStreamBuf;
+    {
+        const Raw s0 = rowp[0], s1 = rowp[64];
+        put_shifted(A + lo, cvt4<DT>(ld, s0), mu_hi, mu_lo);
+        put_shifted(A + 256 + lo, cvt4<DT>(ld, s1), mu_hi, mu_lo);
+    }
+    Raw r0 = rowp[kStreamStep / 4], r1 = rowp[kStreamStep / 4 + 64];
+    if (lane < 4) put_shifted(A + kStreamStep + lo, cvt4<DT>(ld, r0), mu_hi, mu_lo);
+    wave_sync();
+    for (int k = 0; k < S; ++k) {
+        if (k + 1 < S) {
+            put_shifted(Bv + lo, cvt4<DT>(ld, r0), mu_hi, mu_lo);
+            put_shifted(Bv + 256 + lo, cvt4<DT>(ld, r1), mu_hi, mu_lo);
+        }
+        const Raw* nx = rowp + (k + 2) * (kStreamStep / 4);
+        if (k + 2 < S) {
+            r0 = nx[0];
+            r1 = nx[64];
+        } else if (k + 2 == S && lane < 4) {
+            r0 = nx[0];
+        }
+#pragma unroll
+        for (int blk = 0; blk < 2; ++blk) {
+            float sv[4];
+            uint32_t pk;
+            short_block<N>(A + 256 * blk + lo, a, sv, pk);
+            const int off = k * kStreamStep + 256 * blk;
+            if (ba.cand && __ballot(fmaxf(fmaxf(sv[0], sv[1]), fmaxf(sv[2], sv[3])) >= ba.threshold))
+                emit_block_cands(ba, wp, r, t_begin + off + lo, 4, sv, pk);
+            if (OUT) {
+                *(float4*)(so + off) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+                *(uint32_t*)(wo + off) = pk;
+            }
+        }
+        if (k + 1 < S && lane < 4) put_shifted(Bv + kStreamStep + lo, cvt4<DT>(ld, r0), mu_hi, mu_lo);
+        wave_sync();
+        float* tmp = A; A = Bv; Bv = tmp;
+    }
+}
+
+// Starts [t_begin, min(t_begin + kStreamRun, nout)) of row r by one wave, for
+// any run: loads checked against the row end and against vector alignment,
+// stores per element where a step is partial or the rows do not allow vector
+// stores.  buf is the wave's 2*kStreamBuf floats of LDS (16-byte aligned).
+template <int DT, int N>
 __device__ void boxcar_run_short(const PlaneArg& pl, bool vec, int64_t r, int64_t t_begin, const spd_row_stats& st,
                                  const BoxcarArgs& ba, const WidthPlan& wp, float* buf)
 {
@@ -1327,36 +1395,17 @@ __device__ void boxcar_run_short(const PlaneArg& pl, bool vec, int64_t r, int64_
     const int64_t nout = ba.nout;
     const int64_t t_end = min(t_begin + kStreamRun, nout);
     const int steps = (int)((t_end - t_begin + kStreamStep - 1) / kStreamStep);
-
-    // coefficients 1/sigma_w (Eq. sd02 / sd03): lane j computes width j+1 in FP64
-    float a[NS];
-    {
-        const bool zero_var = (st.flags & SPD_FLAG_ZERO_VAR) != 0;
-        float cf = __int_as_float(0x7fc00000);
-        if (lane < wp.n) {
-            const double w = (double)(lane + 1);
-            const double sw = sqrt(w) * st.sigma + (w - 1.0) * st.lin_coef;
-            cf = (zero_var || !(sw > 0.0)) ? 0.f : (float)(1.0 / sw);
-        }
-#pragma unroll
-        for (int j = 0; j < NS; ++j) a[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cf), j));
-    }
-    const int nomatch = wp.n - 1;
+    float a[N];
+    short_coefs<N>(st, a);
     const float mu_hi = (float)st.mean;
     const float mu_lo = (float)(st.mean - (double)mu_hi);
     const Loader<DT> ld(pl, r);
     const int64_t ncols = pl.n_cols;
-    // lane l's two loads of the step at column c: c + 4l and c + 256 + 4l
-    const auto* rowp = ld.row + t_begin;                    // wave-uniform
     const int lo = 4 * lane;
-    auto load = [&](int64_t off) -> Raw {                   // columns t_begin + off .. + 3
-        if constexpr (FAST) return *(const Raw*)(rowp + off);
-        else return raw4<DT>(ld, t_begin + off, ncols, vec);
-    };
+    auto load = [&](int64_t off) -> Raw { return raw4<DT>(ld, t_begin + off, ncols, vec); };
 
     float* A = buf;
     float* Bv = buf + kStreamBuf;
-    // prologue: step 0 into A, step 1 in registers, its first 16 samples into A's tail
     {
         const Raw s0 = load(lo), s1 = load(lo + 256);
         put_shifted(A + lo, cvt4<DT>(ld, s0), mu_hi, mu_lo);
@@ -1372,12 +1421,11 @@ __device__ void boxcar_run_short(const PlaneArg& pl, bool vec, int64_t r, int64_
     if (lane < 4) put_shifted(A + kStreamStep + lo, cvt4<DT>(ld, r0), mu_hi, mu_lo);
     wave_sync();
 
-    float* so = ba.snr ? ba.snr + r * ba.out_stride + t_begin : nullptr;     // wave-uniform bases
+    float* so = ba.snr ? ba.snr + r * ba.out_stride + t_begin : nullptr;
     uint8_t* wo = ba.widx ? ba.widx + r * ba.out_stride + t_begin : nullptr;
     const bool vs = (ba.out_vec & 1u) != 0, vw = (ba.out_vec & 4u) != 0;
     for (int k = 0; k < steps; ++k) {
         const int ks = k * kStreamStep;
-        // step k+1 (in registers) into the other buffer; step k+2 in flight
         if (k + 1 < steps) {
             put_shifted(Bv + lo, cvt4<DT>(ld, r0), mu_hi, mu_lo);
             put_shifted(Bv + 256 + lo, cvt4<DT>(ld, r1), mu_hi, mu_lo);
@@ -1388,14 +1436,13 @@ __device__ void boxcar_run_short(const PlaneArg& pl, bool vec, int64_t r, int64_
         } else if (k + 2 == steps && lane < 4) {
             r0 = load(ks + 2 * kStreamStep + lo);
         }
-        // step k from A, one block after the other
-        const bool whole = t_begin + ks + kStreamStep <= t_end;           // wave-uniform
+        const bool whole = t_begin + ks + kStreamStep <= t_end;
 #pragma unroll
         for (int blk = 0; blk < 2; ++blk) {
             float sv[4];
             uint32_t pk;
-            short_block<NS>(A + 256 * blk + lo, a, nomatch, sv, pk);
-            const int off = ks + 256 * blk + lo;                            // start t_begin + off
+            short_block<N>(A + 256 * blk + lo, a, sv, pk);
+            const int off = ks + 256 * blk + lo;
             int cnt = 4;
             if (!whole) {
                 const int64_t left = t_end - (t_begin + off);
@@ -1418,7 +1465,6 @@ __device__ void boxcar_run_short(const PlaneArg& pl, bool vec, int64_t r, int64_
                     if (i < cnt) wo[off + i] = (uint8_t)(pk >> (8 * i));
             }
         }
-        // the next step's tail: the first 16 samples of step k+2
         if (k + 1 < steps && lane < 4) put_shifted(Bv + kStreamStep + lo, cvt4<DT>(ld, r0), mu_hi, mu_lo);
         wave_sync();
         float* tmp = A; A = Bv; Bv = tmp;

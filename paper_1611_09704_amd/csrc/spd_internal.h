@@ -105,6 +105,7 @@ struct BoxcarArgs {
     uint32_t out_vec;       // bit 0: snr rows allow 16-byte stores; bit 1: widx rows allow 8-byte stores;
                             // bit 2: widx rows allow 4-byte stores
     uint32_t reserved;
+    int64_t run0, run1;     // streaming form: the runs [run0, run1) of every row this launch covers
 };
 
 struct SelectArgs {

@@ -14,6 +14,8 @@ size_t boxcar_lds_bytes(int waves, const BoxcarArgs& ba, bool win = false);
 hipError_t launch_boxcar(int dtype, const PlaneArg& pl, bool vec, const spd_row_stats* stats,
                          const BoxcarArgs& ba, const WidthPlan& wp, int X, int waves, uint64_t ntiles,
                          hipStream_t s);
+hipError_t launch_stream(int dtype, const PlaneArg& pl, bool vec, const spd_row_stats* stats, const BoxcarArgs& ba,
+                         const WidthPlan& wp, int waves, uint64_t ntiles, hipStream_t s);
 hipError_t launch_zero_count(int64_t* count, hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
 int msd_xy_waves(int nmax);

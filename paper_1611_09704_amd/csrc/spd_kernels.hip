@@ -10,6 +10,7 @@
 //                                  and each group's reads held in registers
 //   boxcar_dit_kernel              boxcars combined with decimation in time
 //                                  (widths 2^l*(9..16) on the decimated series)
+// (the streaming form of the lists 1..n, n <= 16, is in spd_stream.hip)
 //   select_kernel                  threshold over stored outputs, Sec. 2.4
 //
 // One work-group per (row, column block) or (row, time tile), numbered so that
@@ -91,29 +92,6 @@ __global__ __launch_bounds__(256) void boxcar_dit_kernel(PlaneArg pl, bool vec, 
     const int64_t tt = (int64_t)(tile % (uint64_t)ba.tiles_per_row);
     const spd_row_stats st = stats[ba.scope == SPD_SCOPE_ROW ? r : 0];
     boxcar_tile_win<DT, kDitBase, true>(pl, vec, r, tt, st, ba, wp, smem);
-}
-
-// The list 1..n (n <= 16) in the streaming form: work-group (row, segment),
-// wave w of it the run of kStreamRun starts at (segment * waves + w) * kStreamRun.
-template <int DT, int NS>
-__global__ __launch_bounds__(256) void boxcar_stream_kernel(
-    PlaneArg pl, bool vec, const spd_row_stats* stats, BoxcarArgs ba, WidthPlan wp)
-{
-    extern __shared__ float smem[];
-    const uint64_t wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t r = (int64_t)(wg / (uint64_t)ba.tiles_per_row);
-    const int64_t seg = (int64_t)(wg % (uint64_t)ba.tiles_per_row);
-    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int64_t t0 = (seg * nw + wave) * kStreamRun;
-    if (t0 >= ba.nout) return;
-    const spd_row_stats st = stats[ba.scope == SPD_SCOPE_ROW ? r : 0];
-    float* buf = smem + (size_t)wave * 2 * kStreamBuf;
-    // every column the run reads: its starts, the next step's first 16 samples
-    const int64_t steps = (min(t0 + kStreamRun, ba.nout) - t0 + kStreamStep - 1) / kStreamStep;
-    if (vec && t0 + steps * kStreamStep + 16 <= pl.n_cols)
-        boxcar_run_short<DT, NS, true>(pl, vec, r, t0, st, ba, wp, buf);
-    else
-        boxcar_run_short<DT, NS, false>(pl, vec, r, t0, st, ba, wp, buf);
 }
 
 // Sec. 2.4 over stored snr / width-index arrays.  A work-group covers kSelCols
@@ -233,14 +211,9 @@ static hipError_t launch_boxcar_dt(const PlaneArg& pl, bool vec, const spd_row_s
 {
     const size_t lds = boxcar_lds_bytes(waves, ba, wp.win != 0);   // <= 64 KiB by construction of the plan
     constexpr int X = kOutPerLane;
-    const size_t lds_stream = (size_t)waves * 2 * kStreamBuf * sizeof(float);
-    if (wp.win == 4 && wp.n <= 8)
-        hipLaunchKernelGGL((boxcar_stream_kernel<DT, 8>), dim3(ntiles), dim3(64 * waves), lds_stream, s, pl, vec,
-                           stats, ba, wp);
-    else if (wp.win == 4)
-        hipLaunchKernelGGL((boxcar_stream_kernel<DT, 16>), dim3(ntiles), dim3(64 * waves), lds_stream, s, pl, vec,
-                           stats, ba, wp);
-    else if (wp.win == 3)
+    if (wp.win == 4)
+        return launch_stream(DT, pl, vec, stats, ba, wp, waves, ntiles, s);
+    if (wp.win == 3)
         hipLaunchKernelGGL((boxcar_dit_kernel<DT>), dim3(ntiles), dim3(64 * waves), lds, s, pl, vec, stats, ba, wp);
     else if (wp.win == 1)
         hipLaunchKernelGGL((boxcar_win_kernel<DT, 0>), dim3(ntiles), dim3(64 * waves), lds, s, pl, vec, stats, ba, wp);

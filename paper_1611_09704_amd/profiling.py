@@ -27,7 +27,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 COPY_BYTES = 1 << 31          # calibration copy: reads and writes 2 GiB
 WORKLOADS = {"ska": None, "ska16": list(range(1, 17)), "dit": "dit", "cluster": "cluster", "dedisp": "dedisp"}
-BOXCAR_SOURCES = ("spd_device.h", "spd_kernels.hip", "spd_kernels.h", "spd_internal.h")
+BOXCAR_SOURCES = ("spd_device.h", "spd_kernels.hip", "spd_kernels.h", "spd_internal.h", "spd_stream.hip")
 CLUSTER_SOURCES = ("spd_cluster.hip",)
 DEDISP_SOURCES = ("spd_dedisp.hip",)
 CLUSTER_RADII = (2, 256)     # DM rows, starts
@@ -120,7 +120,7 @@ def _short(name: str, with_args: bool = False) -> str:
     if with_args and "<" in name.split("(")[0]:
         targs = "<" + name.split("(")[0].split("<", 1)[1]
     for key in ("batch_boxcar_win_grid_kernel", "batch_boxcar_grid_kernel", "batch_boxcar_kernel", "batch_msd_kernel",
-                "batch_finalize_kernel", "boxcar_dit_kernel", "boxcar_win_kernel", "boxcar_kernel", "msd_xy_kernel", "msd_x_kernel", "msd_finalize_kernel",
+                "batch_finalize_kernel", "boxcar_dit_kernel", "boxcar_stream_fast_kernel", "boxcar_stream_kernel", "boxcar_win_kernel", "boxcar_kernel", "msd_xy_kernel", "msd_x_kernel", "msd_finalize_kernel",
                 "select_kernel", "cluster_kernel", "dedisp_u8_wide_kernel", "dedisp_u8_kernel",
                 "fill_i64_kernel"):
         if key in name:
@@ -230,8 +230,9 @@ def summarize(args):
             d["dedisp"] = {"kernel_sha": sha,
                            **(traffic.get("dedisp_u8_wide_kernel") or traffic.get("dedisp_u8_kernel") or {})}
         else:
-            box = (traffic.get("boxcar_dit_kernel") or traffic.get("boxcar_win_kernel")
-                   or traffic.get("boxcar_kernel") or {})
+            box = (traffic.get("boxcar_dit_kernel") or traffic.get("boxcar_stream_fast_kernel")
+                   or traffic.get("boxcar_stream_kernel")
+                   or traffic.get("boxcar_win_kernel") or traffic.get("boxcar_kernel") or {})
             d[args.workload] = {"kernel_sha": sha, **box,
                                 "msd": traffic.get("msd_xy_kernel") or traffic.get("msd_x_kernel")}
         json.dump(d, open(tpath, "w"), indent=1)
@@ -286,6 +287,64 @@ def counter_summary(args):
     with open(path, "w") as fh:
         fh.write("\n".join(lines))
     print("wrote", path)
+    if args.workload:
+        write_valu_summary(args.workload, args.out, args.dirs)
+
+
+def workload_evals(workload: str, rows: int = 4096, cols: int = 1 << 20) -> int:
+    """(start, width) evaluations of one boxcar launch of a profiled workload."""
+    from paper_1611_09704_amd import synth
+    if WORKLOADS[workload] == "dit":
+        n_ev = 0
+        levels = DIT_LEVELS
+        nout = cols - 16 * (1 << levels) + 1
+        n_ev = nout * 16
+        for lv in range(1, levels + 1):      # widths 9..16 of level lv at starts that are multiples of 2^lv
+            n_ev += ((nout + (1 << lv) - 1) >> lv) * 8
+        return rows * n_ev
+    W = WORKLOADS[workload] or synth.SKA_WIDTHS
+    return rows * (cols - W[-1] + 1) * len(W)
+
+
+def write_valu_summary(workload, out, dirs):
+    """VALU lane-instructions per (start, width) evaluation and clock of the
+    workload's boxcar kernel, from the SQ_INSTS_VALU / GRBM_GUI_ACTIVE runs in
+    dirs, into profiles/valu_counters.json (keyed by workload, with the hash of
+    the kernel sources the counters were taken on)."""
+    tot = defaultdict(lambda: defaultdict(float))
+    span = {}
+    for d in dirs:
+        for f in _csvs(d, "counter_collection.csv"):
+            for row in csv.DictReader(open(f)):
+                name = _short(row["Kernel_Name"])
+                if not name.startswith("boxcar"):
+                    continue
+                key = (name, row.get("Dispatch_Id"), d)
+                tot[key][row["Counter_Name"]] += float(row["Counter_Value"])
+                span[key] = (int(row["Start_Timestamp"]), int(row["End_Timestamp"]))
+    valu = [(k, c) for k, c in tot.items() if "SQ_INSTS_VALU" in c]
+    clk = [(k, c) for k, c in tot.items() if "GRBM_GUI_ACTIVE" in c]
+    if not valu:
+        return
+    k, c = valu[0]
+    evals = workload_evals(workload)
+    ent = {"kernel_sha": kernel_source_sha(), "kernel": k[0],
+           "valu_lane_instr_per_eval": round(c["SQ_INSTS_VALU"] * 64 / evals, 4)}
+    if clk:
+        kc, cc = clk[0]
+        ms = (span[kc][1] - span[kc][0]) / 1e6
+        cyc = cc["GRBM_GUI_ACTIVE"] / N_XCD
+        ent["clock_ghz"] = round(cyc / (ms * 1e-3) / 1e9, 3)
+        if kc[2] == k[2]:
+            ent["valu_per_simd_quad_cycle"] = round(c["SQ_INSTS_VALU"] / (N_SIMD * cyc / 4), 3)
+    path = os.path.join(out, "valu_counters.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        d = {}
+    d[workload] = ent
+    json.dump(d, open(path, "w"), indent=1)
+    print("wrote", path)
 
 
 def main(argv=None):
@@ -313,6 +372,8 @@ def main(argv=None):
     c.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     c.add_argument("--name", required=True)
     c.add_argument("--title", required=True)
+    c.add_argument("--workload", choices=sorted(WORKLOADS),
+                   help="also write the boxcar kernel's VALU per evaluation to valu_counters.json")
     a = ap.parse_args(argv)
     {"run": run, "summarize": summarize, "counters": counter_summary}[a.cmd](a)
 
