@@ -44,11 +44,11 @@
  *         uses sigma_Nmax/(Nmax-1).  sigma_Nmax is the population standard
  *         deviation of B_Nmax(t) over the unit's valid starts.
  *       * The highest SNR keeps the FIRST width that reaches it (strict '>').
- *         For the lists 1..n (n <= 16) this holds where that SNR is >= +0;
- *         where it is negative or a -0, exactly equal SNRs of several widths
- *         keep the last of them (both are maximisers of Algorithm 1's
- *         comparison; ties of this kind need equal products of different
- *         sums and coefficients).
+ *         For the lists 1..n (n <= 16) exact ties are resolved this way
+ *         only among positive SNRs and +0; among exactly equal negative
+ *         SNRs the last width is kept, and +0 counts above -0.  Every width
+ *         kept is a maximiser (ties of this kind need equal products of
+ *         different sums and coefficients).
  *       * A unit with sigma == 0 is flagged SPD_FLAG_ZERO_VAR: all its SNRs
  *         are 0 and all width indices 0.  A width whose sigma_w <= 0 gives 0.
  *       * A sample is a candidate iff its highest SNR >= threshold.
