@@ -31,6 +31,7 @@
 #include "spd_abi_internal.h"
 #include "spd_device.h"
 #include "spd_kernels.h"
+#include "spd_sched.h"
 
 namespace spd {
 
@@ -479,8 +480,9 @@ static spd_status tune(spd_batch_plan* P, hipStream_t s)
     Schedule best;
     best.X = 8;
     best.waves = P->max_waves[1];
-    if (cache_lookup(key, best) && (best.X == 4 || best.X == 8) && best.wgs_per_cu >= 0 && best.grab >= 1 &&
-        (!best.win || (P->has_win && best.X == 8 && best.wgs_per_cu == 0))) {
+    if (cache_lookup(key, best) && (best.X == 4 || best.X == 8) &&
+        schedule_usable(best.X, best.win, best.wgs_per_cu, best.grab, P->has_win, P->tiles[slot(best)],
+                        P->max_waves[slot(best)], kMaxGridItems)) {
         best.waves = P->max_waves[slot(best)];
         P->sched = best;
         P->tuned = 2;

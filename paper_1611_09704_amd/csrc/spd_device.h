@@ -1172,9 +1172,12 @@ __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t
 // no work-group barrier is needed and every sample is read from HBM once.
 // The coefficients 1/sigma_w are wave-uniform (scalar registers).
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
 template <int DT> struct RawT;
-template <> struct RawT<SPD_F32> { using T = float4; };
-template <> struct RawT<SPD_F16> { using T = uint2; };
+template <> struct RawT<SPD_F32> { using T = f32x4; };
+template <> struct RawT<SPD_F16> { using T = u32x2; };
 template <> struct RawT<SPD_U8> { using T = uint32_t; };
 
 // Four samples from column c as stored; past the end of the row the value is
@@ -1186,7 +1189,7 @@ __device__ __forceinline__ typename RawT<DT>::T raw4(const Loader<DT>& ld, int64
     using T = typename RawT<DT>::T;
     if (vec && c + 3 < ncols) return *(const T*)(ld.row + c);
     if constexpr (DT == SPD_F32) {
-        float4 v;
+        f32x4 v;
         v.x = c < ncols ? ld.row[c] : 0.f;
         v.y = c + 1 < ncols ? ld.row[c + 1] : 0.f;
         v.z = c + 2 < ncols ? ld.row[c + 2] : 0.f;
@@ -1197,7 +1200,8 @@ __device__ __forceinline__ typename RawT<DT>::T raw4(const Loader<DT>& ld, int64
         uint32_t e[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) e[k] = c + k < ncols ? (uint32_t)h[c + k] : 0u;
-        return make_uint2(e[0] | (e[1] << 16), e[2] | (e[3] << 16));
+        const u32x2 u = {e[0] | (e[1] << 16), e[2] | (e[3] << 16)};
+        return u;
     } else {
         uint32_t u = 0;
 #pragma unroll
@@ -1210,10 +1214,11 @@ template <int DT>
 __device__ __forceinline__ float4 cvt4(const Loader<DT>& ld, typename RawT<DT>::T u)
 {
     if constexpr (DT == SPD_F32) {
-        return u;
+        return make_float4(u.x, u.y, u.z, u.w);
     } else if constexpr (DT == SPD_F16) {
-        const float2 a = __half22float2(*reinterpret_cast<const __half2*>(&u.x));
-        const float2 b = __half22float2(*reinterpret_cast<const __half2*>(&u.y));
+        const uint32_t lo = u.x, hi = u.y;
+        const float2 a = __half22float2(*reinterpret_cast<const __half2*>(&lo));
+        const float2 b = __half22float2(*reinterpret_cast<const __half2*>(&hi));
         return make_float4(a.x, a.y, b.x, b.y);
     } else {
         return make_float4(ld.deq(u & 255u), ld.deq((u >> 8) & 255u), ld.deq((u >> 16) & 255u), ld.deq(u >> 24));
@@ -1357,9 +1362,9 @@ __device__ void boxcar_run_fast(const PlaneArg& pl, int64_t r, int64_t t_begin, 
             put_shifted(Bv + 256 + lo, cvt4<DT>(ld, r1), mu_hi, mu_lo);
         }
         const Raw* nx = rowp + (k + 2) * (kStreamStep / 4);
-        if (k + 2 < S) {
-            r0 = nx[0];
-            r1 = nx[64];
+        if (k + 2 < S) {                                    // read once: nontemporal
+            r0 = __builtin_nontemporal_load(nx);
+            r1 = __builtin_nontemporal_load(nx + 64);
         } else if (k + 2 == S && lane < 4) {
             r0 = nx[0];
         }
@@ -1371,9 +1376,10 @@ __device__ void boxcar_run_fast(const PlaneArg& pl, int64_t r, int64_t t_begin, 
             const int off = k * kStreamStep + 256 * blk;
             if (ba.cand && __ballot(fmaxf(fmaxf(sv[0], sv[1]), fmaxf(sv[2], sv[3])) >= ba.threshold))
                 emit_block_cands(ba, wp, r, t_begin + off + lo, 4, sv, pk);
-            if (OUT) {
-                *(float4*)(so + off) = make_float4(sv[0], sv[1], sv[2], sv[3]);
-                *(uint32_t*)(wo + off) = pk;
+            if (OUT) {                                                  // written once, never read here
+                const f32x4 q = {sv[0], sv[1], sv[2], sv[3]};
+                __builtin_nontemporal_store(q, (f32x4*)(so + off));
+                __builtin_nontemporal_store(pk, (uint32_t*)(wo + off));
             }
         }
         if (k + 1 < S && lane < 4) put_shifted(Bv + kStreamStep + lo, cvt4<DT>(ld, r0), mu_hi, mu_lo);
