@@ -178,6 +178,10 @@ def main():
     ap.add_argument("--cols", type=int, default=1 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the precision, batched and serving legs of the default line")
+    ap.add_argument("--serve-paced-s", type=float, default=20.0,
+                    help="seconds of Poisson arrivals at 1.5x real time in the serving leg")
     ap.add_argument("--workload", default="ska", choices=["ska", "ska16"],
                     help="ska: widths 1..16,18..256/2 (default); ska16: the same plane with widths 1..16 only")
     ap.add_argument("--form", default="plain",
@@ -358,6 +362,20 @@ def main():
         out["cpu_baseline"]["one_thread_small_plane"] = {"value": round(small.size / d1 / 1e9, 5),
                                                          "unit": "GSamples/s", "seconds": round(d1, 3),
                                                          "sample": "64 x 65536, widths 1..32"}
+    if not args.no_forms and args.workload == "ska":
+        # the production forms on the same box, in brief: precision (error against the FP64
+        # oracle on the FP32 values, speed on this plane), batched beams against per-beam
+        # launches, and the serving loop's chunk latency
+        t_leg = time.perf_counter()
+        out["precision"] = {"errors": precision_errors(dev, B, synth),
+                            "speed": precision_speed(dev, B, synth, cfg, 5, 1)}
+        del x, cfg, snr_flat, widx_flat, cand, ws, stats
+        torch.cuda.empty_cache()
+        out["batched"] = batch_compare(dev, B, synth.batch(device=dev, max_samples=int(args.batch_samples)), 3, 1)
+        out["batched"].pop("autotune_table", None)
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg(dev, B, synth, args.serve_paced_s)
+        out["forms_wall_s"] = round(time.perf_counter() - t_leg, 1)
     print(json.dumps(out), flush=True)
 
 
@@ -373,48 +391,10 @@ def run_batch(args, dev):
     cfg = synth.batch(device=dev, max_samples=int(args.batch_samples))
     planes = [pl.x for pl in cfg["planes"]]
     W = cfg["widths"]
-    p = B.Params(W, cfg["threshold"])
     samples = sum(x.numel() for x in planes)
     evals = sum(x.shape[0] * (x.shape[1] - W[-1] + 1) for x in planes) * len(W)
-    cap = 1 << 23
-    cand = B.new_candidates(cap, dev)
-    count = torch.zeros(1, dtype=torch.int64, device=dev)
-    stream = torch.cuda.current_stream()
-    # per-beam plain launches
-    stats = [torch.empty((x.shape[0], B.STATS_FIELDS), dtype=torch.float64, device=dev) for x in planes]
-    wss = [torch.empty(B.workspace_bytes(x, p), dtype=torch.uint8, device=dev) for x in planes]
-
-    def plain_step():
-        n = 0
-        for x, st, ws in zip(planes, stats, wss):
-            B.msd_compute(x, p, stats=st, workspace=ws, stream=stream)
-            B.boxcar_snr(x, p, st, cand=cand, cand_count=count, stream=stream)
-        return n
-
-    plain_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plain_step()
-    torch.cuda.synchronize()
-    t_plain = (time.perf_counter() - t0) / args.steps
-    # batched plan
-    t0 = time.perf_counter()
-    os.environ.setdefault("SPD_TUNE_CACHE", os.path.join("/tmp", "spd_bench_schedule_%d.txt" % os.getpid()))
-    plan = B.BatchPlan(planes, p, autotune=True)
-    t_create = time.perf_counter() - t0
-    for _ in range(max(1, args.warmup)):
-        plan.run(cand, count, use_graph=True, stream=stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plan.run(cand, count, use_graph=True, stream=stream)
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / args.steps
-    n_cand = int(count.item())
-    info = plan.describe()
-    table = plan.tune_table()
-    plan.close()
+    leg = batch_compare(dev, B, cfg, args.steps, args.warmup)
+    t_batch, t_plain = leg["batched"]["ms_per_step"] * 1e-3, leg["plain_per_beam"]["ms_per_step"] * 1e-3
     small = batch_small_beams(args, dev, B, synth)
     cpu = None
     if not args.no_cpu_baseline:
@@ -439,10 +419,67 @@ def run_batch(args, dev):
                          kernel="whole batched step (msd + finalize + boxcar) from wall time"),
         "plain_per_beam": {"value": round(samples / t_plain / 1e9, 3), "unit": "GSamples/s",
                            "ms_per_step": round(t_plain * 1e3, 3)},
-        "speedup_vs_plain": round(t_plain / t_batch, 4),
-        "schedule": info, "autotune_table": table, "plan_create_s": round(t_create, 3), "n_candidates": n_cand,
-        "small_beams": small, "cpu_baseline": cpu,
+        "speedup_vs_plain": leg["speedup_vs_plain"], "schedule": leg["schedule"],
+        "autotune_table": leg["autotune_table"], "plan_create_s": leg["plan_create_s"],
+        "n_candidates": leg["n_candidates"], "small_beams": small, "cpu_baseline": cpu,
     }
+
+
+def batch_compare(dev, B, cfg, steps, warmup):
+    """The batched workload's beams run as one batched plan (autotuned
+    schedule, hipGraph replay) and as per-beam plain launches of msd_compute
+    and boxcar_snr, candidates only; wall time per step of each, and the same
+    candidate count from both."""
+    import torch
+    planes = [pl.x for pl in cfg["planes"]]
+    p = B.Params(cfg["widths"], cfg["threshold"])
+    samples = sum(x.numel() for x in planes)
+    cand = B.new_candidates(1 << 23, dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    stats = [torch.empty((x.shape[0], B.STATS_FIELDS), dtype=torch.float64, device=dev) for x in planes]
+    wss = [torch.empty(B.workspace_bytes(x, p), dtype=torch.uint8, device=dev) for x in planes]
+    total = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def plain_step():
+        total.zero_()
+        for x, st, ws in zip(planes, stats, wss):
+            B.msd_compute(x, p, stats=st, workspace=ws, stream=stream)
+            B.boxcar_snr(x, p, st, cand=cand, cand_count=count, stream=stream)
+            total.add_(count)
+
+    for _ in range(max(1, warmup)):
+        plain_step()
+    torch.cuda.synchronize()
+    n_plain = int(total.item())
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plain_step()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    os.environ.setdefault("SPD_TUNE_CACHE", os.path.join("/tmp", "spd_bench_schedule_%d.txt" % os.getpid()))
+    plan = B.BatchPlan(planes, p, autotune=True)
+    t_create = time.perf_counter() - t0
+    for _ in range(max(1, warmup)):
+        plan.run(cand, count, use_graph=True, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.run(cand, count, use_graph=True, stream=stream)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    n_cand = int(count.item())
+    info, table = plan.describe(), plan.tune_table()
+    plan.close()
+    if n_cand != n_plain:
+        raise RuntimeError("batched and per-beam candidate counts differ (%d vs %d)" % (n_cand, n_plain))
+    return {"workload": cfg["name"], "beams": len(planes), "samples": samples, "widths": "1..%d" % cfg["widths"][-1],
+            "batched": {"GSamples/s": round(samples / t_batch / 1e9, 3), "ms_per_step": round(t_batch * 1e3, 3)},
+            "plain_per_beam": {"GSamples/s": round(samples / t_plain / 1e9, 3),
+                               "ms_per_step": round(t_plain * 1e3, 3)},
+            "speedup_vs_plain": round(t_plain / t_batch, 4), "n_candidates": n_cand, "schedule": info,
+            "autotune_table": table, "plan_create_s": round(t_create, 3)}
 
 
 def batch_small_beams(args, dev, B, synth, n_beams=256, rows=64, cols=32768, wmax=32):
@@ -858,12 +895,29 @@ def run_precision(args, dev):
     (max |dSNR|, candidate-set differences), next to the FP32 path's own
     numbers; kernel parity on the dequantised values is checked too.  (2) Speed:
     the SKA-like plane as FP32, FP16 and U8 (per-row zero at the row mean)."""
+    from paper_1611_09704_amd import binding as B
+    from paper_1611_09704_amd import synth
+    errors = precision_errors(dev, B, synth)
+    # speed on the SKA-like plane
+    sk = synth.ska(device=dev, R=args.rows, L=args.cols)
+    speed = precision_speed(dev, B, synth, sk, args.steps, args.warmup)
+    return {"metric": METRIC, "value": speed["ska136/f16"]["GSamples_per_s"], "unit": "GSamples/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+            "dtype": "f16/u8 storage, f32 accumulation, f64 merge", "data": "synthetic",
+            "config": {"workload": "precision forms: tiny 64x65536 error, ska 4096x2^20 speed"},
+            "errors": errors, "speed": speed}
+
+
+def precision_errors(dev, B, synth):
+    """The tiny plane (64 x 65,536, widths 1..32, threshold 6) stored as FP16
+    and as U8 (s_r = sigma_r/20, z = 64), each run on the GPU and compared with
+    the FP64 oracle on the ORIGINAL FP32 values (max |dSNR|, candidate-set
+    differences), next to the FP32 path's own numbers; kernel parity on the
+    dequantised values is reported too."""
     import numpy as np
     import torch
 
     import oracle
-    from paper_1611_09704_amd import binding as B
-    from paper_1611_09704_amd import synth
     cfg = synth.tiny(device=dev)
     x32 = cfg["plane"].x
     W, thr = cfg["widths"], cfg["threshold"]
@@ -890,8 +944,14 @@ def run_precision(args, dev):
             "kernel_parity_max_abs_dSNR_on_stored_values": float(np.abs(snr - own["snr"]).max()),
             "bytes_per_sample": x.element_size(),
         }
-    # speed on the SKA-like plane
-    sk = synth.ska(device=dev, R=args.rows, L=args.cols)
+    return errors
+
+
+def precision_speed(dev, B, synth, sk, steps, warmup):
+    """One step (statistics + boxcars with outputs and the fused threshold) on
+    the SKA-like plane stored as FP32, FP16 and U8 (per-row zero at the row
+    mean), for the 136-width list and for widths 1..16."""
+    import torch
     xs = sk["plane"].x
     R, L = xs.shape
     q, sc, zr = synth.quantize_u8(xs, sk["plane"].row_sigma, row_mu=sk["plane"].row_mu)
@@ -900,34 +960,37 @@ def run_precision(args, dev):
     for wname, Wl in (("ska136", sk["widths"]), ("w16", list(range(1, 17)))):
         p = B.Params(Wl, sk["threshold"], "row", "auto", 1.0)
         nout = L - p.nmax + 1
-        snr = torch.empty((R, nout), dtype=torch.float32, device=dev)
-        widx = torch.empty((R, nout), dtype=torch.uint8, device=dev)
+        po = (nout + 15) // 16 * 16               # output rows padded to 64-byte multiples, as in the main step
+        snr = torch.empty((R, po), dtype=torch.float32, device=dev)[:, :nout]
+        widx = torch.empty((R, po), dtype=torch.uint8, device=dev)[:, :nout]
         cand = B.new_candidates(1 << 21, dev)
         count = torch.zeros(1, dtype=torch.int64, device=dev)
         for name, (x, s_, z_) in planes.items():
             stats = torch.empty((R, B.STATS_FIELDS), dtype=torch.float64, device=dev)
             ws = torch.empty(B.workspace_bytes(x, p, s_, z_), dtype=torch.uint8, device=dev)
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-            for rep in range(args.warmup + args.steps):
-                if rep == args.warmup:
+            for rep in range(warmup + steps):
+                if rep == warmup:
                     ev[0].record()
                 B.msd_compute(x, p, scale=s_, zero=z_, stats=stats, workspace=ws)
-                if rep == args.warmup:
+                if rep == warmup:
                     ev[1].record()
                 B.boxcar_snr(x, p, stats, scale=s_, zero=z_, snr=snr, widx=widx, cand=cand, cand_count=count)
             ev[2].record()
             torch.cuda.synchronize()
             t_msd = ev[0].elapsed_time(ev[1])
-            t_all = ev[0].elapsed_time(ev[2]) / args.steps
+            t_all = ev[0].elapsed_time(ev[2]) / steps
             speed["%s/%s" % (wname, name)] = {"msd_ms": round(t_msd, 4), "step_ms": round(t_all, 3),
                                               "GSamples_per_s": round(R * L / t_all / 1e6, 3),
                                               "msd_GB_per_s": round(R * L * x.element_size() / t_msd / 1e6, 1)}
         del snr, widx
-    return {"metric": METRIC, "value": speed["ska136/f16"]["GSamples_per_s"], "unit": "GSamples/s",
-            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
-            "dtype": "f16/u8 storage, f32 accumulation, f64 merge", "data": "synthetic",
-            "config": {"workload": "precision forms: tiny 64x65536 error, ska 4096x2^20 speed"},
-            "errors": errors, "speed": speed}
+    for wname in ("ska136", "w16"):
+        f32 = speed["%s/f32" % wname]["step_ms"]
+        for name in ("f16", "u8"):
+            speed["%s/%s" % (wname, name)]["speedup_vs_f32"] = round(f32 / speed["%s/%s" % (wname, name)]["step_ms"], 4)
+    del planes
+    torch.cuda.empty_cache()
+    return speed
 
 
 SAMPLE_S = 64e-6                  # sampling time of the serving workload
@@ -984,6 +1047,65 @@ def serve_run(B, srv, payloads, n_beams, rate_x, window_s, chunk_sky_s, seed, ma
     return np.array(lat), wall, len(events), per_beam
 
 
+SERVE_BEAMS, SERVE_ROWS, SERVE_COLS = 16, 1024, 131072
+
+
+def serve_payloads(dev, synth):
+    """Two consecutive FP16 chunks per beam (pulses straddle the cut), in
+    pinned host memory; beams reuse them chunk after chunk."""
+    import torch
+    payloads = []
+    for b in range(SERVE_BEAMS):
+        chunks, _ = synth.stream_chunks(2, SERVE_ROWS, SERVE_COLS, seed=4000 + b, device=dev, wmax=256,
+                                        dtype=torch.float16)
+        payloads.append([c.cpu().pin_memory() for c in chunks])
+        del chunks
+    torch.cuda.empty_cache()
+    return payloads
+
+
+def serve_runs(B, payloads, plan):
+    """One server (widths 1..256, threshold 7, sqrt(N) sigma_N, two slots per
+    beam) driven through the runs of `plan` [(label, input rate x real time,
+    window s, chunk cap per beam)] one after another; latency is arrival to
+    candidates on the host, host-to-device copy included."""
+    import numpy as np
+    import torch
+    n_beams, R, C = SERVE_BEAMS, SERVE_ROWS, SERVE_COLS
+    chunk_sky = C * SAMPLE_S
+    srv = B.Server(n_beams, R, C, B.Params(list(range(1, 257)), 7.0), dtype=torch.float16, cand_capacity=1 << 16,
+                   slots_per_beam=2)
+    out_runs, base = [], [0] * n_beams
+    for label, rate_x, win, cap in plan:
+        lat, wall, n, per_beam = serve_run(B, _Offset(srv, list(base)), payloads, n_beams, rate_x, win, chunk_sky,
+                                           seed=len(out_runs), max_per_beam=cap)
+        base = [a + b for a, b in zip(base, per_beam)]
+        out_runs.append({"run": label, "input_rate_x_real_time": rate_x, "chunks": n,
+                         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                         "max_ms": round(float(lat.max()) * 1e3, 3), "wall_s": round(wall, 3),
+                         "GSamples_per_s": round(n * R * C / wall / 1e9, 3),
+                         "achieved_x_real_time": round(n * chunk_sky / n_beams / wall, 3)})
+    cnt = srv.counters()
+    srv.close()
+    return out_runs, cnt
+
+
+def serving_leg(dev, B, synth, paced_s):
+    """The serving form in brief for the default line: Poisson arrivals at
+    1.5x aggregate real time for paced_s seconds (p50/p99 chunk latency), then
+    an unpaced replay (highest sustained real-time factor and throughput)."""
+    payloads = serve_payloads(dev, synth)
+    runs, cnt = serve_runs(B, payloads, [("paced 1.5x real time", 1.5, paced_s, 1000),
+                                         ("replay 1000x", 1500.0, 0.25, 24)])
+    paced, fast = runs
+    return {"workload": "serve-%dbeams-%dx%d-f16 widths 1..256" % (SERVE_BEAMS, SERVE_ROWS, SERVE_COLS),
+            "p50_chunk_latency_ms": paced["p50_ms"], "p99_chunk_latency_ms": paced["p99_ms"],
+            "chunks_at_1.5x": paced["chunks"], "achieved_x_real_time_at_1.5x": paced["achieved_x_real_time"],
+            "max_real_time_factor": fast["achieved_x_real_time"], "GSamples/s": fast["GSamples_per_s"],
+            "runs": runs, "counters": cnt}
+
+
 def run_serve(args, dev):
     """Serving workload: 16 beams of 1,024 DM x 131,072 FP16 chunks (64 us
     sampling, 8.39 s of sky each), widths 1..256, threshold 7, carried halo
@@ -994,31 +1116,14 @@ def run_serve(args, dev):
 
     from paper_1611_09704_amd import binding as B
     from paper_1611_09704_amd import synth
-    n_beams, R, C = 16, 1024, 131072
+    n_beams, R, C = SERVE_BEAMS, SERVE_ROWS, SERVE_COLS
     W = list(range(1, 257))
     chunk_sky = C * SAMPLE_S
-    payloads = []
-    for b in range(n_beams):
-        chunks, _ = synth.stream_chunks(2, R, C, seed=4000 + b, device=dev, wmax=256, dtype=torch.float16)
-        payloads.append([c.cpu().pin_memory() for c in chunks])
-    srv = B.Server(n_beams, R, C, B.Params(W, 7.0), dtype=torch.float16, cand_capacity=1 << 16, slots_per_beam=2)
-    out_runs = []
+    payloads = serve_payloads(dev, synth)
     window = float(os.environ.get("SPD_SERVE_PACED_S", "20"))
-    base = [0] * n_beams
-    for label, rate_x, win, cap in [("paced 1.5x real time", 1.5, window, 1000), ("replay 10x", 15.0, 4.0, 1000),
-                                    ("replay 100x", 150.0, 1.0, 16), ("replay 1000x", 1500.0, 0.1, 16)]:
-        lat, wall, n, per_beam = serve_run(B, _Offset(srv, list(base)), payloads, n_beams, rate_x, win, chunk_sky,
-                                           seed=len(out_runs), max_per_beam=cap)
-        base = [a + b for a, b in zip(base, per_beam)]
-        samples = n * R * C
-        out_runs.append({"run": label, "input_rate_x_real_time": rate_x, "chunks": n,
-                         "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-                         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-                         "max_ms": round(float(lat.max()) * 1e3, 3), "wall_s": round(wall, 3),
-                         "GSamples_per_s": round(samples / wall / 1e9, 3),
-                         "achieved_x_real_time": round(n * chunk_sky / n_beams / wall, 3)})
-    cnt = srv.counters()
-    srv.close()
+    out_runs, cnt = serve_runs(B, payloads, [("paced 1.5x real time", 1.5, window, 1000),
+                                             ("replay 10x", 15.0, 4.0, 1000), ("replay 100x", 150.0, 1.0, 16),
+                                             ("replay 1000x", 1500.0, 0.1, 16)])
     fastest = out_runs[-1]
     cpu = None
     if not args.no_cpu_baseline:

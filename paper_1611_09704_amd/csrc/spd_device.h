@@ -1260,7 +1260,7 @@ __device__ __forceinline__ void short_block(const float* src, const float (&a)[N
         const float4 f = *(const float4*)(src + 4 * q);
         v[4 * q] = f.x; v[4 * q + 1] = f.y; v[4 * q + 2] = f.z; v[4 * q + 3] = f.w;
     }
-    packed = 0;
+    uint32_t ranks = 0;                                     // N-1-j of each start's width, one byte each
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         float b = v[i];
@@ -1271,8 +1271,9 @@ __device__ __forceinline__ void short_block(const float* src, const float (&a)[N
             m = key_max(m, __hiloint2double(__float_as_int(__fmul_rn(b, a[j])), N - 1 - j));
         }
         sv[i] = __int_as_float(__double2hiint(m));
-        packed |= (uint32_t)(N - 1 - __double2loint(m)) << (8 * i);
+        ranks |= (uint32_t)__double2loint(m) << (8 * i);
     }
+    packed = (uint32_t)(N - 1) * 0x01010101u - ranks;      // bytewise, no borrows: every rank <= N-1
 }
 
 // One candidate per (start, lane) with snr >= threshold among the lane's
