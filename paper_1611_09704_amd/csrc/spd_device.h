@@ -753,6 +753,21 @@ __device__ void boxcar_tile(const PlaneArg& pl, bool vec, int64_t r, int64_t tt,
     }
 }
 
+// The highest SNR and its first width in one max: the key of width index j
+// is the double whose high word is the SNR's bit pattern and whose low word is
+// N-1-j.  Doubles and floats are both sign-magnitude, so keys order as their
+// SNRs do; between equal SNRs the larger low word, i.e. the smaller j, wins
+// when the SNR is positive (zero included), and the larger j when it is
+// negative.  The maximum key carries the highest SNR exactly in its high word.
+// v_max_f64 runs at the FP32 rate; written out so that no canonicalising max
+// is inserted for the keys, which are not arithmetic results.
+__device__ __forceinline__ double key_max(double a, double b)
+{
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // Sec. 2.3 / Algorithm 1, register-window form
 // ---------------------------------------------------------------------------
@@ -887,8 +902,22 @@ __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t
             const float4 c = *(const float4*)(coef + j);
             a[j] = c.x; a[j + 1] = c.y; a[j + 2] = c.z; a[j + 3] = c.w;
         }
+        // the decimated search keeps, per start, the running maximum of FP64 keys
+        // (key_max) over its base widths and then over each level's widths
+        double mk[DIT ? X : 1];
 #pragma unroll
         for (int i = 0; i < X; ++i) {
+            if constexpr (DIT) {
+                float b = v[i];
+                double m = __hiloint2double(__float_as_int(__fmul_rn(b, a[0])), wp.n - 1);
+#pragma unroll
+                for (int j = 1; j < NS; ++j) {
+                    b = __fadd_rn(b, v[i + j]);
+                    m = key_max(m, __hiloint2double(__float_as_int(__fmul_rn(b, a[j])), wp.n - 1 - j));
+                }
+                mk[i] = m;
+                continue;
+            }
             float b = 0.f, s[NS];
 #pragma unroll
             for (int j = 0; j < NS; ++j) {
@@ -922,8 +951,9 @@ __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t
             // Decimated levels: level lv holds x'_lv[k] = x'_{lv-1}[2k] + x'_{lv-1}[2k+1].
             // Lane l evaluates widths 9..16 at its 8/2^lv decimated starts
             // 8l/2^lv + j (level 4: lane l/2, even lanes only), i.e. physical
-            // widths 2^lv*(9..16) at starts 8l + 2^lv*j, and keeps them where
-            // they beat the narrower widths (ascending width, strict '>').
+            // widths 2^lv*(9..16) at starts 8l + 2^lv*j, and merges their keys
+            // into those starts' running maxima (the list ascends, so equal
+            // positive SNRs keep the narrower width).
             const int levels = (wp.n - kDitBase) / (kDitBase / 2);
             float* lev = arrs + ba.npw;
             auto level = [&](auto lv_c) {
@@ -949,32 +979,31 @@ __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t
                 const float4 a03 = *(const float4*)(coef + c0);
                 const float4 a47 = *(const float4*)(coef + c0 + 4);
                 const float a[8] = {a03.x, a03.y, a03.z, a03.w, a47.x, a47.y, a47.z, a47.w};
+                const int rank0 = wp.n - 1 - c0;
 #pragma unroll
                 for (int j = 0; j < S; ++j) {
-                    float b = 0.f, sk[8];
+                    float b = v[j];
 #pragma unroll
-                    for (int q = 0; q < kDitBase; ++q) {
+                    for (int q = 1; q < kDitBase / 2; ++q) b = __fadd_rn(b, v[j + q]);
+                    double m = mk[LV < 4 ? (j << LV) : 0];
+#pragma unroll
+                    for (int q = kDitBase / 2; q < kDitBase; ++q) {
                         b = __fadd_rn(b, v[j + q]);
-                        if (q >= kDitBase / 2) sk[q - kDitBase / 2] = __fmul_rn(b, a[q - kDitBase / 2]);
+                        const float sq = __fmul_rn(b, a[q - kDitBase / 2]);
+                        m = key_max(m, __hiloint2double(__float_as_int(sq), rank0 - (q - kDitBase / 2)));
                     }
-                    float m = sk[0];
-#pragma unroll
-                    for (int q = 1; q < 8; ++q) m = fmaxf(m, sk[q]);
-                    int kk = 0;
-#pragma unroll
-                    for (int q = 7; q >= 0; --q) kk = (sk[q] == m) ? q : kk;
-                    const int i = LV < 4 ? (j << LV) : 0;
-                    const bool here = LV < 4 || (lane & 1) == 0;
-                    if (here && m > sv[i]) {
-                        sv[i] = m;
-                        iv[i] = c0 + kk;
-                    }
+                    if (LV < 4 || (lane & 1) == 0) mk[LV < 4 ? (j << LV) : 0] = m;
                 }
             };
             if (levels >= 1) level(std::integral_constant<int, 1>());
             if (levels >= 2) level(std::integral_constant<int, 2>());
             if (levels >= 3) level(std::integral_constant<int, 3>());
             if (levels >= 4) level(std::integral_constant<int, 4>());
+#pragma unroll
+            for (int i = 0; i < X; ++i) {
+                sv[i] = __int_as_float(__double2hiint(mk[i]));
+                iv[i] = wp.n - 1 - __double2loint(mk[i]);
+            }
         }
     } else {
         float B[X], mx[X], Bg[X];
@@ -1229,21 +1258,6 @@ __device__ __forceinline__ void put_shifted(float* d, float4 v, float mu_hi, flo
 {
     *(float4*)d = make_float4((v.x - mu_hi) - mu_lo, (v.y - mu_hi) - mu_lo, (v.z - mu_hi) - mu_lo,
                               (v.w - mu_hi) - mu_lo);
-}
-
-// The highest SNR and its first width in one max: the key of width index j
-// is the double whose high word is the SNR's bit pattern and whose low word is
-// N-1-j.  Doubles and floats are both sign-magnitude, so keys order as their
-// SNRs do; between equal SNRs the larger low word, i.e. the smaller j, wins
-// when the SNR is positive (zero included), and the larger j when it is
-// negative.  The maximum key carries the highest SNR exactly in its high word.
-// v_max_f64 runs at the FP32 rate; written out so that no canonicalising max
-// is inserted for the keys, which are not arithmetic results.
-__device__ __forceinline__ double key_max(double a, double b)
-{
-    double r;
-    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
 }
 
 // The 4 starts of one block for the list 1..N: their highest SNR and the index
