@@ -450,9 +450,16 @@ void spd_batch_plan_destroy(spd_batch_plan* plan);
  * of the next chunk: every boxcar window that ends inside chunk k is
  * evaluated with chunk k, exactly once, and its SNR uses the statistics after
  * chunk k (Sec. 2.2-2.4).  Candidate times are global sample indices.
- * Requests are admitted as soon as the beam has a free chunk buffer and every
- * earlier chunk of the beam was admitted; chunks of different beams run
- * concurrently on the device (one stream per beam), copies overlap work.
+ * Chunk buffers on the device come from one pool shared by the beams, sized
+ * from the device-memory budget: after the beams' own state (running
+ * statistics, statistics workspace, halos) the budget is cut into buffers, at
+ * most slots_per_beam per beam (all of them when the budget is 0).  Requests
+ * are admitted in arrival order across beams and chunk order within a beam as
+ * soon as a buffer is free and the beam has fewer than slots_per_beam chunks
+ * on the device; a buffer returns to the pool when its chunk's candidates are
+ * on the host.  The device work runs on n_streams compute streams plus as
+ * many copy streams (2*n_streams hardware queues): chunks of different beams
+ * overlap, copies overlap work, and each beam's chunks stay in order.
  * ------------------------------------------------------------------------ */
 typedef struct spd_server spd_server;
 
@@ -462,9 +469,9 @@ typedef struct {
     int64_t n_rows;            /* DM trials per chunk */
     int64_t chunk_cols;        /* new samples per chunk, >= the widest boxcar */
     int64_t cand_capacity;     /* candidates kept per chunk (more are counted, not kept) */
-    int32_t slots_per_beam;    /* device chunk buffers per beam, 1..8 (2: the next copy overlaps work) */
-    int32_t reserved0;
-    int64_t hbm_budget_bytes;  /* 0, or the most device memory the server may take */
+    int32_t slots_per_beam;    /* chunks of one beam on the device at once, 1..8 (2: the next copy overlaps work) */
+    int32_t n_streams;         /* compute streams (each with a copy stream), 0..8; 0 = 2 */
+    int64_t hbm_budget_bytes;  /* 0, or the most device memory the server may take; it sets the pool's buffers */
 } spd_server_config;
 
 typedef struct {
@@ -479,7 +486,9 @@ typedef struct {
     double done_s;             /* when its results reached the host */
 } spd_server_result;
 
-/* Device bytes a server with this configuration allocates (0 if invalid). */
+/* Device bytes a server with this configuration allocates (0 if invalid, or
+ * if the budget cannot hold the beams' state plus one chunk buffer).  Host
+ * only; for a server with de-dispersion in front see spd_server_info.      */
 size_t spd_server_device_bytes(const spd_server_config* cfg, const spd_params* p);
 
 /* Create a server (ALLOCATES all device buffers, pinned result buffers,
@@ -518,6 +527,10 @@ spd_status spd_server_poll(spd_server* server, spd_server_result* result, spd_ca
 
 /* Chunks submitted, admitted to the device, and completed so far. */
 spd_status spd_server_counters(spd_server* server, int64_t* submitted, int64_t* admitted, int64_t* completed);
+
+/* The server's pool of chunk buffers, its compute streams and the device
+ * bytes it allocated (any output may be NULL).                             */
+spd_status spd_server_info(spd_server* server, int32_t* pool_buffers, int32_t* n_streams, int64_t* device_bytes);
 
 /* Finish the chunks in flight, stop the worker and free everything. */
 void spd_server_destroy(spd_server* server);

@@ -65,7 +65,7 @@ class SpdBand(ctypes.Structure):
 class SpdServerConfig(ctypes.Structure):
     _fields_ = [("n_beams", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n_rows", ctypes.c_int64),
                 ("chunk_cols", ctypes.c_int64), ("cand_capacity", ctypes.c_int64),
-                ("slots_per_beam", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("slots_per_beam", ctypes.c_int32), ("n_streams", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_int64)]
 
 
@@ -149,6 +149,8 @@ def load():
         lib.spd_server_counters.argtypes = [vp, P(i64), P(i64), P(i64)]
         lib.spd_server_counters.restype = ctypes.c_int
         lib.spd_server_destroy.argtypes = [vp]
+        lib.spd_server_info.argtypes = [vp, P(i32), P(i32), P(i64)]
+        lib.spd_server_info.restype = ctypes.c_int
         lib.spd_server_destroy.restype = None
         lib.spd_batch_plan_destroy.argtypes = [vp]
         lib.spd_batch_plan_destroy.restype = None
@@ -575,23 +577,34 @@ def steady_now() -> float:
     return time.monotonic()
 
 
+def server_device_bytes(n_beams: int, n_rows: int, chunk_cols: int, params: Params, dtype=torch.float16,
+                        cand_capacity: int = 1 << 16, slots_per_beam: int = 2, hbm_budget_bytes: int = 0) -> int:
+    """Device bytes a server (no de-dispersion) of this configuration would
+    allocate; 0 when the budget cannot hold the beams' state and one buffer."""
+    dt = {torch.float32: SPD_F32, torch.float16: SPD_F16}[dtype]
+    cfg = SpdServerConfig(n_beams, dt, n_rows, chunk_cols, cand_capacity, slots_per_beam, 0, hbm_budget_bytes)
+    return load().spd_server_device_bytes(ctypes.byref(cfg), ctypes.byref(params.c))
+
+
 class Server:
     """Serving form (spd_server_*): chunk streams from several beams with
     carried halo and running statistics; results are polled as they finish."""
 
     def __init__(self, n_beams: int, n_rows: int, chunk_cols: int, params: Params, dtype=torch.float16,
                  cand_capacity: int = 1 << 16, slots_per_beam: int = 2, hbm_budget_bytes: int = 0,
-                 dedisp: Optional["DedispPlan"] = None):
+                 dedisp: Optional["DedispPlan"] = None, n_streams: int = 0):
         """With ``dedisp`` (a DedispPlan, kept alive by the server) the beams
         stream uint8 filterbank chunks [n_chan][chunk_cols], de-dispersed on
-        the device in front of the detection stream."""
+        the device in front of the detection stream.  ``hbm_budget_bytes``
+        sizes the shared pool of chunk buffers; ``n_streams`` compute streams
+        (0: 2) each with a copy stream carry the work."""
         lib = load()
         if dedisp is not None:
             dtype = torch.uint8
         dt = {torch.float32: SPD_F32, torch.float16: SPD_F16, torch.uint8: SPD_U8}[dtype]
         self.params = params
         self.dedisp = dedisp
-        self.cfg = SpdServerConfig(n_beams, dt, n_rows, chunk_cols, cand_capacity, slots_per_beam, 0,
+        self.cfg = SpdServerConfig(n_beams, dt, n_rows, chunk_cols, cand_capacity, slots_per_beam, n_streams,
                                    hbm_budget_bytes)
         self.cap = cand_capacity
         self._buf = np.empty(cand_capacity, dtype=CANDIDATE_DTYPE)
@@ -625,6 +638,11 @@ class Server:
         self._keep.pop((res.beam, res.seq), None)
         out = {f: getattr(res, f) for f, _ in SpdServerResult._fields_}
         return out, self._buf[:res.n_copied].copy()
+
+    def info(self) -> dict:
+        n, q, m = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(load().spd_server_info(self._h, ctypes.byref(n), ctypes.byref(q), ctypes.byref(m)))
+        return {"pool_buffers": n.value, "n_streams": q.value, "device_bytes": m.value}
 
     def counters(self) -> dict:
         a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

@@ -2,28 +2,32 @@
 // chunks from several beams (Sec. 2.1-2.4 applied chunk by chunk).
 //
 // Each beam streams consecutive chunks of [n_rows][chunk_cols] new samples.
-// The server keeps, per beam and on the device:
+// Per beam the server keeps on the device:
 //   - the running FP64 statistics (Eq. MSD04 merges each chunk's partials), so
 //     mean and sigma cover every sample received so far;
-//   - the last Nmax-1 columns of the previous chunk (the halo), placed in front
-//     of the next chunk so every boxcar window that ends in the new chunk is
-//     evaluated exactly once;
-//   - `slots_per_beam` chunk buffers, so the host-to-device copy of chunk k+1
-//     overlaps the work on chunk k.
-// Requests are admitted as soon as their beam has a free slot and every
-// earlier chunk of the beam has been admitted (continuous batching: nothing
-// waits for a batch to fill).  Each beam has its own compute stream, so chunks
-// of different beams run concurrently on the device while chunks of one beam
-// stay in order; copies run on per-beam copy streams, a chunk in row groups
-// whose statistics and boxcars start as soon as their rows have arrived.  A
-// worker thread admits requests and detects completions; spd_server_poll
-// hands finished chunks out.
+//   - the last Nmax-1 columns of its previous chunk (the halo), put in front of
+//     the next chunk so every boxcar window that ends in the new chunk is
+//     evaluated exactly once.
+// Chunk buffers come from one pool shared by all beams.  Its size follows the
+// device-memory budget: what the per-beam state takes is set aside and the
+// rest is cut into buffers (at most slots_per_beam per beam, all of them when
+// there is no budget).  A request is admitted, in arrival order across beams
+// and in chunk order within a beam, as soon as a buffer is free and its beam
+// has fewer than slots_per_beam chunks on the device; the buffer goes back to
+// the pool when the chunk's candidates are on the host (continuous batching:
+// nothing waits for a batch to fill).  The device work runs on a small pool of
+// streams (n_streams compute streams and as many copy streams, so the server
+// occupies 2*n_streams hardware queues): chunks of different beams overlap,
+// and an event per beam keeps each beam's chunks in order.  A chunk is copied
+// in row groups whose statistics and boxcars start as soon as their rows have
+// arrived.  A worker thread admits requests and detects completions;
+// spd_server_poll hands finished chunks out.
 //
 // With a de-dispersion plan in front (spd_server_create_dedisp) a beam streams
 // 8-bit filterbank chunks instead.  The server also keeps the beam's last
 // max-delay filterbank columns (rounded up to 4 bytes), de-disperses
-// [filterbank halo | chunk] into the beam's DM-trial x time plane right
-// behind its detection halo, and runs the detection stream on that plane.
+// [filterbank halo | chunk] into the chunk buffer's DM-trial x time plane
+// right behind its detection halo, and runs the detection steps on that plane.
 // Chunk 0 yields chunk_cols - max_delay new de-dispersed starts, every later
 // chunk chunk_cols (global starts k * chunk_cols - max_delay onwards).
 #include <hip/hip_runtime.h>
@@ -48,6 +52,7 @@ namespace spd {
 // (rows are independent under per-row statistics), so a chunk's latency is
 // close to its copy time plus the work of one group.
 constexpr int kServeRowGroups = 4;
+constexpr int kServeMaxStreams = 8;
 
 static double now_s()
 {
@@ -60,7 +65,7 @@ struct ServeReq {
     int64_t seq = 0;
     const void* host = nullptr;
     double submit_s = 0.0, start_s = 0.0, done_s = 0.0;
-    int slot = 0;
+    int buf = 0;                           // pool buffer while admitted
 };
 
 struct ServeDone {
@@ -68,24 +73,29 @@ struct ServeDone {
     std::vector<spd_candidate> cands;
 };
 
+// One chunk buffer of the pool.
+struct ServeBuf {
+    void* plane = nullptr;                 // device [det_rows][H + C]: halo, then the chunk's columns
+    void* stage = nullptr;                 // device [n_rows][C], the contiguous copy-in target
+    void* fb = nullptr;                    // device [n_chan][fb_pitch] filterbank (de-dispersion)
+    spd_candidate* d_cand = nullptr;
+    int64_t* d_count = nullptr;
+    spd_candidate* h_cand = nullptr;       // pinned
+    int64_t* h_count = nullptr;
+    hipEvent_t h2d[kServeRowGroups] = {};  // a row group of the chunk is on the device
+    hipEvent_t done = nullptr;             // count and candidates are on the host
+};
+
 struct ServeBeam {
-    std::deque<ServeReq> pending;          // submitted, not admitted
     std::deque<ServeReq> inflight;         // admitted, not complete (in order)
     int64_t next_submit = 0;               // next sequence number accepted
-    std::vector<void*> buf;                // [slots] device [n_rows][H + C]
-    std::vector<void*> stage;              // [slots] device [n_rows][C], the contiguous copy-in target
-    std::vector<void*> fb;                 // [slots] device [n_chan][fb_pitch] filterbank (de-dispersion)
-    std::vector<spd_candidate*> d_cand;    // [slots]
-    std::vector<int64_t*> d_count;
-    std::vector<spd_candidate*> h_cand;    // pinned
-    std::vector<int64_t*> h_count;
-    std::vector<hipEvent_t> h2d_done;      // [slots][kServeRowGroups]: a row group of the chunk is on the device
-    std::vector<hipEvent_t> free_ev, done_ev;
+    void* halo = nullptr;                  // device [det_rows][H]: last columns of the previous chunk
+    void* fb_halo = nullptr;               // device [n_chan][dd_halo]: last filterbank columns (de-dispersion)
+    hipEvent_t ready = nullptr;            // the beam's previous chunk has left its state and halos
     spd_msd_state* state = nullptr;
     spd_row_stats* stats = nullptr;
     void* ws = nullptr;
     size_t ws_bytes = 0;
-    hipStream_t stream = nullptr, copy = nullptr;
 };
 
 }  // namespace spd
@@ -102,8 +112,15 @@ struct spd_server {
     const spd_dedisp_plan* dd = nullptr;   // de-dispersion in front, or none
     int64_t dd_delay = 0;                  // the plan's largest delay (samples)
     int64_t dd_halo = 0;                   // filterbank columns kept: dd_delay rounded up to 4
-    int64_t fb_pitch = 0;                  // bytes per filterbank row in a slot
+    int64_t fb_pitch = 0;                  // bytes per filterbank row in a buffer
+    int n_streams = 2;
+    hipStream_t compute[spd::kServeMaxStreams] = {}, copy[spd::kServeMaxStreams] = {};
+    int64_t launches = 0;                  // chunks launched (picks the stream pair)
     std::vector<spd::ServeBeam> beams;
+    std::vector<spd::ServeBuf> pool;
+    std::vector<int> free_bufs;
+    std::deque<spd::ServeReq> pending;     // submitted, not admitted, in arrival order
+    size_t device_bytes = 0;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<spd::ServeDone> done;
@@ -134,12 +151,12 @@ static int64_t chunk_t_offset(const spd_server* S, int64_t seq)
     return seq == 0 ? 0 : first_col(S, seq) - S->halo;
 }
 
-static spd_plane view_plane(const spd_server* S, const ServeBeam& b, int slot, int64_t seq)
+static spd_plane view_plane(const spd_server* S, const ServeBuf& pb, int64_t seq)
 {
     spd_plane x;
     memset(&x, 0, sizeof x);
     const int64_t pitch = S->halo + S->cfg.chunk_cols;
-    const char* base = (const char*)b.buf[slot];
+    const char* base = (const char*)pb.plane;
     if (seq == 0) {                                 // first chunk: no halo in front
         x.data = base + S->halo * S->esize;
         x.n_cols = new_cols(S, 0);
@@ -153,19 +170,25 @@ static spd_plane view_plane(const spd_server* S, const ServeBeam& b, int slot, i
     return x;
 }
 
-// De-dispersion of one chunk on the beam's compute stream: re-pitch the
-// staged bytes behind the filterbank halo, de-disperse into the detection
-// plane behind its halo, and hand the last dd_halo filterbank columns on to
-// the next slot.  After chunk 0 the view starts dd_halo - dd_delay (< 4)
-// columns early so that its rows stay 4-byte aligned; those first outputs
-// repeat the previous chunk's last ones exactly (whole-count sums) and land
-// on the same columns of the detection halo.
-static spd_status dedisperse_chunk(spd_server* S, ServeBeam& b, int slot, int64_t seq)
+// De-dispersion of one chunk on compute stream cs: the beam's filterbank
+// halo in front (after chunk 0), the staged bytes re-pitched behind it, the
+// de-dispersion into the detection plane behind its halo, and the last dd_halo
+// filterbank columns kept for the beam's next chunk.  After chunk 0 the view
+// starts dd_halo - dd_delay (< 4) columns early so that its rows stay 4-byte
+// aligned; those first outputs repeat the previous chunk's last ones exactly
+// (whole-count sums) and land on the same columns of the detection halo.
+static spd_status dedisperse_chunk(spd_server* S, ServeBeam& b, ServeBuf& pb, int64_t seq, hipStream_t cs)
 {
     const int64_t C = S->cfg.chunk_cols, Hf = S->dd_halo, R = S->cfg.n_rows, H = S->halo;
-    char* fb = (char*)b.fb[slot];
-    hipError_t e = hipMemcpy2DAsync(fb + Hf, (size_t)S->fb_pitch, b.stage[slot], (size_t)C, (size_t)C, (size_t)R,
-                                    hipMemcpyDeviceToDevice, b.stream);
+    char* fb = (char*)pb.fb;
+    hipError_t e;
+    if (seq > 0 && Hf > 0) {
+        e = hipMemcpy2DAsync(fb, (size_t)S->fb_pitch, b.fb_halo, (size_t)Hf, (size_t)Hf, (size_t)R,
+                             hipMemcpyDeviceToDevice, cs);
+        if (e != hipSuccess) return device_status(e, "filterbank halo in");
+    }
+    e = hipMemcpy2DAsync(fb + Hf, (size_t)S->fb_pitch, pb.stage, (size_t)C, (size_t)C, (size_t)R,
+                         hipMemcpyDeviceToDevice, cs);
     if (e != hipSuccess) return device_status(e, "filterbank re-pitch");
     spd_plane f;
     memset(&f, 0, sizeof f);
@@ -175,43 +198,51 @@ static spd_status dedisperse_chunk(spd_server* S, ServeBeam& b, int slot, int64_
     f.data = seq == 0 ? fb + Hf : fb;
     f.n_cols = seq == 0 ? C : Hf + C;
     const int64_t lead = seq == 0 ? 0 : Hf - S->dd_delay;
-    float* out = (float*)b.buf[slot] + (H - lead);
-    spd_status st = spd_dedisperse(S->dd, &f, out, H + C, b.stream);
+    float* out = (float*)pb.plane + (H - lead);
+    spd_status st = spd_dedisperse(S->dd, &f, out, H + C, cs);
     if (st) return st;
-    e = hipMemcpy2DAsync((char*)b.fb[(slot + 1) % S->cfg.slots_per_beam], (size_t)S->fb_pitch, fb + C,
-                         (size_t)S->fb_pitch, (size_t)Hf, (size_t)R, hipMemcpyDeviceToDevice, b.stream);
-    return device_status(e, "filterbank halo copy");
+    if (Hf > 0) {
+        e = hipMemcpy2DAsync(b.fb_halo, (size_t)Hf, fb + C, (size_t)S->fb_pitch, (size_t)Hf, (size_t)R,
+                             hipMemcpyDeviceToDevice, cs);
+        if (e != hipSuccess) return device_status(e, "filterbank halo out");
+    }
+    return SPD_OK;
 }
 
-// Enqueue one admitted chunk: copy in, statistics, boxcar/SNR with the fused
-// threshold, halo hand-over to the next slot, candidates back to the host.
+// Enqueue one admitted chunk in its pool buffer on the next stream pair: copy
+// in, statistics, boxcar/SNR with the fused threshold, the beam's halo, and
+// the candidates back to the host.
 static spd_status launch_chunk(spd_server* S, ServeReq& r)
 {
     ServeBeam& b = S->beams[r.beam];
-    const int slots = S->cfg.slots_per_beam;
-    const int slot = (int)(r.seq % slots);
-    r.slot = slot;
+    ServeBuf& pb = S->pool[r.buf];
+    const int q = (int)(S->launches++ % S->n_streams);
+    hipStream_t cs = S->compute[q], ps = S->copy[q];
     const int64_t C = S->cfg.chunk_cols, H = S->halo, R = S->cfg.n_rows, D = S->det_rows;
     const size_t pitch_b = (size_t)(H + C) * S->esize;
-    char* base = (char*)b.buf[slot];
+    char* base = (char*)pb.plane;
     hipError_t e;
-    // the slot's previous chunk has handed its halo on and is finished
-    if ((e = hipStreamWaitEvent(b.copy, b.free_ev[slot], 0)) != hipSuccess) return device_status(e, "wait free");
     spd_status st;
-    const spd_plane x = view_plane(S, b, slot, r.seq);
+    // in order within the beam: its previous chunk has left the state and halos
+    if ((e = hipStreamWaitEvent(cs, b.ready, 0)) != hipSuccess) return device_status(e, "wait beam");
+    if (r.seq > 0 && H > 0) {
+        e = hipMemcpy2DAsync(base, pitch_b, b.halo, (size_t)H * S->esize, (size_t)H * S->esize, (size_t)D,
+                             hipMemcpyDeviceToDevice, cs);
+        if (e != hipSuccess) return device_status(e, "halo in");
+    }
+    const spd_plane x = view_plane(S, pb, r.seq);
     if (S->dd) {
         // de-dispersion needs every channel: one contiguous host-to-device copy
-        e = hipMemcpyAsync(b.stage[slot], r.host, (size_t)R * C * S->in_esize, hipMemcpyHostToDevice, b.copy);
+        e = hipMemcpyAsync(pb.stage, r.host, (size_t)R * C * S->in_esize, hipMemcpyHostToDevice, ps);
         if (e != hipSuccess) return device_status(e, "chunk copy-in");
-        hipEvent_t h2d = b.h2d_done[(size_t)slot * kServeRowGroups];
-        if ((e = hipEventRecord(h2d, b.copy)) != hipSuccess) return device_status(e, "record h2d");
-        if ((e = hipStreamWaitEvent(b.stream, h2d, 0)) != hipSuccess) return device_status(e, "wait h2d");
-        if ((st = dedisperse_chunk(S, b, slot, r.seq))) return st;
+        if ((e = hipEventRecord(pb.h2d[0], ps)) != hipSuccess) return device_status(e, "record h2d");
+        if ((e = hipStreamWaitEvent(cs, pb.h2d[0], 0)) != hipSuccess) return device_status(e, "wait h2d");
+        if ((st = dedisperse_chunk(S, b, pb, r.seq, cs))) return st;
         st = msd_compute(&x, &S->params, r.seq == 0 ? 0 : H, r.seq == 0 ? 0 : 1, b.state, b.stats, b.ws, b.ws_bytes,
-                         b.stream);
+                         cs);
         if (st) return st;
-        st = boxcar_snr(&x, &S->params, b.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq), b.d_cand[slot],
-                        S->cfg.cand_capacity, b.d_count[slot], b.stream);
+        st = boxcar_snr(&x, &S->params, b.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq), pb.d_cand,
+                        S->cfg.cand_capacity, pb.d_count, cs);
         if (st) return st;
     } else {
         // row groups: each is one contiguous host-to-device copy (full link speed), then a
@@ -220,78 +251,85 @@ static spd_status launch_chunk(spd_server* S, ServeReq& r)
         const MsdLayout m = msd_layout(&x);
         if ((st = check_msd_workspace(&x, m, b.ws, b.ws_bytes))) return st;
         BoxcarPlan bp;
-        if ((st = plan_boxcar(&x, &S->params, b.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq), b.d_cand[slot],
-                              S->cfg.cand_capacity, b.d_count[slot], bp)))
+        if ((st = plan_boxcar(&x, &S->params, b.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq), pb.d_cand,
+                              S->cfg.cand_capacity, pb.d_count, bp)))
             return st;
-        if ((e = launch_zero_count(b.d_count[slot], b.stream)) != hipSuccess) return device_status(e, "count reset");
+        if ((e = launch_zero_count(pb.d_count, cs)) != hipSuccess) return device_status(e, "count reset");
         const int64_t per = (R + kServeRowGroups - 1) / kServeRowGroups;
         for (int g = 0; g < kServeRowGroups; ++g) {
             const int64_t r0 = (int64_t)g * per, rows = std::min<int64_t>(per, R - r0);
             if (rows <= 0) break;
             const size_t in_off = (size_t)r0 * (size_t)C * S->in_esize;
-            e = hipMemcpyAsync((char*)b.stage[slot] + in_off, (const char*)r.host + in_off,
-                               (size_t)rows * (size_t)C * S->in_esize, hipMemcpyHostToDevice, b.copy);
+            e = hipMemcpyAsync((char*)pb.stage + in_off, (const char*)r.host + in_off,
+                               (size_t)rows * (size_t)C * S->in_esize, hipMemcpyHostToDevice, ps);
             if (e != hipSuccess) return device_status(e, "chunk copy-in");
-            hipEvent_t h2d = b.h2d_done[(size_t)slot * kServeRowGroups + g];
-            if ((e = hipEventRecord(h2d, b.copy)) != hipSuccess) return device_status(e, "record h2d");
-            if ((e = hipStreamWaitEvent(b.stream, h2d, 0)) != hipSuccess) return device_status(e, "wait h2d");
-            e = hipMemcpy2DAsync(base + (size_t)r0 * pitch_b + H * S->esize, pitch_b, (char*)b.stage[slot] + in_off,
-                                 (size_t)C * S->esize, (size_t)C * S->esize, (size_t)rows, hipMemcpyDeviceToDevice,
-                                 b.stream);
+            if ((e = hipEventRecord(pb.h2d[g], ps)) != hipSuccess) return device_status(e, "record h2d");
+            if ((e = hipStreamWaitEvent(cs, pb.h2d[g], 0)) != hipSuccess) return device_status(e, "wait h2d");
+            e = hipMemcpy2DAsync(base + (size_t)r0 * pitch_b + H * S->esize, pitch_b, (char*)pb.stage + in_off,
+                                 (size_t)C * S->esize, (size_t)C * S->esize, (size_t)rows, hipMemcpyDeviceToDevice, cs);
             if (e != hipSuccess) return device_status(e, "chunk re-pitch");
             const spd_plane sub = row_slice(&x, r0, rows);
             if ((st = enqueue_msd(&sub, &S->params, r.seq == 0 ? 0 : H, r.seq != 0, b.state + r0, b.stats + r0,
-                                  (double*)b.ws, m, b.stream)))
+                                  (double*)b.ws, m, cs)))
                 return st;
-            if ((st = enqueue_boxcar(&sub, b.stats + r0, bp, r0, rows, b.stream))) return st;
+            if ((st = enqueue_boxcar(&sub, b.stats + r0, bp, r0, rows, cs))) return st;
         }
     }
-    if (H > 0) {                                    // last H columns become the next chunk's halo
-        char* next = (char*)b.buf[(slot + 1) % slots];
-        e = hipMemcpy2DAsync(next, pitch_b, base + new_cols(S, r.seq) * S->esize, pitch_b, (size_t)H * S->esize,
-                             (size_t)D, hipMemcpyDeviceToDevice, b.stream);
-        if (e != hipSuccess) return device_status(e, "halo copy");
+    if (H > 0) {                                    // the last H columns become the beam's halo
+        e = hipMemcpy2DAsync(b.halo, (size_t)H * S->esize, base + new_cols(S, r.seq) * S->esize, pitch_b,
+                             (size_t)H * S->esize, (size_t)D, hipMemcpyDeviceToDevice, cs);
+        if (e != hipSuccess) return device_status(e, "halo out");
     }
-    if ((e = hipEventRecord(b.free_ev[slot], b.stream)) != hipSuccess) return device_status(e, "record free");
-    e = hipMemcpyAsync(b.h_count[slot], b.d_count[slot], sizeof(int64_t), hipMemcpyDeviceToHost, b.stream);
+    if ((e = hipEventRecord(b.ready, cs)) != hipSuccess) return device_status(e, "record beam");
+    e = hipMemcpyAsync(pb.h_count, pb.d_count, sizeof(int64_t), hipMemcpyDeviceToHost, cs);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(b.h_cand[slot], b.d_cand[slot], sizeof(spd_candidate) * (size_t)S->cfg.cand_capacity,
-                           hipMemcpyDeviceToHost, b.stream);
+        e = hipMemcpyAsync(pb.h_cand, pb.d_cand, sizeof(spd_candidate) * (size_t)S->cfg.cand_capacity,
+                           hipMemcpyDeviceToHost, cs);
     if (e != hipSuccess) return device_status(e, "candidates copy-out");
-    if ((e = hipEventRecord(b.done_ev[slot], b.stream)) != hipSuccess) return device_status(e, "record done");
+    if ((e = hipEventRecord(pb.done, cs)) != hipSuccess) return device_status(e, "record done");
     return SPD_OK;
 }
 
 static void worker_loop(spd_server* S)
 {
     (void)hipSetDevice(S->device);
+    std::vector<char> blocked(S->beams.size());
     std::unique_lock<std::mutex> lk(S->mu);
     while (!S->stop) {
         bool progress = false;
-        // admission: in order per beam, while the beam has a free slot
-        for (size_t bi = 0; bi < S->beams.size() && S->fault == SPD_OK; ++bi) {
-            ServeBeam& b = S->beams[bi];
-            while (!b.pending.empty() && (int)b.inflight.size() < S->cfg.slots_per_beam) {
-                ServeReq r = b.pending.front();
-                b.pending.pop_front();
-                r.start_s = now_s();
-                const spd_status st = launch_chunk(S, r);
-                if (st) {
-                    S->fault = st;
-                    S->fault_msg = spd_last_error();
-                    break;
-                }
-                b.inflight.push_back(r);
-                ++S->n_admitted;
-                progress = true;
+        // admission: arrival order across beams, chunk order within a beam, while a
+        // pool buffer is free and the beam has fewer than slots_per_beam chunks in flight
+        std::fill(blocked.begin(), blocked.end(), 0);
+        for (auto it = S->pending.begin(); it != S->pending.end() && !S->free_bufs.empty() && S->fault == SPD_OK;) {
+            ServeBeam& b = S->beams[it->beam];
+            if (blocked[it->beam] || (int)b.inflight.size() >= S->cfg.slots_per_beam) {
+                blocked[it->beam] = 1;
+                ++it;
+                continue;
             }
+            ServeReq r = *it;
+            it = S->pending.erase(it);
+            r.buf = S->free_bufs.back();
+            S->free_bufs.pop_back();
+            r.start_s = now_s();
+            const spd_status st = launch_chunk(S, r);
+            if (st) {
+                S->fault = st;
+                S->fault_msg = spd_last_error();
+                S->free_bufs.push_back(r.buf);
+                break;
+            }
+            b.inflight.push_back(r);
+            ++S->n_admitted;
+            progress = true;
         }
-        // completions: the oldest in-flight chunk of each beam
+        // completions: the oldest in-flight chunk of each beam; its buffer returns to the pool
         for (size_t bi = 0; bi < S->beams.size(); ++bi) {
             ServeBeam& b = S->beams[bi];
             while (!b.inflight.empty()) {
                 ServeReq& r = b.inflight.front();
-                const hipError_t q = hipEventQuery(b.done_ev[r.slot]);
+                const ServeBuf& pb = S->pool[r.buf];
+                const hipError_t q = hipEventQuery(pb.done);
                 if (q == hipErrorNotReady) break;
                 ServeDone d;
                 memset(&d.res, 0, sizeof d.res);
@@ -304,13 +342,14 @@ static void worker_loop(spd_server* S)
                 if (q != hipSuccess) {
                     d.res.status = SPD_E_DEVICE;
                 } else {
-                    const int64_t n = *b.h_count[r.slot];
+                    const int64_t n = *pb.h_count;
                     d.res.n_cands = n;
                     d.res.status = n > S->cfg.cand_capacity ? SPD_E_NOMEM : SPD_OK;
                     const int64_t k = n < S->cfg.cand_capacity ? n : S->cfg.cand_capacity;
-                    d.cands.assign(b.h_cand[r.slot], b.h_cand[r.slot] + k);
+                    d.cands.assign(pb.h_cand, pb.h_cand + k);
                     for (auto& c : d.cands) c.beam = (uint32_t)r.beam;
                 }
+                S->free_bufs.push_back(r.buf);
                 S->done.push_back(std::move(d));
                 b.inflight.pop_front();
                 ++S->n_completed;
@@ -342,26 +381,67 @@ static size_t serve_ws_bytes(int64_t rows, int64_t halo, int64_t cols)
     return a > b ? a : b;
 }
 
+// Device bytes of a server: what each beam keeps (running statistics, the
+// statistics workspace, the halos) and what one pool buffer holds (the chunk
+// with its halo, the staged copy, the filterbank, the candidate list), and
+// the number of pool buffers the budget allows.
+struct ServeSizes {
+    size_t per_beam = 0, per_buf = 0;
+    int64_t buffers = 0;                 // 0: the budget does not hold the beams' state and one buffer
+    size_t total = 0;
+};
+
+static ServeSizes serve_sizes(const spd_server_config* cfg, int64_t H, int64_t det_rows, int det_esize,
+                              int64_t dd_halo, int64_t fb_pitch, bool dd)
+{
+    ServeSizes z;
+    const int in_es = elem_size(cfg->dtype);
+    z.per_beam = (size_t)det_rows * (sizeof(spd_msd_state) + sizeof(spd_row_stats)) +
+                 serve_ws_bytes(det_rows, H, cfg->chunk_cols) + (size_t)det_rows * (size_t)H * det_esize +
+                 (dd ? (size_t)cfg->n_rows * (size_t)dd_halo : 0);
+    z.per_buf = (size_t)det_rows * (size_t)(H + cfg->chunk_cols) * det_esize +
+                (size_t)cfg->n_rows * (size_t)cfg->chunk_cols * in_es +
+                (dd ? (size_t)cfg->n_rows * (size_t)fb_pitch : 0) +
+                (size_t)cfg->cand_capacity * sizeof(spd_candidate) + sizeof(int64_t);
+    const int64_t most = (int64_t)cfg->n_beams * cfg->slots_per_beam;
+    const size_t beams = z.per_beam * (size_t)cfg->n_beams;
+    if (cfg->hbm_budget_bytes <= 0) {
+        z.buffers = most;
+    } else if ((size_t)cfg->hbm_budget_bytes > beams) {
+        z.buffers = std::min<int64_t>(most, (int64_t)(((size_t)cfg->hbm_budget_bytes - beams) / z.per_buf));
+    }
+    z.total = beams + (size_t)z.buffers * z.per_buf;
+    return z;
+}
+
 static void free_server(spd_server* S)
 {
+    for (int q = 0; q < S->n_streams; ++q) {
+        if (S->compute[q]) (void)hipStreamSynchronize(S->compute[q]);
+        if (S->copy[q]) (void)hipStreamSynchronize(S->copy[q]);
+    }
+    for (auto& pb : S->pool) {
+        if (pb.plane) (void)hipFree(pb.plane);
+        if (pb.stage) (void)hipFree(pb.stage);
+        if (pb.fb) (void)hipFree(pb.fb);
+        if (pb.d_cand) (void)hipFree(pb.d_cand);
+        if (pb.d_count) (void)hipFree(pb.d_count);
+        if (pb.h_cand) (void)hipHostFree(pb.h_cand);
+        if (pb.h_count) (void)hipHostFree(pb.h_count);
+        for (auto ev : pb.h2d) if (ev) (void)hipEventDestroy(ev);
+        if (pb.done) (void)hipEventDestroy(pb.done);
+    }
     for (auto& b : S->beams) {
-        if (b.stream) (void)hipStreamSynchronize(b.stream);
-        if (b.copy) (void)hipStreamSynchronize(b.copy);
-        for (void* p : b.buf) if (p) (void)hipFree(p);
-        for (void* p : b.stage) if (p) (void)hipFree(p);
-        for (void* p : b.fb) if (p) (void)hipFree(p);
-        for (auto* p : b.d_cand) if (p) (void)hipFree(p);
-        for (auto* p : b.d_count) if (p) (void)hipFree(p);
-        for (auto* p : b.h_cand) if (p) (void)hipHostFree(p);
-        for (auto* p : b.h_count) if (p) (void)hipHostFree(p);
-        for (auto ev : b.h2d_done) if (ev) (void)hipEventDestroy(ev);
-        for (auto ev : b.free_ev) if (ev) (void)hipEventDestroy(ev);
-        for (auto ev : b.done_ev) if (ev) (void)hipEventDestroy(ev);
+        if (b.halo) (void)hipFree(b.halo);
+        if (b.fb_halo) (void)hipFree(b.fb_halo);
+        if (b.ready) (void)hipEventDestroy(b.ready);
         if (b.state) (void)hipFree(b.state);
         if (b.stats) (void)hipFree(b.stats);
         if (b.ws) (void)hipFree(b.ws);
-        if (b.stream) (void)hipStreamDestroy(b.stream);
-        if (b.copy) (void)hipStreamDestroy(b.copy);
+    }
+    for (int q = 0; q < S->n_streams; ++q) {
+        if (S->compute[q]) (void)hipStreamDestroy(S->compute[q]);
+        if (S->copy[q]) (void)hipStreamDestroy(S->copy[q]);
     }
     delete S;
 }
@@ -376,32 +456,20 @@ size_t spd_server_device_bytes(const spd_server_config* cfg, const spd_params* p
 {
     clear_error();
     if (!cfg || check_params(p)) return 0;
-    const int es = elem_size(cfg->dtype);
+    if (cfg->n_beams < 1 || cfg->slots_per_beam < 1) return 0;
     const int64_t H = p->widths[p->n_widths - 1] - 1;
-    const size_t ws = serve_ws_bytes(cfg->n_rows, H, cfg->chunk_cols);
-    const size_t per_beam = (size_t)cfg->slots_per_beam *
-                                ((size_t)cfg->n_rows * (size_t)(H + 2 * cfg->chunk_cols) * es +
-                                 (size_t)cfg->cand_capacity * sizeof(spd_candidate) + 256) +
-                            (size_t)cfg->n_rows * (sizeof(spd_msd_state) + sizeof(spd_row_stats)) + ws;
-    return per_beam * (size_t)cfg->n_beams;
+    const ServeSizes z = serve_sizes(cfg, H, cfg->n_rows, elem_size(cfg->dtype), 0, 0, false);
+    if (z.buffers < 1) {
+        fail(SPD_E_NOMEM, "budget %lld bytes < %zu for the beams' state and one chunk buffer",
+             (long long)cfg->hbm_budget_bytes, z.per_beam * (size_t)cfg->n_beams + z.per_buf);
+        return 0;
+    }
+    return z.total;
 }
 
 }  // extern "C"
 
 namespace spd {
-
-// Device bytes of a server with de-dispersion in front: per slot the staged
-// chunk, the filterbank with its halo and the FP32 detection plane.
-static size_t dedisp_server_bytes(const spd_server_config* cfg, int64_t H, int64_t n_dm, int64_t fb_pitch)
-{
-    const size_t ws = serve_ws_bytes(n_dm, H, cfg->chunk_cols);
-    const size_t per_beam = (size_t)cfg->slots_per_beam *
-                                ((size_t)cfg->n_rows * (size_t)cfg->chunk_cols + (size_t)cfg->n_rows * fb_pitch +
-                                 (size_t)n_dm * (size_t)(H + cfg->chunk_cols) * 4 +
-                                 (size_t)cfg->cand_capacity * sizeof(spd_candidate) + 256) +
-                            (size_t)n_dm * (sizeof(spd_msd_state) + sizeof(spd_row_stats)) + ws;
-    return per_beam * (size_t)cfg->n_beams;
-}
 
 static spd_status create_server(const spd_server_config* cfg, const spd_params* p, const spd_dedisp_plan* dd,
                                 spd_server** out)
@@ -420,6 +488,9 @@ static spd_status create_server(const spd_server_config* cfg, const spd_params* 
     if (cfg->chunk_cols < nmax) return fail(SPD_E_INVALID, "chunk_cols must be >= the widest boxcar");
     if (cfg->slots_per_beam < 1 || cfg->slots_per_beam > 8) return fail(SPD_E_INVALID, "slots_per_beam outside [1, 8]");
     if (cfg->cand_capacity < 1) return fail(SPD_E_INVALID, "cand_capacity must be >= 1");
+    if (cfg->n_streams < 0 || cfg->n_streams > kServeMaxStreams)
+        return fail(SPD_E_INVALID, "n_streams outside [0, %d]", kServeMaxStreams);
+    if (cfg->hbm_budget_bytes < 0) return fail(SPD_E_INVALID, "hbm_budget_bytes < 0");
     int32_t n_chan = 0, n_dm = 0, max_delay = 0;
     int plan_device = 0, device = 0;
     int64_t dd_halo = 0, fb_pitch = 0;
@@ -434,10 +505,12 @@ static spd_status create_server(const spd_server_config* cfg, const spd_params* 
         dd_halo = ((int64_t)max_delay + 3) & ~(int64_t)3;
         fb_pitch = (dd_halo + cfg->chunk_cols + 3) & ~(int64_t)3;
     }
-    const size_t need = dd ? dedisp_server_bytes(cfg, nmax - 1, n_dm, fb_pitch) : spd_server_device_bytes(cfg, p);
-    if (cfg->hbm_budget_bytes && need > (size_t)cfg->hbm_budget_bytes)
-        return fail(SPD_E_NOMEM, "configuration needs %zu device bytes > budget %lld", need,
-                    (long long)cfg->hbm_budget_bytes);
+    const int64_t det_rows = dd ? n_dm : cfg->n_rows;
+    const int esize = dd ? 4 : elem_size(cfg->dtype);
+    const ServeSizes z = serve_sizes(cfg, nmax - 1, det_rows, esize, dd_halo, fb_pitch, dd != nullptr);
+    if (z.buffers < 1)
+        return fail(SPD_E_NOMEM, "budget %lld bytes < %zu for the beams' state and one chunk buffer",
+                    (long long)cfg->hbm_budget_bytes, z.per_beam * (size_t)cfg->n_beams + z.per_buf);
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess) return device_status(e, "hipGetDevice");
     if (dd && plan_device != device)
@@ -448,58 +521,55 @@ static spd_status create_server(const spd_server_config* cfg, const spd_params* 
     S->params = *p;
     S->params.widths = S->widths.data();
     S->in_esize = elem_size(cfg->dtype);
-    S->esize = dd ? 4 : S->in_esize;
+    S->esize = esize;
     S->halo = nmax - 1;
-    S->det_rows = dd ? n_dm : cfg->n_rows;
+    S->det_rows = det_rows;
     S->dd = dd;
     S->dd_delay = max_delay;
     S->dd_halo = dd_halo;
     S->fb_pitch = fb_pitch;
     S->device = device;
+    S->n_streams = cfg->n_streams ? cfg->n_streams : 2;
+    S->device_bytes = z.total;
     S->beams.resize(cfg->n_beams);
-    const int slots = cfg->slots_per_beam;
-    const int64_t D = S->det_rows;
-    const size_t ws_bytes = serve_ws_bytes(D, S->halo, cfg->chunk_cols);
+    S->pool.resize((size_t)z.buffers);
+    const int64_t D = det_rows, H = S->halo;
+    const size_t ws_bytes = serve_ws_bytes(D, H, cfg->chunk_cols);
+    for (int q = 0; q < S->n_streams && e == hipSuccess; ++q) {
+        e = hipStreamCreateWithFlags(&S->compute[q], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->copy[q], hipStreamNonBlocking);
+    }
+    for (auto& pb : S->pool) {
+        if (e != hipSuccess) break;
+        e = hipMalloc(&pb.plane, (size_t)D * (size_t)(H + cfg->chunk_cols) * esize);
+        if (e == hipSuccess) e = hipMalloc(&pb.stage, (size_t)cfg->n_rows * (size_t)cfg->chunk_cols * S->in_esize);
+        if (e == hipSuccess && dd) e = hipMalloc(&pb.fb, (size_t)cfg->n_rows * (size_t)fb_pitch);
+        if (e == hipSuccess) e = hipMalloc((void**)&pb.d_cand, sizeof(spd_candidate) * cfg->cand_capacity);
+        if (e == hipSuccess) e = hipMalloc((void**)&pb.d_count, sizeof(int64_t));
+        if (e == hipSuccess) e = hipHostMalloc((void**)&pb.h_cand, sizeof(spd_candidate) * cfg->cand_capacity, 0);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&pb.h_count, sizeof(int64_t), 0);
+        for (int g = 0; g < kServeRowGroups && e == hipSuccess; ++g)
+            e = hipEventCreateWithFlags(&pb.h2d[g], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&pb.done, hipEventDisableTiming);
+    }
     for (auto& b : S->beams) {
-        b.buf.assign(slots, nullptr);
-        b.stage.assign(slots, nullptr);
-        b.fb.assign(dd ? slots : 0, nullptr);
-        b.d_cand.assign(slots, nullptr);
-        b.d_count.assign(slots, nullptr);
-        b.h_cand.assign(slots, nullptr);
-        b.h_count.assign(slots, nullptr);
-        b.h2d_done.assign((size_t)slots * kServeRowGroups, nullptr);
-        b.free_ev.assign(slots, nullptr);
-        b.done_ev.assign(slots, nullptr);
-        const size_t bytes = (size_t)D * (size_t)(S->halo + cfg->chunk_cols) * S->esize;
-        for (int s = 0; s < slots && e == hipSuccess; ++s) {
-            e = hipMalloc(&b.buf[s], bytes);
-            if (e == hipSuccess) e = hipMalloc(&b.stage[s], (size_t)cfg->n_rows * (size_t)cfg->chunk_cols * S->in_esize);
-            if (e == hipSuccess && dd) e = hipMalloc(&b.fb[s], (size_t)cfg->n_rows * (size_t)fb_pitch);
-            if (e == hipSuccess) e = hipMalloc((void**)&b.d_cand[s], sizeof(spd_candidate) * cfg->cand_capacity);
-            if (e == hipSuccess) e = hipMalloc((void**)&b.d_count[s], sizeof(int64_t));
-            if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_cand[s], sizeof(spd_candidate) * cfg->cand_capacity, 0);
-            if (e == hipSuccess) e = hipHostMalloc((void**)&b.h_count[s], sizeof(int64_t), 0);
-            for (int g = 0; g < kServeRowGroups && e == hipSuccess; ++g)
-                e = hipEventCreateWithFlags(&b.h2d_done[(size_t)s * kServeRowGroups + g], hipEventDisableTiming);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&b.free_ev[s], hipEventDisableTiming);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&b.done_ev[s], hipEventDisableTiming);
-        }
+        if (e != hipSuccess) break;
+        if (H > 0) e = hipMalloc(&b.halo, (size_t)D * (size_t)H * esize);
+        if (e == hipSuccess && dd && dd_halo > 0) e = hipMalloc(&b.fb_halo, (size_t)cfg->n_rows * (size_t)dd_halo);
         if (e == hipSuccess) e = hipMalloc((void**)&b.state, sizeof(spd_msd_state) * D);
         if (e == hipSuccess) e = hipMemset(b.state, 0, sizeof(spd_msd_state) * D);
         if (e == hipSuccess) e = hipMalloc((void**)&b.stats, sizeof(spd_row_stats) * D);
         b.ws_bytes = ws_bytes;
         if (e == hipSuccess) e = hipMalloc(&b.ws, ws_bytes);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&b.copy, hipStreamNonBlocking);
-        if (e != hipSuccess) break;
-        for (int s = 0; s < slots && e == hipSuccess; ++s) e = hipEventRecord(b.free_ev[s], b.stream);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b.ready, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(b.ready, S->compute[0]);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         free_server(S);
         return device_status(e, "server allocation");
     }
+    for (int i = (int)S->pool.size() - 1; i >= 0; --i) S->free_bufs.push_back(i);
     S->worker = std::thread(worker_loop, S);
     *out = S;
     return SPD_OK;
@@ -539,7 +609,7 @@ spd_status spd_server_submit(spd_server* S, int32_t beam, int64_t seq, const voi
     r.seq = seq;
     r.host = host_chunk;
     r.submit_s = arrival_s > 0.0 ? arrival_s : now_s();
-    b.pending.push_back(r);
+    S->pending.push_back(r);
     ++b.next_submit;
     ++S->n_submitted;
     S->cv_work.notify_one();
@@ -575,6 +645,16 @@ spd_status spd_server_counters(spd_server* S, int64_t* submitted, int64_t* admit
     if (submitted) *submitted = S->n_submitted;
     if (admitted) *admitted = S->n_admitted;
     if (completed) *completed = S->n_completed;
+    return SPD_OK;
+}
+
+spd_status spd_server_info(spd_server* S, int32_t* pool_buffers, int32_t* n_streams, int64_t* device_bytes)
+{
+    clear_error();
+    if (!S) return fail(SPD_E_INVALID, "server is NULL");
+    if (pool_buffers) *pool_buffers = (int32_t)S->pool.size();
+    if (n_streams) *n_streams = S->n_streams;
+    if (device_bytes) *device_bytes = (int64_t)S->device_bytes;
     return SPD_OK;
 }
 

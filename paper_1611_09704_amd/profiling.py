@@ -347,6 +347,83 @@ def write_valu_summary(workload, out, dirs):
     print("wrote", path)
 
 
+def _busy(intervals):
+    """Total length of the union of [start, end) intervals, and the length
+    covered by at least two of them."""
+    ev = []
+    for a, b in intervals:
+        ev.append((a, 1))
+        ev.append((b, -1))
+    ev.sort()
+    union = two = 0
+    depth, last = 0, None
+    for t, d in ev:
+        if last is not None:
+            if depth >= 1:
+                union += t - last
+            if depth >= 2:
+                two += t - last
+        depth += d
+        last = t
+    return union, two
+
+
+def overlap_summary(args):
+    """Concurrency of a serving run from a rocprofv3 kernel and memory-copy
+    trace: the hardware queues used, how long kernels and host-to-device
+    copies were in flight, and how much of that time two or more of them ran
+    at once (chunks of different beams overlapping on the device)."""
+    kern = []
+    for f in _csvs(args.trace, "kernel_trace.csv"):
+        for row in csv.DictReader(open(f)):
+            kern.append((_short(row["Kernel_Name"]), int(row["Start_Timestamp"]), int(row["End_Timestamp"]),
+                         row.get("Queue_Id", ""), row.get("Stream_Id", "")))
+    copies = []
+    for f in _csvs(args.trace, "memory_copy_trace.csv"):
+        for row in csv.DictReader(open(f)):
+            copies.append((row.get("Direction", row.get("Operation", "")), int(row["Start_Timestamp"]),
+                           int(row["End_Timestamp"])))
+    lines = ["# %s\n" % args.title, "command: `%s`\n" % args.cmd]
+    if not kern:
+        lines.append("no kernel trace found")
+    else:
+        t0 = min(k[1] for k in kern + [(0, c[1], c[2]) for c in copies])
+        t1 = max(k[2] for k in kern + [(0, c[1], c[2]) for c in copies])
+        ku, k2 = _busy([(k[1], k[2]) for k in kern])
+        lines.append("| quantity | value |")
+        lines.append("|---|---|")
+        lines.append("| traced span | %.1f ms |" % ((t1 - t0) / 1e6))
+        lines.append("| kernel dispatches | %d |" % len(kern))
+        lines.append("| hardware queues used by kernels | %d (%s) |" % (
+            len({k[3] for k in kern}), ", ".join(sorted({k[3] for k in kern}))))
+        lines.append("| HIP streams used by kernels | %d |" % len({k[4] for k in kern}))
+        lines.append("| time with a kernel running | %.1f ms |" % (ku / 1e6))
+        lines.append("| time with two or more kernels running | %.1f ms (%.0f%% of the kernel time) |" % (
+            k2 / 1e6, 100.0 * k2 / max(ku, 1)))
+        h2d = [(c[1], c[2]) for c in copies if "HOST_TO_DEVICE" in c[0].upper() or "H2D" in c[0].upper()]
+        if h2d:
+            cu, c2 = _busy(h2d)
+            both = _busy([(a, b) for a, b in h2d] + [(k[1], k[2]) for k in kern])
+            lines.append("| host-to-device copies | %d, in flight %.1f ms, two or more at once %.1f ms |" % (
+                len(h2d), cu / 1e6, c2 / 1e6))
+            lines.append("| time with a copy or a kernel in flight | %.1f ms; copies and kernels at once %.1f ms |" % (
+                both[0] / 1e6, (cu + ku - both[0]) / 1e6))
+        lines.append("")
+        lines.append("| kernel | dispatches | total ms |")
+        lines.append("|---|---|---|")
+        tot = defaultdict(lambda: [0, 0.0])
+        for k in kern:
+            tot[k[0]][0] += 1
+            tot[k[0]][1] += (k[2] - k[1]) / 1e6
+        for name, (n, ms) in sorted(tot.items(), key=lambda kv: -kv[1][1]):
+            lines.append("| %s | %d | %.3f |" % (name, n, ms))
+    lines.append("")
+    path = os.path.join(args.out, args.name + ".md")
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines))
+    print("wrote", path)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -374,8 +451,14 @@ def main(argv=None):
     c.add_argument("--title", required=True)
     c.add_argument("--workload", choices=sorted(WORKLOADS),
                    help="also write the boxcar kernel's VALU per evaluation to valu_counters.json")
+    o = sub.add_parser("overlap")
+    o.add_argument("--trace", required=True)
+    o.add_argument("--cmd", default="")
+    o.add_argument("--out", default=os.path.join(ROOT, "profiles"))
+    o.add_argument("--name", required=True)
+    o.add_argument("--title", required=True)
     a = ap.parse_args(argv)
-    {"run": run, "summarize": summarize, "counters": counter_summary}[a.cmd](a)
+    {"run": run, "summarize": summarize, "counters": counter_summary, "overlap": overlap_summary}[a.cmd](a)
 
 
 if __name__ == "__main__":

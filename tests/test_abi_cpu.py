@@ -233,18 +233,43 @@ def test_server_validation(lib):
 
     def cfg(**kw):
         c = dict(n_beams=2, dtype=B.SPD_F16, n_rows=8, chunk_cols=4096, cand_capacity=100, slots_per_beam=2,
-                 reserved0=0, hbm_budget_bytes=0)
+                 n_streams=0, hbm_budget_bytes=0)
         c.update(kw)
         return B.SpdServerConfig(**c)
 
     for c, code, msg in [(cfg(n_beams=0), 1, "n_beams"), (cfg(dtype=B.SPD_U8), 2, "F32 or F16"),
                          (cfg(chunk_cols=8), 1, "chunk_cols"), (cfg(slots_per_beam=0), 1, "slots_per_beam"),
-                         (cfg(cand_capacity=0), 1, "cand_capacity"), (cfg(hbm_budget_bytes=1000), 3, "budget")]:
+                         (cfg(cand_capacity=0), 1, "cand_capacity"), (cfg(hbm_budget_bytes=1000), 3, "budget"),
+                         (cfg(n_streams=9), 1, "n_streams"), (cfg(hbm_budget_bytes=-1), 1, "budget")]:
         assert lib.spd_server_create(ctypes.byref(c), ctypes.byref(p.c), ctypes.byref(out)) == code
         assert out.value is None and msg in _err(lib)
     pp = B.Params([1, 2], 5.0, scope="plane")
     assert lib.spd_server_create(ctypes.byref(cfg()), ctypes.byref(pp.c), ctypes.byref(out)) == 2
     need = lib.spd_server_device_bytes(ctypes.byref(cfg()), ctypes.byref(p.c))
     assert need > 2 * 2 * 8 * (4096 + 15) * 2
+
+
+def test_server_pool_sizing(lib):
+    """The shared pool of chunk buffers follows the device-memory budget: the
+    beams' own state first, then as many buffers as fit, at most
+    slots_per_beam per beam, and none (an error) when not even one fits."""
+    p = B.Params(list(range(1, 17)), 7.0)
+
+    def need(**kw):
+        c = dict(n_beams=4, dtype=B.SPD_F16, n_rows=8, chunk_cols=4096, cand_capacity=100, slots_per_beam=2,
+                 n_streams=0, hbm_budget_bytes=0)
+        c.update(kw)
+        return lib.spd_server_device_bytes(ctypes.byref(B.SpdServerConfig(**c)), ctypes.byref(p.c))
+
+    all2, all1 = need(), need(slots_per_beam=1)
+    per_buf = (all2 - all1) // 4
+    beams = all1 - 4 * per_buf
+    # one buffer: the chunk with its halo (FP16), the staged chunk, 100 candidates and a count
+    assert per_buf == 8 * (15 + 4096) * 2 + 8 * 4096 * 2 + 100 * 24 + 8
+    assert beams > 4 * 8 * 15 * 2                               # halos, statistics, workspaces
+    for k in range(1, 9):
+        assert need(hbm_budget_bytes=beams + k * per_buf + per_buf // 3) == beams + k * per_buf
+    assert need(hbm_budget_bytes=beams + 100 * per_buf) == all2     # never more than slots_per_beam each
+    assert need(hbm_budget_bytes=beams + per_buf - 1) == 0 and "budget" in _err(lib)
     assert lib.spd_server_submit(None, 0, 0, FAKE, 0.0) == 1
     lib.spd_server_destroy(None)

@@ -110,6 +110,49 @@ def test_server_same_result_alone_and_in_a_mix():
         assert ka == km                      # bitwise: a beam's work never depends on the others
 
 
+@pytest.mark.parametrize("n_streams", [1, 2, 4])
+def test_server_budget_pool_matches_oracle_and_unbudgeted(n_streams):
+    """A device-memory budget that holds the beams' state and only 3 chunk
+    buffers for 6 beams: chunks wait for a buffer, are admitted as buffers
+    come back, and every chunk's candidates equal, bit for bit, those of a
+    server with a buffer for every chunk (and pass the streaming oracle)."""
+    R, Lc, K, nb = 5, 4096, 3, 6
+    W = list(range(1, 49))
+    p = B.Params(W, 5.5, "row", "auto", 1.0)
+    streams = _streams(nb, K, R, Lc, 48, torch.float16, seed=303)
+    free = B.Server(nb, R, Lc, p, cand_capacity=4096, n_streams=n_streams)
+    full = free.info()
+    assert full["pool_buffers"] == nb * 2 and full["n_streams"] == n_streams
+    one = B.server_device_bytes(nb, R, Lc, p, cand_capacity=4096, slots_per_beam=1)
+    per_buf = (full["device_bytes"] - one) // nb
+    budget = full["device_bytes"] - (2 * nb - 3) * per_buf + per_buf // 2
+    srv = B.Server(nb, R, Lc, p, cand_capacity=4096, hbm_budget_bytes=budget, n_streams=n_streams)
+    info = srv.info()
+    assert info["pool_buffers"] == 3 and info["device_bytes"] <= budget
+    print("case: budget pool of 3 buffers for %d beams, %d streams" % (nb, n_streams), flush=True)
+    out = {}
+    for name, s in (("free", free), ("budget", srv)):
+        for k in range(K):
+            for b in range(nb):
+                s.submit(b, k, streams[b][0][k])
+        res = _drain(s, nb * K)
+        cnt = s.counters()
+        s.close()
+        assert cnt == {"submitted": nb * K, "admitted": nb * K, "completed": nb * K}
+        for b in range(nb):
+            assert [r["seq"] for r, _ in res if r["beam"] == b] == list(range(K))
+        out[name] = {(r["beam"], r["seq"]): sorted((int(x["row"]), int(x["t"]), float(x["snr"]), int(x["width"]))
+                                                   for x in c) for r, c in res}
+    assert out["free"] == out["budget"]
+    for b in range(nb):
+        orc = _oracle_stream(streams[b][0], W, 5.5, "auto")
+        for k in range(K):
+            oc, snr, toff, wr = orc[k]
+            c = np.array([(row, 0, t, sn, 0) for row, t, sn, w in out["budget"][(b, k)]], dtype=B.CANDIDATE_DTYPE)
+            c["width"] = [w for _, _, _, w in out["budget"][(b, k)]]
+            C.check_candidates(c, oc, 5.5, lambda row, t: snr[row, t - toff], wr)
+
+
 def test_server_backpressure_and_order():
     R, Lc, K = 4, 2048, 12
     W = [1, 2, 4, 8]
