@@ -376,14 +376,20 @@ def overlap_summary(args):
     kern = []
     for f in _csvs(args.trace, "kernel_trace.csv"):
         for row in csv.DictReader(open(f)):
-            kern.append((_short(row["Kernel_Name"]), int(row["Start_Timestamp"]), int(row["End_Timestamp"]),
+            name = _short(row["Kernel_Name"])
+            if not any(k in name for k in ("boxcar", "msd", "select", "fill_i64", "dedisp")):
+                continue                  # the path's kernels only (not the workload generator's)
+            kern.append((name, int(row["Start_Timestamp"]), int(row["End_Timestamp"]),
                          row.get("Queue_Id", ""), row.get("Stream_Id", "")))
     copies = []
-    for f in _csvs(args.trace, "memory_copy_trace.csv"):
-        for row in csv.DictReader(open(f)):
-            copies.append((row.get("Direction", row.get("Operation", "")), int(row["Start_Timestamp"]),
-                           int(row["End_Timestamp"])))
-    lines = ["# %s\n" % args.title, "command: `%s`\n" % args.cmd]
+    if kern:
+        lo, hi = min(k[1] for k in kern), max(k[2] for k in kern)
+        for f in _csvs(args.trace, "memory_copy_trace.csv"):
+            for row in csv.DictReader(open(f)):
+                a, b = int(row["Start_Timestamp"]), int(row["End_Timestamp"])
+                if b >= lo and a <= hi:   # copies while the path ran
+                    copies.append((row.get("Direction", row.get("Operation", "")), a, b))
+    lines = ["# %s\n" % args.title, "command: `%s`\n" % args.command]
     if not kern:
         lines.append("no kernel trace found")
     else:
@@ -453,7 +459,7 @@ def main(argv=None):
                    help="also write the boxcar kernel's VALU per evaluation to valu_counters.json")
     o = sub.add_parser("overlap")
     o.add_argument("--trace", required=True)
-    o.add_argument("--cmd", default="")
+    o.add_argument("--command", default="")
     o.add_argument("--out", default=os.path.join(ROOT, "profiles"))
     o.add_argument("--name", required=True)
     o.add_argument("--title", required=True)
