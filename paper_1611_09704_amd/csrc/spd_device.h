@@ -238,7 +238,118 @@ __device__ float pilot_shift(const Loader<DT>& ld, int64_t ncols, float* scratch
 struct MsdScratch {
     Msd part[16];
     float shift[16];
+    unsigned long long isum[4][16];        // U8: per-wave integer sums
 };
+
+// ---------------------------------------------------------------------------
+// Sec. 2.1 on U8 planes: exact integer sums in the stored domain
+// ---------------------------------------------------------------------------
+//
+// x = s*(q - z) is affine in the stored byte q, so a block's count, sum and
+// sum of squared deviations follow exactly from the integer sums Sum q and
+// Sum q^2: T_x = s*(Sum q - n*z) and S_x = s^2*(n*Sum q^2 - (Sum q)^2)/n.
+// Four bytes take one v_sad_u8 (their sum) and one v_dot4_u32_u8 (their
+// squares' sum); the widest boxcar's values y are integer window sums (exact
+// prefix differences), their squares accumulated in 64 bits.
+
+__device__ __forceinline__ void u8_word(uint32_t w, uint32_t& s1, uint32_t& s2)
+{
+    s1 = __builtin_amdgcn_sad_u8(w, 0u, s1);
+    s2 = __builtin_amdgcn_udot4(w, w, s2, false);
+}
+
+// Block sums of up to four per-thread 64-bit counters (in a fixed order, so
+// every launch gives the same bits); the result is valid in thread 0.
+template <int K>
+__device__ __forceinline__ void block_isum(unsigned long long (&v)[K], MsdScratch& sh)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh.isum[k][wave] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            unsigned long long t = 0;
+            for (int w = 0; w < nw; ++w) t += sh.isum[k][w];
+            v[k] = t;
+        }
+}
+
+// (n, T, S) in the x domain from integer sums of n stored values v, where
+// x = s*(v - c*z) (c = 1 for samples, Nmax for widest-boxcar values).
+__device__ __forceinline__ void u8_partial(double n, unsigned long long sum, unsigned long long sumsq, double s,
+                                           double cz, double* out3)
+{
+    if (n == 0.0) {
+        out3[0] = out3[1] = out3[2] = 0.0;
+        return;
+    }
+    const unsigned long long nn = (unsigned long long)n;
+    const unsigned __int128 num = (unsigned __int128)nn * sumsq - (unsigned __int128)sum * sum;
+    out3[0] = n;
+    out3[1] = s * ((double)sum - n * cz);
+    out3[2] = s * s * ((double)num / n);
+}
+
+// Raw-sample partials of one (row, column block) of a U8 plane: columns
+// [lo, hi), lo = max(block start, new_col_begin).
+__device__ void msd_block_x_u8(const PlaneArg& pl, bool vec, int64_t r, int64_t b, int64_t ncb, int64_t bc,
+                               double* out6, MsdScratch& sh)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const uint8_t* row = (const uint8_t*)pl.data + r * pl.stride;
+    const int64_t lo = max(b * bc, ncb), hi = min((b + 1) * bc, pl.n_cols);
+    uint32_t s1 = 0, s2 = 0;                            // <= 256 samples per thread: no overflow
+    if (lo < hi) {
+        if (vec) {                                      // rows start on 4-byte boundaries
+            const int64_t a = min(hi, (lo + 3) & ~(int64_t)3), e = max(a, hi & ~(int64_t)3);
+            if (tid < a - lo) { const uint32_t q = row[lo + tid]; s1 += q; s2 += q * q; }
+            if (tid < hi - e) { const uint32_t q = row[e + tid]; s1 += q; s2 += q * q; }
+            const uint32_t* w = (const uint32_t*)(row + a);
+            const int64_t nw = (e - a) / 4;
+            int64_t i = tid;
+            for (; i + 3 * nt < nw; i += 4 * nt) {
+                const uint32_t w0 = w[i], w1 = w[i + nt], w2 = w[i + 2 * nt], w3 = w[i + 3 * nt];
+                u8_word(w0, s1, s2); u8_word(w1, s1, s2); u8_word(w2, s1, s2); u8_word(w3, s1, s2);
+            }
+            for (; i < nw; i += nt) u8_word(w[i], s1, s2);
+        } else {
+            for (int64_t c = lo + tid; c < hi; c += nt) { const uint32_t q = row[c]; s1 += q; s2 += q * q; }
+        }
+    }
+    unsigned long long v[2] = {s1, s2};
+    block_isum<2>(v, sh);
+    if (tid == 0) {
+        u8_partial((double)max(hi - lo, (int64_t)0), v[0], v[1], (double)pl.scale[r], (double)pl.zero[r], out6);
+        out6[3] = 0.0; out6[4] = 0.0; out6[5] = 0.0;
+    }
+}
+
+// Inclusive prefix sum of 32-bit integers across the 64 lanes of a wave
+// (DPP row shifts and row broadcasts, as wave_inclusive_scan).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int dpp_mov_i(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xf, true);
+}
+
+__device__ __forceinline__ int wave_inclusive_scan_i(int x)
+{
+    x += dpp_mov_i<0x111, 0xf>(x);
+    x += dpp_mov_i<0x112, 0xf>(x);
+    x += dpp_mov_i<0x114, 0xf>(x);
+    x += dpp_mov_i<0x118, 0xf>(x);
+    x += dpp_mov_i<0x142, 0xa>(x);
+    x += dpp_mov_i<0x143, 0xc>(x);
+    return x;
+}
 
 // Raw-sample partials of one (row, column block): columns [lo, hi) with
 // lo = max(block start, new_col_begin).  Writes {n, T, S, 0, 0, 0} to out6.
@@ -246,6 +357,10 @@ template <int DT>
 __device__ void msd_block_x(const PlaneArg& pl, bool vec, int64_t r, int64_t b, int64_t ncb, int64_t bc,
                             double* out6, MsdScratch& sh)
 {
+    if constexpr (DT == SPD_U8) {
+        msd_block_x_u8(pl, vec, r, b, ncb, bc, out6, sh);
+        return;
+    }
     const int tid = threadIdx.x, nt = blockDim.x;
     Loader<DT> ld(pl, r);
     const float K = pilot_shift<DT>(ld, pl.n_cols, sh.shift);
@@ -323,10 +438,124 @@ __host__ __device__ inline int msd_xy_npw(int nmax) { return (kMsdSubTile + nmax
 // K), forms the exclusive prefix E in its own LDS region (`lds`, npw floats per
 // wave) with a wave scan, and takes y(t) = E[t+nmax] - E[t].  The same loads
 // feed the raw statistics.
+// msd_block_xy on a U8 plane, in integers: each wave's exclusive prefix E of
+// the stored bytes (int32, exact) over a sub-tile and its nmax-1 halo, the
+// raw sums from the same words, and y(t) = E[t+nmax] - E[t].
+__device__ void msd_block_xy_u8(const PlaneArg& pl, bool vec, int64_t r, int64_t b, int64_t ncb, int64_t bc,
+                                int32_t nmax, int64_t nout, int32_t npw, float* lds, double* out6, MsdScratch& sh)
+{
+    constexpr int TSW = kMsdSubTile;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+    int* E = (int*)lds + (size_t)wave * npw;
+    const uint8_t* row = (const uint8_t*)pl.data + r * pl.stride;
+    const int64_t ncols = pl.n_cols;
+    const int64_t c0 = b * bc, c1 = min(c0 + bc, ncols);
+    const int64_t xlo = max(c0, ncb), yhi = min(c1, nout);
+    const int nrow = npw / 256;
+    uint32_t sx1 = 0, sx2 = 0;                          // <= 16 samples per sub-tile, <= 64 sub-tiles per lane
+    unsigned long long sy1 = 0;
+    // a lane's y^2 sum: at most 512 values (<= 255 * 4096 each) per lane and
+    // block, below 2^53, so the FP64 sum is the exact integer
+    double sy2 = 0.0;
+    // four bytes from column c (a multiple of 4), zero past the end of the row
+    auto word = [&](int64_t c) -> uint32_t {
+        if (vec && c + 3 < ncols) return *(const uint32_t*)(row + c);
+        uint32_t w = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) w |= (c + k < ncols ? (uint32_t)row[c + k] : 0u) << (8 * k);
+        return w;
+    };
+    for (int64_t u0 = c0 + (int64_t)wave * TSW; u0 < c1; u0 += (int64_t)nw * TSW) {
+        const int64_t u1 = min(u0 + TSW, c1);
+        int carry = 0;
+        uint32_t wr[4];                                 // the lane's raw words of rows 0..3
+        // one row of 256 bytes: its share of the prefix E
+        auto rowscan = [&](int m, uint32_t w) {
+            const int l0 = w & 255, l1 = l0 + ((w >> 8) & 255), l2 = l1 + ((w >> 16) & 255), l3 = l2 + (w >> 24);
+            const int inc = wave_inclusive_scan_i(l3);
+            const int ex = inc - l3 + carry;
+            carry += __builtin_amdgcn_readlane(inc, 63);
+            *(int4*)(E + 256 * m + 4 * lane) = make_int4(ex, ex + l0, ex + l1, ex + l2);
+        };
+        if (vec && u0 + 256 * nrow <= ncols) {
+            // the sub-tile and its halo inside the row: four word loads in flight at once
+            for (int m0 = 0; m0 < nrow; m0 += 4) {
+                uint32_t w[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) w[j] = *(const uint32_t*)(row + u0 + 256 * min(m0 + j, nrow - 1) + 4 * lane);
+                if (m0 == 0) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) wr[j] = w[j];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (m0 + j < nrow) rowscan(m0 + j, w[j]);
+            }
+        } else {
+            for (int m = 0; m < nrow; ++m) {
+                const uint32_t w = word(u0 + 256 * m + 4 * lane);
+                if (m < 4) wr[m] = w;
+                rowscan(m, w);
+            }
+        }
+        if (u0 >= xlo && u0 + TSW <= c1) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) u8_word(wr[m], sx1, sx2);
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t c = u0 + 256 * m + 4 * lane + j;
+                    if (c >= xlo && c < u1) {
+                        const uint32_t q = (wr[m] >> (8 * j)) & 255u;
+                        sx1 += q;
+                        sx2 += q * q;
+                    }
+                }
+        }
+        wave_sync();
+        // with nmax a multiple of 4 the shifted reads are aligned 16-byte reads
+        const bool y_whole = u0 + TSW <= yhi;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int p = 256 * m + 4 * lane;
+            const int4 e = *(const int4*)(E + p);
+            int4 f;
+            if ((nmax & 3) == 0) f = *(const int4*)(E + p + nmax);
+            else f = make_int4(E[p + nmax], E[p + 1 + nmax], E[p + 2 + nmax], E[p + 3 + nmax]);
+            const uint32_t y[4] = {(uint32_t)(f.x - e.x), (uint32_t)(f.y - e.y), (uint32_t)(f.z - e.z),
+                                   (uint32_t)(f.w - e.w)};
+            uint32_t t1 = 0;                            // < 2^32: four values of at most 255 * 4096
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (y_whole || u0 + p + j < yhi) {
+                    t1 += y[j];
+                    const double yd = (double)y[j];
+                    sy2 = fma(yd, yd, sy2);
+                }
+            }
+            sy1 += t1;
+        }
+        wave_sync();
+    }
+    unsigned long long v[4] = {sx1, sx2, sy1, (unsigned long long)sy2};
+    block_isum<4>(v, sh);
+    if (tid == 0) {
+        const double sc = (double)pl.scale[r], z = (double)pl.zero[r];
+        u8_partial((double)max(c1 - xlo, (int64_t)0), v[0], v[1], sc, z, out6);
+        u8_partial((double)max(yhi - c0, (int64_t)0), v[2], v[3], sc, (double)nmax * z, out6 + 3);
+    }
+}
+
 template <int DT>
 __device__ void msd_block_xy(const PlaneArg& pl, bool vec, int64_t r, int64_t b, int64_t ncb, int64_t bc,
                              int32_t nmax, int64_t nout, int32_t npw, float* lds, double* out6, MsdScratch& sh)
 {
+    if constexpr (DT == SPD_U8) {
+        msd_block_xy_u8(pl, vec, r, b, ncb, bc, nmax, nout, npw, lds, out6, sh);
+        return;
+    }
     constexpr int TSW = kMsdSubTile;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     float* E = lds + (size_t)wave * npw;
