@@ -6,11 +6,10 @@
  * The path runs over a plane of de-dispersed time series, one row per DM
  * trial, time contiguous (Sec. 1, Sec. 2.3):
  *   1. msd_compute       mean and standard deviation per unit (Sec. 2.1:
- *                        inside a block, FP32 mini-batches of 16 samples
- *                        merged with Eq. MSD04 and Eq. MSD03 at the edges;
- *                        Eq. MSD04 in FP64 across blocks), plus sigma of the
- *                        widest boxcar when the linear approximation of
- *                        Sec. 2.2 Eq. (sd03) is in use;
+ *                        partial sums inside a block, Eq. MSD04 in FP64
+ *                        across blocks), plus sigma of the widest boxcar
+ *                        when the linear approximation of Sec. 2.2
+ *                        Eq. (sd03) is in use;
  *   2. boxcar_snr        boxcars of every listed width at every sample, their
  *                        SNR with sigma_N from Eq. (sd02) or Eq. (sd03), and
  *                        the highest SNR with its width (Sec. 2.3,
@@ -152,9 +151,14 @@ size_t spd_workspace_bytes(const spd_plane* x, const spd_params* p);
 /*
  * msd_compute -- Sec. 2.1: per-unit mean and standard deviation.
  *   A unit is a row (SPD_SCOPE_ROW) or the whole plane (SPD_SCOPE_PLANE).
- *   Each block of a row is reduced in FP32 with the streaming update
- *   (Eq. MSD03) and the pairwise merge (Eq. MSD04) inside the block; the
- *   block partials are then merged across blocks in FP64 (Eq. MSD04).
+ *   Each block of a row (16384 to 65536 columns) gives a partial (n, T, S):
+ *   raw statistics only: FP32 mini-batches of 16 samples merged with the
+ *   streaming update (Eq. MSD03) and the pairwise merge (Eq. MSD04);
+ *   with sigma_Nmax: sums of samples shifted by a sample near the row's
+ *   mean, in FP32 over runs of 8 or 16 and in FP64 across runs, and the
+ *   widest boxcar advanced one start at a time from a running FP64 value;
+ *   U8 planes: exact integer sums of the stored bytes.  The block partials
+ *   are merged across blocks in FP64 (Eq. MSD04).
  *   Raw-sample statistics use columns [new_col_begin, n_cols).  When
  *   sigma_mode != SPD_SIGMA_SQRTN, the statistics of B_Nmax(t) over every
  *   valid start t in [0, n_cols-Nmax] are gathered in the same pass.

@@ -48,6 +48,10 @@ SCOPES = {"row": 0, "plane": 1}
 SIGMA_MODES = {"sqrtn": 0, "linear": 1, "auto": 2, "linear_literal": 3}
 FLAG_ZERO_VAR = 1
 FLAG_LINEAR = 2
+# sigma_w counts as positive above SW_FLOOR * sqrt(w) * sigma: the anchored form of
+# Eq. (sd03) reaches zero at w = Nmax when sigma_Nmax = 0, where its rounding
+# residual can take either sign.
+SW_FLOOR = 1e-9
 
 
 def build(force: bool = True) -> str:
@@ -305,7 +309,7 @@ def snr_at(row, t, width, unit_stats):
     ``stats`` array returned by ``stream_step``."""
     mean, sigma, _, coef, flags = (float(v) for v in unit_stats)
     sw = np.sqrt(width) * sigma + (width - 1) * coef
-    if int(flags) & FLAG_ZERO_VAR or not sw > 0.0:
+    if int(flags) & FLAG_ZERO_VAR or not sw > SW_FLOOR * np.sqrt(width) * sigma:
         return 0.0
     b = float(np.sum(np.asarray(row[t:t + width], dtype=np.float64)))
     return (b - width * mean) / sw

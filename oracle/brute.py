@@ -10,6 +10,8 @@ from __future__ import annotations
 
 import math
 
+SW_FLOOR = 1e-9   # sigma_w counts as positive above SW_FLOOR * sqrt(w) * sigma
+
 
 def two_pass(values):
     """Population mean and the sum of squared deviations, two passes."""
@@ -60,7 +62,7 @@ def detect(plane, widths, threshold, scope="row", sigma_mode="sqrtn", kappa=1.0)
         for t in range(len(row) - nmax + 1):
             vals = []
             for i, w in enumerate(widths):
-                if flags & 1 or sw[i] <= 0.0:
+                if flags & 1 or sw[i] <= SW_FLOOR * math.sqrt(w) * sigma:
                     vals.append(0.0)
                 else:
                     vals.append((sum(row[t:t + w]) - w * mu) / sw[i])

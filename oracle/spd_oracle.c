@@ -44,7 +44,11 @@
  *   - AUTO mode applies the anchored linear form to a unit iff
  *     rho = sigma_Nmax / (sqrt(Nmax)*sigma) > 1 + kappa.
  *   - A unit with sigma == 0 is flagged ZERO_VAR: every SNR is 0 and the width
- *     index is 0.  A width whose sigma_w is not positive contributes SNR 0.
+ *     index is 0.  A width whose sigma_w is not positive contributes SNR 0;
+ *     "positive" means above SW_FLOOR * sqrt(w) * sigma, since the anchored form
+ *     reaches zero at w = Nmax when sigma_Nmax = 0 (one valid start, or a row
+ *     whose Nmax-boxcar is constant) and its rounding residual there can take
+ *     either sign.
  *   - Threshold (Sec. 2.4): a sample is a candidate iff SNR >= f_T.
  */
 #include <math.h>
@@ -58,6 +62,7 @@
 enum { SCOPE_ROW = 0, SCOPE_PLANE = 1 };
 enum { SIG_SQRTN = 0, SIG_LINEAR = 1, SIG_AUTO = 2, SIG_LINEAR_LITERAL = 3 };
 enum { FLAG_ZERO_VAR = 1, FLAG_LINEAR = 2 };
+#define SW_FLOOR 1e-9
 
 /* Sec. 2.1 Eq. (MSD03): serial streaming update over x[0..n).
  * T_j = T_{j-1} + x_j ;  S_j = S_{j-1} + (j*x_j - T_j)^2 / (j*(j-1)).       */
@@ -157,7 +162,7 @@ static void detect_row(const double* row, int64_t n_out, const int32_t* W, const
         for (int i = 0; i < nW; ++i) {
             while (k < W[i]) { B += row[t + k]; ++k; }
             if (stride && t % stride[i] != 0) continue;
-            double s = sig_w[i] > 0.0 ? (B - (double)W[i] * mu) / sig_w[i] : 0.0;
+            double s = sig_w[i] > SW_FLOOR * sqrt((double)W[i]) * sigma ? (B - (double)W[i] * mu) / sig_w[i] : 0.0;
             if (s > best) { best = s; bi = i; }
         }
         snr[t] = best;

@@ -105,7 +105,9 @@ MsdLayout msd_layout(const spd_plane* x)
 {
     MsdLayout m;
     const int64_t total = x->n_rows * x->n_cols;
-    int64_t bc = 4096;
+    // at least 16384 columns per block, so each of its four waves walks at least
+    // 4096 (whole steps of the widest-boxcar pass); at most 16384 blocks
+    int64_t bc = 16384;
     while (bc < 65536 && (total + bc - 1) / bc > 16384) bc <<= 1;
     m.bc = bc;
     m.nblk = (x->n_cols + bc - 1) / bc;

@@ -82,10 +82,8 @@ __device__ __forceinline__ int64_t grab_items(int64_t* queue, int grab, int64_t*
 
 template <int DT, bool WITH_Y>
 __global__ __launch_bounds__(256) void batch_msd_kernel(const BeamDesc* beams, int n_beams, int64_t total,
-                                                        int64_t* queue, int grab, int32_t nmax, int32_t npw,
-                                                        double* part)
+                                                        int64_t* queue, int grab, int32_t nmax, double* part)
 {
-    extern __shared__ float lds[];
     __shared__ MsdScratch sh;
     __shared__ int64_t starts[kMaxBeams];
     __shared__ int64_t slot;
@@ -102,7 +100,7 @@ __global__ __launch_bounds__(256) void batch_msd_kernel(const BeamDesc* beams, i
             const int64_t r = local / d.nblk, blk = local % d.nblk;
             double* out6 = part + it * 6;
             if (WITH_Y)
-                msd_block_xy<DT>(d.pl, d.vec != 0, r, blk, 0, kMsdBlockCols, nmax, d.nout, npw, lds, out6, sh);
+                msd_block_xy<DT>(d.pl, d.vec != 0, r, blk, 0, kMsdBlockCols, nmax, d.nout, out6, sh);
             else
                 msd_block_x<DT>(d.pl, d.vec != 0, r, blk, 0, kMsdBlockCols, out6, sh);
         }
@@ -260,16 +258,12 @@ static hipError_t enqueue_msd(spd_batch_plan* P, hipStream_t s)
     const bool need_y = P->params.sigma_mode != SPD_SIGMA_SQRTN;
     const int nmax = P->widths.back();
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(P->msd_items, (int64_t)P->cus * 8));
-    if (need_y) {
-        const int npw = msd_xy_npw(nmax);
-        const int waves = msd_xy_waves(nmax);
-        hipLaunchKernelGGL((batch_msd_kernel<DT, true>), dim3(grid), dim3(64 * waves),
-                           (size_t)waves * npw * sizeof(float), s, P->d_beams[1], P->n_beams, P->msd_items,
-                           P->d_counters, 2, nmax, npw, P->d_part);
-    } else {
+    if (need_y)
+        hipLaunchKernelGGL((batch_msd_kernel<DT, true>), dim3(grid), dim3(256), 0, s, P->d_beams[1], P->n_beams,
+                           P->msd_items, P->d_counters, 2, nmax, P->d_part);
+    else
         hipLaunchKernelGGL((batch_msd_kernel<DT, false>), dim3(grid), dim3(256), 0, s, P->d_beams[1], P->n_beams,
-                           P->msd_items, P->d_counters, 2, nmax, 0, P->d_part);
-    }
+                           P->msd_items, P->d_counters, 2, nmax, P->d_part);
     return hipGetLastError();
 }
 

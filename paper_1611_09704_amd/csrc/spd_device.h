@@ -104,6 +104,15 @@ __device__ __forceinline__ float4 load4_shifted(const Loader<DT>& ld, int64_t c,
     return v;
 }
 
+// Eq. (sd02)/(sd03): a width contributes SNR 0 unless sigma_w is positive
+// beyond rounding, i.e. above 1e-9 * sqrt(w) * sigma.  The anchored linear form
+// reaches zero at w = Nmax when sigma_Nmax = 0 (one valid start, or a row whose
+// Nmax-boxcar is constant), and its rounding residual there has either sign.
+__device__ __forceinline__ bool sigma_w_positive(double sw, double w, double sigma)
+{
+    return sw > 1e-9 * sqrt(w) * sigma;
+}
+
 // ---------------------------------------------------------------------------
 // Sec. 2.1: streaming and pairwise mean / deviation in FP32 inside a block
 // ---------------------------------------------------------------------------
@@ -214,32 +223,50 @@ __device__ __forceinline__ Msd block_merge(Msd v, Msd* scratch)
     return acc;
 }
 
-// Shift applied before the FP32 reduction: the mean of the row's first (up to)
-// block-size samples, so shifted samples -- and the widest-boxcar series built
-// from them -- have a mean small against their spread.  Any constant gives the
-// same statistics in exact arithmetic; T is shifted back in FP64.
-template <int DT>
-__device__ float pilot_shift(const Loader<DT>& ld, int64_t ncols, float* scratch)
-{
-    const int tid = threadIdx.x;
-    const int64_t n = ncols < (int64_t)blockDim.x ? ncols : (int64_t)blockDim.x;
-    float v = tid < n ? ld.at(tid) : 0.f;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    __syncthreads();
-    if ((tid & 63) == 0) scratch[tid >> 6] = v;
-    __syncthreads();
-    float sum = 0.f;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += scratch[w];
-    return sum / (float)n;
-}
-
 // Shared-memory scratch of the MSD block functions.
 struct MsdScratch {
     Msd part[16];
     float shift[16];
-    unsigned long long isum[4][16];        // U8: per-wave integer sums
+    unsigned long long isum[4][16];        // U8: per-wave integer sums; the pilot's closest sample
+    double dsum[4][16];                    // per-wave FP64 sums
 };
+
+// Shift applied before the FP32 reduction: among the row's first (up to)
+// block-size samples, the one closest to their mean (the first such on a
+// tie).  Shifted samples -- and the widest-boxcar series built from them --
+// then have a mean small against their spread, and a constant row shifts to
+// exact zeros.  Any constant gives the same statistics in exact arithmetic; T
+// is shifted back in FP64.
+template <int DT>
+__device__ float pilot_shift(const Loader<DT>& ld, int64_t ncols, MsdScratch& sh)
+{
+    const int tid = threadIdx.x, nw = blockDim.x >> 6;
+    const int64_t n = ncols < (int64_t)blockDim.x ? ncols : (int64_t)blockDim.x;
+    const float x = tid < n ? ld.at(tid) : 0.f;
+    float v = x;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    __syncthreads();
+    if ((tid & 63) == 0) sh.shift[tid >> 6] = v;
+    __syncthreads();
+    float sum = 0.f;
+    for (int w = 0; w < nw; ++w) sum += sh.shift[w];
+    const float m = sum / (float)n;
+    // key: |x - m| (a non-negative float orders as its bits), then the index
+    unsigned long long key = tid < n ? ((unsigned long long)__float_as_uint(fabsf(x - m)) << 32) | (unsigned)tid
+                                     : ~0ull;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(key, off);
+        key = o < key ? o : key;
+    }
+    if ((tid & 63) == 0) sh.isum[0][tid >> 6] = key;
+    __syncthreads();
+    unsigned long long best = sh.isum[0][0];
+    for (int w = 1; w < nw; ++w) best = sh.isum[0][w] < best ? sh.isum[0][w] : best;
+    __syncthreads();                                    // isum is reused by the caller
+    return ld.at((int64_t)(best & 0xffffffffu));
+}
 
 // ---------------------------------------------------------------------------
 // Sec. 2.1 on U8 planes: exact integer sums in the stored domain
@@ -363,7 +390,7 @@ __device__ void msd_block_x(const PlaneArg& pl, bool vec, int64_t r, int64_t b, 
     }
     const int tid = threadIdx.x, nt = blockDim.x;
     Loader<DT> ld(pl, r);
-    const float K = pilot_shift<DT>(ld, pl.n_cols, sh.shift);
+    const float K = pilot_shift<DT>(ld, pl.n_cols, sh);
     const int64_t lo = max(b * bc, ncb), hi = min((b + 1) * bc, pl.n_cols);
     Msd s{0.f, 0.f, 0.f};
     if (lo < hi) {
@@ -426,246 +453,360 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-constexpr int kMsdSubTile = 1024;  // window starts per wave sub-tile in msd_block_xy
+// ---------------------------------------------------------------------------
+// Sec. 2.1-2.2: raw statistics and the widest boxcar's statistics in one read
+// ---------------------------------------------------------------------------
+//
+// sigma_Nmax of Eq. (sd03) needs the mean and spread of the widest boxcar
+// y(t) = sum_{k<nmax} x[t+k] over every start t.  A wave owns a contiguous
+// range of the block's columns and walks it in steps of 64*R starts; lane l
+// takes the run of R consecutive starts t0 = u + R*l (R = 16, 8 for F32) and
+// reads two windows of R samples straight from memory: its own x[t0 ..] and
+// the shifted x[t0+nmax ..].  With D_k = x[t0+nmax+k] - x[t0+k] the series
+// advances as y(t+1) = y(t) + D_k, so y(t0+k) = y0 + c_k, c_k = D_0 + ... +
+// D_{k-1}, and the lane needs y0 = y(t0) only once per run:
+//   sum_k y = R*y0 + sum_k c_k,   sum_k y^2 = R*y0^2 + 2*y0*sum_k c_k + sum_k c_k^2.
+// y0 of lane l is the y of the step's first start plus the exclusive wave scan
+// of the runs' drifts c_R; the next step starts from that plus the whole
+// wave's drift (a running FP64 carry), and only the first start of the range
+// takes a direct window sum.  Every sample is read twice, the second time
+// mostly from cache, with no LDS and no barrier inside the walk.  Samples are
+// shifted by K (pilot_shift); the raw sums and the run sums are FP32 over one
+// run and FP64 across runs, and the block's S = sum d^2 - (sum d)^2/n is
+// formed in FP64.
 
-// LDS floats per wave of msd_block_xy for a given widest boxcar.
-__host__ __device__ inline int msd_xy_npw(int nmax) { return (kMsdSubTile + nmax + 255) / 256 * 256; }
+constexpr int kRun = 16;                // consecutive starts per lane
+constexpr int kRunStep = 64 * kRun;     // starts per wave step (U8); wave spans are multiples of 4 steps
+// Steps per iteration of the U8 walk, their loads in flight together (one for
+// F32 / F16, whose wider windows fill the registers).
+constexpr int kU8Steps = 2;
 
-// Raw-sample partials plus the partials of the widest boxcar series
-// y(t) = sum_{k<nmax} x[t+k] for starts t in [block start, min(block end, nout)),
-// which give sigma_Nmax of Eq. (sd03).  Each wave walks its own sub-tiles of
-// kMsdSubTile starts: it loads the sub-tile plus its nmax-1 halo (shifted by
-// K), forms the exclusive prefix E in its own LDS region (`lds`, npw floats per
-// wave) with a wave scan, and takes y(t) = E[t+nmax] - E[t].  The same loads
-// feed the raw statistics.
-// msd_block_xy on a U8 plane, in integers: each wave's exclusive prefix E of
-// the stored bytes (int32, exact) over a sub-tile and its nmax-1 halo, the
-// raw sums from the same words, and y(t) = E[t+nmax] - E[t].
-__device__ void msd_block_xy_u8(const PlaneArg& pl, bool vec, int64_t r, int64_t b, int64_t ncb, int64_t bc,
-                                int32_t nmax, int64_t nout, int32_t npw, float* lds, double* out6, MsdScratch& sh)
+// 4*NDW bytes from `p` with aligned dword loads.  RA (realign): p may sit off a
+// 4-byte boundary by sh = p & 3 (the same for every lane of the wave); one more
+// dword is read and v_alignbyte shifts the bytes into place.  Each dword read
+// holds a byte of the window or of the 4 bytes after it.
+template <int NDW, bool RA>
+__device__ __forceinline__ void load_window(const uint8_t* p, uint32_t sh, uint32_t (&w)[NDW])
 {
-    constexpr int TSW = kMsdSubTile;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    int* E = (int*)lds + (size_t)wave * npw;
+    struct __attribute__((aligned(4))) U4 { uint32_t v[4]; };
+    const uint32_t* q = (const uint32_t*)(p - (RA ? sh : 0u));
+    uint32_t d[NDW + 1];
+#pragma unroll
+    for (int j = 0; j < NDW; j += 4) {
+        const U4 t = *(const U4*)(q + j);
+        d[j] = t.v[0]; d[j + 1] = t.v[1]; d[j + 2] = t.v[2]; d[j + 3] = t.v[3];
+    }
+    if constexpr (RA) {
+        d[NDW] = q[NDW];
+#pragma unroll
+        for (int j = 0; j < NDW; ++j) w[j] = __builtin_amdgcn_alignbyte(d[j + 1], d[j], sh);
+    } else {
+#pragma unroll
+        for (int j = 0; j < NDW; ++j) w[j] = d[j];
+    }
+}
+
+// Run length of the F32 / F16 walks: 8 for F32, so that a lane's window is 32
+// bytes as for F16 (64-byte windows per lane cost F32 about 10% in load rate).
+template <int DT> constexpr int run_len() { return DT == SPD_F32 ? 8 : kRun; }
+
+// Sample k of a run's dwords (F32 / F16).
+template <int DT, int NDW>
+__device__ __forceinline__ float run_at(const uint32_t (&w)[NDW], int k)
+{
+    if constexpr (DT == SPD_F32) {
+        return __uint_as_float(w[k]);
+    } else {
+        const __half2 h = *reinterpret_cast<const __half2*>(&w[k >> 1]);
+        return (k & 1) ? __high2float(h) : __low2float(h);
+    }
+}
+
+// Sum of a double over the wave (every lane gets the same value).
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Block sums of K per-thread doubles in a fixed order (lanes, then waves);
+// the result is valid in thread 0.
+template <int K>
+__device__ __forceinline__ void block_dsum(double (&v)[K], MsdScratch& sh)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_sum_f64(v[k]);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh.dsum[k][wave] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            double t = 0.0;
+            for (int w = 0; w < nw; ++w) t += sh.dsum[k][w];
+            v[k] = t;
+        }
+}
+
+// One run's sums, fed start by start: the raw sums of the shifted samples
+// that count (xv), and sum c_k, sum c_k^2 over the starts that count (yv);
+// c ends as the run's drift c_kRun.
+struct RunAcc {
+    float s1 = 0.f, s2 = 0.f, c = 0.f, sc = 0.f, qc = 0.f;
+    // d = x[t0+k] - K, D = x[t0+nmax+k] - x[t0+k]
+    template <bool ALL>
+    __device__ __forceinline__ void add(float d, float D, bool xv, bool yv)
+    {
+        const float v = ALL || xv ? d : 0.f;
+        s1 += v;
+        s2 = fmaf(v, v, s2);
+        const float cy = ALL || yv ? c : 0.f;
+        sc += cy;
+        qc = fmaf(cy, cy, qc);
+        c += D;
+    }
+};
+
+// Folds one step's run sums into the lane's FP64 accumulators {sum x, sum x^2,
+// sum y, sum y^2} (shifted); `ny` starts of the run count for y.
+__device__ __forceinline__ void step_fold(double (&acc)[4], double& carry, bool with_y, const RunAcc& ra, int ny)
+{
+    acc[0] += (double)ra.s1;
+    acc[1] += (double)ra.s2;
+    if (with_y) {                                       // uniform
+        const float inc = wave_inclusive_scan(ra.c);
+        const double y0 = carry + (double)(inc - ra.c);
+        const double dsc = (double)ra.sc;
+        acc[2] += fma((double)ny, y0, dsc);
+        acc[3] += fma(y0, fma((double)ny, y0, 2.0 * dsc), (double)ra.qc);
+        carry += (double)__int_as_float(__builtin_amdgcn_readlane(__float_as_int(inc), 63));
+    }
+}
+
+// The walk of one wave's columns [w0, w1) on an F32 / F16 row, one step at a
+// time: RAO / RAN say whether the own / shifted windows sit off 4-byte
+// boundaries.  (Loading the next step ahead into a second register set was
+// slower: the extra registers halve the waves per SIMD.)
+template <int DT, bool RAO, bool RAN>
+__device__ __forceinline__ void walk_f(const Loader<DT>& ld, float K, int64_t w0, int64_t w1, int64_t xlo,
+                                       int64_t yhi, int64_t ncols, int32_t nmax, double (&acc)[4], double& carry)
+{
+    constexpr int ES = DT == SPD_F32 ? 4 : 2, RUN = run_len<DT>(), STEP = 64 * RUN, NDW = RUN * ES / 4;
+    const int lane = threadIdx.x & 63;
+    const uint8_t* rowb = (const uint8_t*)ld.row;
+    // F16: x - K and x[t+nmax] - x as FMAs by an opaque 1 take the halves as
+    // they are (v_fma_mix_f32, one rounding like a convert and a subtract)
+    float one = 1.f;
+    if constexpr (DT == SPD_F16) asm("s_mov_b32 %0, 1.0" : "=s"(one));
+    const uint32_t sho = (uint32_t)((uintptr_t)rowb & 3), shn = (uint32_t)(((uintptr_t)rowb + nmax * ES) & 3);
+    for (int64_t u = w0; u < w1; u += STEP) {
+        const int64_t t0 = u + RUN * lane;
+        RunAcc ra;
+        if (u >= xlo && u + STEP <= min(w1, yhi) && u + STEP + nmax + 4 <= ncols) {
+            // every start counts and every sample read is inside the row
+            uint32_t wo[NDW], wn[NDW];
+            load_window<NDW, RAO>(rowb + t0 * ES, sho, wo);
+            load_window<NDW, RAN>(rowb + (t0 + nmax) * ES, shn, wn);
+#pragma unroll
+            for (int k = 0; k < RUN; ++k) {
+                const float x = run_at<DT, NDW>(wo, k), xn = run_at<DT, NDW>(wn, k);
+                ra.add<true>(fmaf(x, one, -K), fmaf(xn, one, -x), true, true);
+            }
+            step_fold(acc, carry, true, ra, RUN);
+        } else {
+            const bool with_y = u < yhi;
+#pragma unroll 1
+            for (int k = 0; k < RUN; ++k) {
+                const int64_t c = t0 + k;
+                const float x = c < ncols ? ld.at(c) : 0.f;
+                const float xn = with_y && c + nmax < ncols ? ld.at(c + nmax) : 0.f;
+                ra.add<false>(x - K, xn - x, c >= xlo && c < w1, c < yhi);
+            }
+            step_fold(acc, carry, with_y, ra, (int)max(min(yhi - t0, (int64_t)RUN), (int64_t)0));
+        }
+    }
+}
+
+// Raw-sample partials of columns [max(block start, new_col_begin), block end)
+// and the widest-boxcar partials of starts [block start, min(block end, nout)),
+// which give sigma_Nmax of Eq. (sd03).  Writes {n, T, S} of each to out6.
+template <int DT>
+__device__ void msd_block_xy_f(const PlaneArg& pl, int64_t r, int64_t b, int64_t ncb, int64_t bc, int32_t nmax,
+                               int64_t nout, double* out6, MsdScratch& sh)
+{
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar walk bounds
+    Loader<DT> ld(pl, r);
+    const float K = pilot_shift<DT>(ld, pl.n_cols, sh);
+    const int64_t ncols = pl.n_cols;
+    const int64_t c0 = b * bc, c1 = min(c0 + bc, ncols);
+    const int64_t xlo = max(c0, ncb), yhi = min(c1, nout);
+    const int64_t w0 = c0 + (int64_t)wave * (bc / nw), w1 = min(w0 + bc / nw, c1);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};              // sum x, sum x^2, sum y, sum y^2 (shifted)
+    double carry = 0.0;                                 // y at the next step's first start
+    if (w0 < yhi) {
+        double s = 0.0;
+        for (int64_t c = w0 + lane; c < w0 + nmax; c += 64) s += c < ncols ? (double)(ld.at(c) - K) : 0.0;
+        carry = wave_sum_f64(s);
+    }
+    if constexpr (DT == SPD_F32) {
+        walk_f<DT, false, false>(ld, K, w0, w1, xlo, yhi, ncols, nmax, acc, carry);
+    } else {
+        const uintptr_t a = (uintptr_t)ld.row;
+        const bool ro = (a & 3) != 0, rn = ((a + 2 * (uintptr_t)nmax) & 3) != 0;
+        if (!ro && !rn) walk_f<DT, false, false>(ld, K, w0, w1, xlo, yhi, ncols, nmax, acc, carry);
+        else if (!ro) walk_f<DT, false, true>(ld, K, w0, w1, xlo, yhi, ncols, nmax, acc, carry);
+        else if (!rn) walk_f<DT, true, false>(ld, K, w0, w1, xlo, yhi, ncols, nmax, acc, carry);
+        else walk_f<DT, true, true>(ld, K, w0, w1, xlo, yhi, ncols, nmax, acc, carry);
+    }
+    block_dsum<4>(acc, sh);
+    if (threadIdx.x == 0) {
+        // S = sum d^2 - (sum d)^2 / n without contraction: one value gives S = 0
+#pragma clang fp contract(off)
+        const double nx = (double)max(c1 - xlo, (int64_t)0), ny = (double)max(yhi - c0, (int64_t)0);
+        out6[0] = nx;
+        out6[1] = acc[0] + nx * (double)K;
+        out6[2] = nx > 0.0 ? fmax(acc[1] - acc[0] * (acc[0] / nx), 0.0) : 0.0;
+        out6[3] = ny;
+        out6[4] = acc[2] + ny * (double)nmax * (double)K;
+        out6[5] = ny > 0.0 ? fmax(acc[3] - acc[2] * (acc[2] / ny), 0.0) : 0.0;
+    }
+}
+
+// One U8 run's widest-boxcar sums in integers, fed start by start (as RunAcc):
+// |c_k| <= 255*kRun, so c_k^2 and the run's sums fit in int32.
+struct RunAccI {
+    int c = 0, sc = 0, qc = 0;
+    template <bool ALL>
+    __device__ __forceinline__ void add(int x, int xn, bool yv)
+    {
+        if (ALL || yv) {
+            sc += c;
+            // |c| < 2^23: the full-rate 24-bit multiply-add (the compiler cannot
+            // prove the range through the run and would pick v_mul_lo_u32)
+            int r;
+            asm("v_mad_i32_i24 %0, %1, %1, %2" : "=v"(r) : "v"(c), "v"(qc));
+            qc = r;
+        }
+        c += xn - x;
+    }
+};
+
+// Folds a U8 step into the lane's y sums: y0 and the carry are at most
+// 255*nmax < 2^21; a lane's sum of y over its <= 16 runs (a block spans at most
+// 65536 columns, 16384 per wave) stays below 2^31; the sum of y^2 is 64-bit.
+__device__ __forceinline__ void u8_fold(const RunAccI& ra, int ny, uint32_t& sy1, long long& sy2, int& carry)
+{
+    const int inc = wave_inclusive_scan_i(ra.c);
+    const int y0 = carry + (inc - ra.c);
+    sy1 += (uint32_t)(ny * y0 + ra.sc);
+    sy2 += (long long)y0 * (long long)(ny * y0 + 2 * ra.sc) + (long long)ra.qc;
+    carry += __builtin_amdgcn_readlane(inc, 63);
+}
+
+// The walk of one wave's columns [w0, w1) on a U8 row.  RAO / RAN: the own /
+// shifted windows sit off 4-byte boundaries.  (Taking the shifted window
+// across lanes with ds_bpermute instead of a second load was slower.)
+template <bool RAO, bool RAN>
+__device__ __forceinline__ void walk_u8(const uint8_t* row, int64_t w0, int64_t w1, int64_t xlo, int64_t yhi,
+                                        int64_t ncols, int32_t nmax, uint32_t& sx1, uint32_t& sx2, uint32_t& sy1,
+                                        long long& sy2, int& carry)
+{
+    constexpr int kRunSteps = kU8Steps, SPAN = kRunSteps * kRunStep, NW = kRun / 4;
+    const int lane = threadIdx.x & 63;
+    const uint32_t sho = (uint32_t)((uintptr_t)row & 3), shn = (uint32_t)(((uintptr_t)row + nmax) & 3);
+    for (int64_t u = w0; u < w1; u += SPAN) {
+        if (u >= xlo && u + SPAN <= min(w1, yhi) && u + SPAN + nmax + 4 <= ncols) {
+            uint32_t wo[kRunSteps][NW], wn[kRunSteps][NW];
+#pragma unroll
+            for (int j = 0; j < kRunSteps; ++j) {
+                const int64_t t0 = u + j * kRunStep + kRun * lane;
+                load_window<NW, RAO>(row + t0, sho, wo[j]);
+                load_window<NW, RAN>(row + t0 + nmax, shn, wn[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < kRunSteps; ++j) {
+                RunAccI ra;
+#pragma unroll
+                for (int i = 0; i < NW; ++i) {
+                    u8_word(wo[j][i], sx1, sx2);
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        ra.add<true>((int)((wo[j][i] >> (8 * k)) & 255u), (int)((wn[j][i] >> (8 * k)) & 255u), true);
+                }
+                u8_fold(ra, kRun, sy1, sy2, carry);
+            }
+        } else {
+            for (int j = 0; j < kRunSteps && u + j * kRunStep < w1; ++j) {
+                const int64_t us = u + j * kRunStep, t0 = us + kRun * lane;
+                const bool with_y = us < yhi;
+                RunAccI ra;
+#pragma unroll 1
+                for (int k = 0; k < kRun; ++k) {
+                    const int64_t c = t0 + k;
+                    const uint32_t q = c < ncols ? (uint32_t)row[c] : 0u;
+                    const uint32_t qn = with_y && c + nmax < ncols ? (uint32_t)row[c + nmax] : 0u;
+                    if (c >= xlo && c < w1) {
+                        sx1 += q;
+                        sx2 += q * q;
+                    }
+                    ra.add<false>((int)q, (int)qn, c < yhi);
+                }
+                if (with_y) u8_fold(ra, (int)max(min(yhi - t0, (int64_t)kRun), (int64_t)0), sy1, sy2, carry);
+            }
+        }
+    }
+}
+
+// The same on a U8 plane, in integers (exact up to the conversion's last
+// rounding in u8_partial): byte sums per word (v_sad_u8, v_dot4), the runs'
+// c_k sums in int32, the y sums in 64 bits.
+__device__ void msd_block_xy_u8(const PlaneArg& pl, int64_t r, int64_t b, int64_t ncb, int64_t bc, int32_t nmax,
+                                int64_t nout, double* out6, MsdScratch& sh)
+{
+    const int lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // uniform: scalar walk bounds
     const uint8_t* row = (const uint8_t*)pl.data + r * pl.stride;
     const int64_t ncols = pl.n_cols;
     const int64_t c0 = b * bc, c1 = min(c0 + bc, ncols);
     const int64_t xlo = max(c0, ncb), yhi = min(c1, nout);
-    const int nrow = npw / 256;
-    uint32_t sx1 = 0, sx2 = 0;                          // <= 16 samples per sub-tile, <= 64 sub-tiles per lane
-    unsigned long long sy1 = 0;
-    // a lane's y^2 sum: at most 512 values (<= 255 * 4096 each) per lane and
-    // block, below 2^53, so the FP64 sum is the exact integer
-    double sy2 = 0.0;
-    // four bytes from column c (a multiple of 4), zero past the end of the row
-    auto word = [&](int64_t c) -> uint32_t {
-        if (vec && c + 3 < ncols) return *(const uint32_t*)(row + c);
-        uint32_t w = 0;
+    const int64_t w0 = c0 + (int64_t)wave * (bc / nw), w1 = min(w0 + bc / nw, c1);
+    uint32_t sx1 = 0, sx2 = 0, sy1 = 0;                 // <= 16 runs of 16 bytes per lane (block span <= 65536)
+    long long sy2 = 0;
+    int carry = 0;
+    if (w0 < yhi) {
+        int s = 0;
+        for (int64_t c = w0 + lane; c < w0 + nmax; c += 64) s += c < ncols ? (int)row[c] : 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) w |= (c + k < ncols ? (uint32_t)row[c + k] : 0u) << (8 * k);
-        return w;
-    };
-    for (int64_t u0 = c0 + (int64_t)wave * TSW; u0 < c1; u0 += (int64_t)nw * TSW) {
-        const int64_t u1 = min(u0 + TSW, c1);
-        int carry = 0;
-        uint32_t wr[4];                                 // the lane's raw words of rows 0..3
-        // one row of 256 bytes: its share of the prefix E
-        auto rowscan = [&](int m, uint32_t w) {
-            const int l0 = w & 255, l1 = l0 + ((w >> 8) & 255), l2 = l1 + ((w >> 16) & 255), l3 = l2 + (w >> 24);
-            const int inc = wave_inclusive_scan_i(l3);
-            const int ex = inc - l3 + carry;
-            carry += __builtin_amdgcn_readlane(inc, 63);
-            *(int4*)(E + 256 * m + 4 * lane) = make_int4(ex, ex + l0, ex + l1, ex + l2);
-        };
-        if (vec && u0 + 256 * nrow <= ncols) {
-            // the sub-tile and its halo inside the row: four word loads in flight at once
-            for (int m0 = 0; m0 < nrow; m0 += 4) {
-                uint32_t w[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) w[j] = *(const uint32_t*)(row + u0 + 256 * min(m0 + j, nrow - 1) + 4 * lane);
-                if (m0 == 0) {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) wr[j] = w[j];
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (m0 + j < nrow) rowscan(m0 + j, w[j]);
-            }
-        } else {
-            for (int m = 0; m < nrow; ++m) {
-                const uint32_t w = word(u0 + 256 * m + 4 * lane);
-                if (m < 4) wr[m] = w;
-                rowscan(m, w);
-            }
-        }
-        if (u0 >= xlo && u0 + TSW <= c1) {
-#pragma unroll
-            for (int m = 0; m < 4; ++m) u8_word(wr[m], sx1, sx2);
-        } else {
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int64_t c = u0 + 256 * m + 4 * lane + j;
-                    if (c >= xlo && c < u1) {
-                        const uint32_t q = (wr[m] >> (8 * j)) & 255u;
-                        sx1 += q;
-                        sx2 += q * q;
-                    }
-                }
-        }
-        wave_sync();
-        // with nmax a multiple of 4 the shifted reads are aligned 16-byte reads
-        const bool y_whole = u0 + TSW <= yhi;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int p = 256 * m + 4 * lane;
-            const int4 e = *(const int4*)(E + p);
-            int4 f;
-            if ((nmax & 3) == 0) f = *(const int4*)(E + p + nmax);
-            else f = make_int4(E[p + nmax], E[p + 1 + nmax], E[p + 2 + nmax], E[p + 3 + nmax]);
-            const uint32_t y[4] = {(uint32_t)(f.x - e.x), (uint32_t)(f.y - e.y), (uint32_t)(f.z - e.z),
-                                   (uint32_t)(f.w - e.w)};
-            uint32_t t1 = 0;                            // < 2^32: four values of at most 255 * 4096
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (y_whole || u0 + p + j < yhi) {
-                    t1 += y[j];
-                    const double yd = (double)y[j];
-                    sy2 = fma(yd, yd, sy2);
-                }
-            }
-            sy1 += t1;
-        }
-        wave_sync();
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        carry = s;
     }
-    unsigned long long v[4] = {sx1, sx2, sy1, (unsigned long long)sy2};
-    block_isum<4>(v, sh);
-    if (tid == 0) {
-        const double sc = (double)pl.scale[r], z = (double)pl.zero[r];
-        u8_partial((double)max(c1 - xlo, (int64_t)0), v[0], v[1], sc, z, out6);
-        u8_partial((double)max(yhi - c0, (int64_t)0), v[2], v[3], sc, (double)nmax * z, out6 + 3);
+    const uintptr_t a = (uintptr_t)row;
+    const bool ro = (a & 3) != 0, rn = ((a + (uintptr_t)nmax) & 3) != 0;
+    if (!ro && !rn) walk_u8<false, false>(row, w0, w1, xlo, yhi, ncols, nmax, sx1, sx2, sy1, sy2, carry);
+    else if (!ro) walk_u8<false, true>(row, w0, w1, xlo, yhi, ncols, nmax, sx1, sx2, sy1, sy2, carry);
+    else if (!rn) walk_u8<true, false>(row, w0, w1, xlo, yhi, ncols, nmax, sx1, sx2, sy1, sy2, carry);
+    else walk_u8<true, true>(row, w0, w1, xlo, yhi, ncols, nmax, sx1, sx2, sy1, sy2, carry);
+    unsigned long long acc[4] = {sx1, sx2, sy1, (unsigned long long)sy2};
+    block_isum<4>(acc, sh);
+    if (threadIdx.x == 0) {
+        const double s = (double)pl.scale[r], z = (double)pl.zero[r];
+        u8_partial((double)max(c1 - xlo, (int64_t)0), acc[0], acc[1], s, z, out6);
+        u8_partial((double)max(yhi - c0, (int64_t)0), acc[2], acc[3], s, (double)nmax * z, out6 + 3);
     }
 }
 
 template <int DT>
 __device__ void msd_block_xy(const PlaneArg& pl, bool vec, int64_t r, int64_t b, int64_t ncb, int64_t bc,
-                             int32_t nmax, int64_t nout, int32_t npw, float* lds, double* out6, MsdScratch& sh)
+                             int32_t nmax, int64_t nout, double* out6, MsdScratch& sh)
 {
-    if constexpr (DT == SPD_U8) {
-        msd_block_xy_u8(pl, vec, r, b, ncb, bc, nmax, nout, npw, lds, out6, sh);
-        return;
-    }
-    constexpr int TSW = kMsdSubTile;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    float* E = lds + (size_t)wave * npw;
-    Loader<DT> ld(pl, r);
-    const float K = pilot_shift<DT>(ld, pl.n_cols, sh.shift);
-    const int64_t c0 = b * bc, c1 = min(c0 + bc, pl.n_cols);
-    const int64_t xlo = max(c0, ncb), yhi = min(c1, nout);
-    const int nrow = npw / 256;
-    Msd sx{0.f, 0.f, 0.f}, sy{0.f, 0.f, 0.f};
-    static_assert(TSW == 1024, "a lane's raw samples and boxcar starts per sub-tile are one batch of 16");
-    for (int64_t u0 = c0 + (int64_t)wave * TSW; u0 < c1; u0 += (int64_t)nw * TSW) {
-        const int64_t u1 = min(u0 + TSW, c1);
-        // sub-tiles whose raw samples / boxcar starts all count take them as one batch of 16 per lane
-        const bool x_whole = u0 >= xlo && u0 + TSW <= c1;
-        const bool y_whole = u0 + TSW <= yhi;
-        float carry = 0.f;
-        float xb[16];                                       // the lane's raw samples of rows 0..3
-        auto keep = [&](int j, float4 v) {
-            xb[4 * j] = v.x; xb[4 * j + 1] = v.y; xb[4 * j + 2] = v.z; xb[4 * j + 3] = v.w;
-        };
-        // one row of 256 samples: its share of the prefix E (no branches, so the
-        // scans of neighbouring rows can interleave)
-        auto row = [&](int m, float4 v) {
-            const int p = 256 * m + 4 * lane;
-            const float l0 = v.x, l1 = l0 + v.y, l2 = l1 + v.z, l3 = l2 + v.w;
-            const float inc = wave_inclusive_scan(l3);
-            const float ex = (inc - l3) + carry;
-            carry += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(inc), 63));
-            const float4 e = make_float4(ex, ex + l0, ex + l1, ex + l2);
-            *(float4*)(E + p) = e;
-        };
-        if (vec && u0 + 256 * nrow <= pl.n_cols) {
-            // the sub-tile and its halo inside the row: four vector loads in flight at once
-            for (int m0 = 0; m0 < nrow; m0 += 4) {
-                float4 v[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) v[j] = ld.vec(u0 + 256 * min(m0 + j, nrow - 1) + 4 * lane);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    v[j].x -= K; v[j].y -= K; v[j].z -= K; v[j].w -= K;
-                }
-                if (m0 == 0) {                                  // rows 0..3 hold the sub-tile's raw samples
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) keep(j, v[j]);
-                }
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (m0 + j < nrow) row(m0 + j, v[j]);
-            }
-        } else {
-#pragma unroll
-            for (int m = 0; m < TSW / 256; ++m) {               // nrow > TSW / 256 for every nmax >= 1
-                const float4 v = load4_shifted<DT>(ld, u0 + 256 * m + 4 * lane, pl.n_cols, vec, K, 0.f);
-                keep(m, v);
-                row(m, v);
-            }
-            for (int m = TSW / 256; m < nrow; ++m)
-                row(m, load4_shifted<DT>(ld, u0 + 256 * m + 4 * lane, pl.n_cols, vec, K, 0.f));
-        }
-        // raw statistics: one batch of 16 per lane, or group by group at the edges
-        if (x_whole) {
-            msd_add16(sx, xb);
-        } else {
-#pragma unroll
-            for (int m = 0; m < TSW / 256; ++m)
-                msd_add4_clipped(sx, make_float4(xb[4 * m], xb[4 * m + 1], xb[4 * m + 2], xb[4 * m + 3]),
-                                 u0 + 256 * m + 4 * lane, xlo, u1);
-        }
-        wave_sync();
-        // widest-boxcar values y(t) = E[t+nmax] - E[t]; with nmax a multiple of 4 the
-        // shifted reads are aligned 16-byte reads (four dword reads 16 bytes apart
-        // per lane would share banks)
-        float yb[16];
-        auto ydiff = [&](int m, float4 e, float4 f) {
-            yb[4 * m] = f.x - e.x; yb[4 * m + 1] = f.y - e.y; yb[4 * m + 2] = f.z - e.z; yb[4 * m + 3] = f.w - e.w;
-        };
-        if ((nmax & 3) == 0) {
-#pragma unroll
-            for (int m = 0; m < TSW / 256; ++m) {
-                const int p = 256 * m + 4 * lane;
-                ydiff(m, *(const float4*)(E + p), *(const float4*)(E + p + nmax));
-            }
-        } else {
-#pragma unroll
-            for (int m = 0; m < TSW / 256; ++m) {
-                const int p = 256 * m + 4 * lane;
-                ydiff(m, *(const float4*)(E + p),
-                      make_float4(E[p + nmax], E[p + 1 + nmax], E[p + 2 + nmax], E[p + 3 + nmax]));
-            }
-        }
-        if (y_whole) {
-            msd_add16(sy, yb);
-        } else {
-#pragma unroll
-            for (int m = 0; m < TSW / 256; ++m)
-                msd_add4_clipped(sy, make_float4(yb[4 * m], yb[4 * m + 1], yb[4 * m + 2], yb[4 * m + 3]),
-                                 u0 + 256 * m + 4 * lane, u0, yhi);
-        }
-        wave_sync();
-    }
-    Msd tx = block_merge(sx, sh.part);
-    Msd ty = block_merge(sy, sh.part);
-    if (tid == 0) {
-        out6[0] = tx.n;
-        out6[1] = (double)tx.T + (double)tx.n * (double)K;
-        out6[2] = tx.S;
-        out6[3] = ty.n;
-        out6[4] = (double)ty.T + (double)ty.n * (double)nmax * (double)K;
-        out6[5] = ty.S;
-    }
+    (void)vec;                                          // windows are realigned per row
+    if constexpr (DT == SPD_U8) msd_block_xy_u8(pl, r, b, ncb, bc, nmax, nout, out6, sh);
+    else msd_block_xy_f<DT>(pl, r, b, ncb, bc, nmax, nout, out6, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -786,7 +927,7 @@ __device__ void boxcar_tile(const PlaneArg& pl, bool vec, int64_t r, int64_t tt,
             if (i < wp.n) {
                 const int w = wp.width[i];
                 const double sw = sqrt((double)w) * st.sigma + (double)(w - 1) * st.lin_coef;
-                coef[i] = (zero_var || !(sw > 0.0)) ? 0.f : (float)(1.0 / sw);   // Eq. (sd02)/(sd03)
+                coef[i] = (zero_var || !sigma_w_positive(sw, w, st.sigma)) ? 0.f : (float)(1.0 / sw);   // Eq. (sd02)/(sd03)
                 toff[i] = wp.off[i];
                 tcg[i] = wp.cg[i];
             } else {
@@ -1033,7 +1174,7 @@ __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t
             if (i < wp.n) {
                 const int w = wp.width[i];
                 const double sw = sqrt((double)w) * st.sigma + (double)(w - 1) * st.lin_coef;
-                coef[i] = (zero_var || !(sw > 0.0)) ? 0.f : (float)(1.0 / sw);   // Eq. (sd02)/(sd03)
+                coef[i] = (zero_var || !sigma_w_positive(sw, w, st.sigma)) ? 0.f : (float)(1.0 / sw);   // Eq. (sd02)/(sd03)
             } else {
                 coef[i] = __int_as_float(0x7fc00000);
             }
@@ -1562,7 +1703,7 @@ __device__ __forceinline__ void short_coefs(const spd_row_stats& st, float (&a)[
     if (lane < N) {
         const double w = (double)(lane + 1);
         const double sw = sqrt(w) * st.sigma + (w - 1.0) * st.lin_coef;
-        cf = (zero_var || !(sw > 0.0)) ? 0.f : (float)(1.0 / sw);
+        cf = (zero_var || !sigma_w_positive(sw, w, st.sigma)) ? 0.f : (float)(1.0 / sw);
     }
 #pragma unroll
     for (int j = 0; j < N; ++j) a[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cf), j));

@@ -18,7 +18,6 @@ hipError_t launch_stream(int dtype, const PlaneArg& pl, bool vec, const spd_row_
                          const WidthPlan& wp, int waves, uint64_t ntiles, hipStream_t s);
 hipError_t launch_zero_count(int64_t* count, hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t n, int64_t v, hipStream_t s);
-int msd_xy_waves(int nmax);
 hipError_t launch_select(const float* snr, const uint8_t* widx, int64_t nrows, int64_t ncols,
                          int64_t stride, const SelectArgs& sa, hipStream_t s);
 

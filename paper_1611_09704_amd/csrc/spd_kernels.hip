@@ -32,14 +32,12 @@ __global__ __launch_bounds__(256) void msd_x_kernel(PlaneArg pl, bool vec, int64
 
 template <int DT>
 __global__ __launch_bounds__(256) void msd_xy_kernel(PlaneArg pl, bool vec, int64_t ncb, int64_t bc,
-                                                     int64_t nblk, int32_t nmax, int64_t nout,
-                                                     int32_t npw, double* part)
+                                                     int64_t nblk, int32_t nmax, int64_t nout, double* part)
 {
-    extern __shared__ float lds[];
     __shared__ MsdScratch sh;
     const uint64_t wg = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t r = (int64_t)(wg / (uint64_t)nblk), b = (int64_t)(wg % (uint64_t)nblk);
-    msd_block_xy<DT>(pl, vec, r, b, ncb, bc, nmax, nout, npw, lds, part + wg * 6, sh);
+    msd_block_xy<DT>(pl, vec, r, b, ncb, bc, nmax, nout, part + wg * 6, sh);
 }
 
 __global__ __launch_bounds__(256) void msd_finalize_kernel(const double* part, int64_t per_unit,
@@ -156,13 +154,6 @@ __global__ void fill_i64_kernel(int64_t* p, int64_t n, int64_t v)
 // launchers
 // ---------------------------------------------------------------------------
 
-int msd_xy_waves(int nmax)
-{
-    int waves = 4;
-    while (waves > 1 && (size_t)waves * msd_xy_npw(nmax) * sizeof(float) > 65536 - 4096) waves >>= 1;
-    return waves;
-}
-
 template <int DT>
 static hipError_t launch_msd_dt(const PlaneArg& pl, bool vec, bool with_y, int64_t ncb, int64_t bc,
                                 int64_t nblk, int32_t nmax, int64_t nout, double* part, hipStream_t s)
@@ -171,11 +162,8 @@ static hipError_t launch_msd_dt(const PlaneArg& pl, bool vec, bool with_y, int64
     if (!with_y) {
         hipLaunchKernelGGL((msd_x_kernel<DT>), dim3(nwg), dim3(256), 0, s, pl, vec, ncb, bc, nblk, part);
     } else {
-        const int32_t npw = msd_xy_npw(nmax);
-        const int waves = msd_xy_waves(nmax);
-        const size_t lds = (size_t)waves * npw * sizeof(float);
-        hipLaunchKernelGGL((msd_xy_kernel<DT>), dim3(nwg), dim3(64 * waves), lds, s, pl, vec, ncb, bc, nblk,
-                           nmax, nout, npw, part);
+        hipLaunchKernelGGL((msd_xy_kernel<DT>), dim3(nwg), dim3(256), 0, s, pl, vec, ncb, bc, nblk, nmax, nout,
+                           part);
     }
     return hipGetLastError();
 }

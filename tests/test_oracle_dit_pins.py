@@ -28,7 +28,7 @@ def _stats(x, widths, mode="sqrtn"):
 def _snr(b, w, st):
     mean, sigma, _, coef, flags = (float(v) for v in st)
     sw = np.sqrt(w) * sigma + (w - 1) * coef
-    if int(flags) & oracle.FLAG_ZERO_VAR or not sw > 0.0:
+    if int(flags) & oracle.FLAG_ZERO_VAR or not sw > oracle.SW_FLOOR * np.sqrt(w) * sigma:
         return 0.0
     return (b - w * mean) / sw
 

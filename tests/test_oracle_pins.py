@@ -221,6 +221,27 @@ def test_threshold_is_inclusive():
     assert oracle.select(o["snr"], o["widx"], [1, 2, 3], np.nextafter(top, np.inf))["row"].size == 0
 
 
+def test_sigma_w_vanishing_at_nmax_contributes_zero():
+    """Anchored Eq. (sd03) gives sigma_Nmax exactly at w = Nmax; when that is 0
+    (a single valid start, or a row whose Nmax-boxcar is constant) the width
+    has no noise estimate and contributes SNR 0 whatever the rounding residual
+    of sigma_w, while the other widths keep their direct z-scores."""
+    rng = np.random.default_rng(31)
+    for n in (300, 97, 1024):
+        x = rng.standard_normal((1, n))
+        _, st, snr, widx = oracle.stream_step(x, [1, n // 2, n], sigma_mode="linear")
+        mu, sigma, sn, coef = st[0, :4]
+        assert sn == 0.0 and coef == pytest.approx(-math.sqrt(n) * sigma / (n - 1), rel=1e-12)
+        direct = [(x[0, 0] - mu) / sigma,
+                  (x[0, :n // 2].sum() - n // 2 * mu) / (math.sqrt(n // 2) * sigma + (n // 2 - 1) * coef), 0.0]
+        assert snr[0, 0] == pytest.approx(max(direct), rel=1e-12) and widx[0, 0] == int(np.argmax(direct))
+    # period 2: every 4-boxcar sums to 0, so sigma_4 = 0 and width 4 never wins
+    x = np.tile([1.0, -1.0], 500)[None, :]
+    _, st, snr, widx = oracle.stream_step(x, [1, 2, 4], sigma_mode="linear")
+    assert st[0, 2] == 0.0
+    assert np.all(widx[0] != 2) and np.all(np.abs(snr[0]) <= 1.0 + 1e-12)
+
+
 def test_zero_variance_unit():
     x = np.vstack([np.full(300, 4.0), np.random.default_rng(12).standard_normal(300)])
     _, st, snr, widx = oracle.stream_step(x, [1, 3, 9])
