@@ -49,7 +49,10 @@
  *         kept is a maximiser (ties of this kind need equal products of
  *         different sums and coefficients).
  *       * A unit with sigma == 0 is flagged SPD_FLAG_ZERO_VAR: all its SNRs
- *         are 0 and all width indices 0.  A width whose sigma_w <= 0 gives 0.
+ *         are 0 and all width indices 0.  A width whose sigma_w is not above
+ *         1e-9*sqrt(w)*sigma gives 0 (the anchored form is zero at w = Nmax
+ *         when sigma_Nmax = 0, and its rounding residual there has either
+ *         sign).
  *       * A sample is a candidate iff its highest SNR >= threshold.
  */
 #ifndef SPD_H
