@@ -1333,11 +1333,18 @@ __device__ void boxcar_tile_win(const PlaneArg& pl, bool vec, int64_t r, int64_t
                 for (int l2 = 1; l2 < LV; ++l2) dst += dit_level_floats(levels, l2);
                 const float* src = LV == 1 ? arrs : dst - dit_level_floats(levels, LV - 1);
                 const int n = dit_level_len(levels, LV);
-                for (int k = lane; k < n; k += 64) {
-                    const int a = LV == 1 ? win_phys(2 * k) : dit_pad(LV - 1, 2 * k);
-                    const int b = LV == 1 ? win_phys(2 * k + 1) : dit_pad(LV - 1, 2 * k + 1);
-                    dst[dit_pad(LV, k)] = __fadd_rn(src[a], src[b]);
-                }
+                // k = lane + 64 i: every padded index is the lane's plus a multiple of
+                // i known at compile time (the pads repeat every 8, 4 or 2 elements),
+                // so the unrolled build reads and writes at immediate offsets
+                constexpr int NI = (dit_level_len(4, LV) + 63) / 64;
+                const float* s0 = src + (LV == 1 ? win_phys(2 * lane) : dit_pad(LV - 1, 2 * lane));
+                const float* s1 = src + (LV == 1 ? win_phys(2 * lane + 1) : dit_pad(LV - 1, 2 * lane + 1));
+                float* d0 = dst + dit_pad(LV, lane);
+                constexpr int SS = LV == 1 ? win_phys(128) : dit_pad(LV - 1, 128);   // source step per i
+                constexpr int DS = dit_pad(LV, 64);                                  // destination step per i
+#pragma unroll
+                for (int i = 0; i < NI; ++i)
+                    if (lane + 64 * i < n) d0[DS * i] = __fadd_rn(s0[SS * i], s1[SS * i]);
                 wave_sync();
                 const int lstride = LV == 1 ? 5 : LV == 2 ? 3 : 1;      // padded offset of lane l's first start
                 const float* lbv = dst + (LV < 4 ? lstride * lane : (lane >> 1));
