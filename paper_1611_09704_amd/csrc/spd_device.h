@@ -557,12 +557,13 @@ __device__ __forceinline__ void block_dsum(double (&v)[K], MsdScratch& sh)
 // c ends as the run's drift c_kRun.
 struct RunAcc {
     float s1 = 0.f, s2 = 0.f, c = 0.f, sc = 0.f, qc = 0.f;
-    // d = x[t0+k] - K, D = x[t0+nmax+k] - x[t0+k]
-    template <bool ALL>
+    // d = x[t0+k] - K, D = x[t0+nmax+k] - x[t0+k]; S1: also sum d (else the
+    // caller sets s1)
+    template <bool ALL, bool S1 = true>
     __device__ __forceinline__ void add(float d, float D, bool xv, bool yv)
     {
         const float v = ALL || xv ? d : 0.f;
-        s1 += v;
+        if constexpr (S1) s1 += v;
         s2 = fmaf(v, v, s2);
         const float cy = ALL || yv ? c : 0.f;
         sc += cy;
@@ -611,10 +612,25 @@ __device__ __forceinline__ void walk_f(const Loader<DT>& ld, float K, int64_t w0
             uint32_t wo[NDW], wn[NDW];
             load_window<NDW, RAO>(rowb + t0 * ES, sho, wo);
             load_window<NDW, RAN>(rowb + (t0 + nmax) * ES, shn, wn);
+            if constexpr (DT == SPD_F16) {
+                // the run's sum from the stored halves, two per v_dot2c_f32_f16
+                typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+                const h2 ones = {(_Float16)1.0f, (_Float16)1.0f};
+                float sx = 0.f;
 #pragma unroll
-            for (int k = 0; k < RUN; ++k) {
-                const float x = run_at<DT, NDW>(wo, k), xn = run_at<DT, NDW>(wn, k);
-                ra.add<true>(fmaf(x, one, -K), fmaf(xn, one, -x), true, true);
+                for (int j = 0; j < NDW; ++j) sx = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2, wo[j]), ones, sx, false);
+#pragma unroll
+                for (int k = 0; k < RUN; ++k) {
+                    const float x = run_at<DT, NDW>(wo, k), xn = run_at<DT, NDW>(wn, k);
+                    ra.add<true, false>(fmaf(x, one, -K), fmaf(xn, one, -x), true, true);
+                }
+                ra.s1 = fmaf(-(float)RUN, K, sx);
+            } else {
+#pragma unroll
+                for (int k = 0; k < RUN; ++k) {
+                    const float x = run_at<DT, NDW>(wo, k), xn = run_at<DT, NDW>(wn, k);
+                    ra.add<true>(x - K, xn - x, true, true);
+                }
             }
             step_fold(acc, carry, true, ra, RUN);
         } else {
