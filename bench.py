@@ -193,7 +193,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs the path on a single MI355X "
+        print("bench.py measures one GPU only: the path runs on a single MI355X "
               "(rows and beams are independent, so N GPUs would each take 1/N of the rows); "
               "--gpus %d is not supported" % max(args.gpus, world), file=sys.stderr)
         sys.exit(2)

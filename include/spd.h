@@ -72,7 +72,7 @@ extern "C" {
 typedef enum {
     SPD_OK = 0,
     SPD_E_INVALID = 1,      /* bad argument (message in spd_last_error)         */
-    SPD_E_UNSUPPORTED = 2,  /* valid request this build does not handle          */
+    SPD_E_UNSUPPORTED = 2,  /* valid request the library does not handle         */
     SPD_E_NOMEM = 3,        /* workspace too small / allocation failed          */
     SPD_E_DEVICE = 4,       /* the HIP runtime reported an error                */
     SPD_E_AGAIN = 5         /* serving: queue full or nothing ready (retry)      */
