@@ -209,6 +209,24 @@ def test_precision_forms_parity(form):
         run_and_check(x, cfg["widths"], cfg["threshold"], scale=scale, zero=zero, mode="auto")
 
 
+@pytest.mark.parametrize("form", ["f16", "u8"])
+def test_precision_forms_full_tiny_plane(form):
+    """The precision form at its full size: the 64 x 65,536 tiny plane (five
+    pulses, widths 1..32, sqrt(N) sigma, threshold 6) stored as FP16 and as
+    U8 (20 counts per sigma), every output against the oracle on the stored
+    values, and the pulses still recovered."""
+    cfg = synth.tiny(device=DEV)
+    x32 = cfg["plane"].x
+    if form == "f16":
+        x, scale, zero = synth.quantize_f16(x32), None, None
+    else:
+        x, scale, zero = synth.quantize_u8(x32, cfg["plane"].row_sigma)
+    g, o, worst, _ = run_and_check(x, cfg["widths"], cfg["threshold"], scale=scale, zero=zero)
+    for pu in cfg["plane"].pulses:           # every injected pulse is still detected near its start
+        hit = [c for c in g["cands"] if c["row"] == pu.row and abs(int(c["t"]) - pu.t0) <= pu.width]
+        assert hit, "pulse %s not detected" % (pu,)
+
+
 @pytest.mark.parametrize("mode", ["sqrtn", "linear"])
 def test_streaming_accumulate_matches_oracle(mode):
     rng = np.random.default_rng(21)
