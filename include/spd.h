@@ -539,6 +539,34 @@ spd_status spd_server_counters(spd_server* server, int64_t* submitted, int64_t* 
  * bytes it allocated (any output may be NULL).                             */
 spd_status spd_server_info(spd_server* server, int32_t* pool_buffers, int32_t* n_streams, int64_t* device_bytes);
 
+/*
+ * Checkpoint and restore of one beam's stream: its running FP64 statistics
+ * (one spd_msd_state per detection row, Sec. 2.1 Eq. MSD04 merges every chunk
+ * into them), the last Nmax-1 detection columns of its previous chunk, with
+ * de-dispersion in front the last filterbank columns too, and the number of
+ * the chunk it expects next.  A beam restored from a checkpoint continues
+ * exactly where the saved one stopped: the chunks that follow give the
+ * candidates (bit for bit) an uninterrupted stream gives.
+ *
+ * spd_server_beam_state_bytes: size of one beam's checkpoint for this
+ *   server's configuration (0 if server is NULL).
+ * spd_server_save_beam: writes the checkpoint of `beam` to buf [host], of at
+ *   least spd_server_beam_state_bytes bytes.  The beam must be idle: every
+ *   chunk submitted for it has finished on the device (its result need not
+ *   have been polled); otherwise SPD_E_AGAIN and nothing is written.  Blocks
+ *   the calling thread for the device-to-host copies.
+ * spd_server_load_beam: replaces the state of `beam` with a checkpoint
+ *   written by spd_server_save_beam [host buf, bytes as returned by
+ *   spd_server_beam_state_bytes] of a server with the same configuration
+ *   (rows, chunk columns, dtype, widths, threshold, sigma mode, kappa,
+ *   de-dispersion geometry); SPD_E_INVALID for any other buffer.  The beam
+ *   must be idle (SPD_E_AGAIN otherwise).  Its next accepted chunk number is
+ *   the saved one.  Nothing changes on error.
+ */
+size_t spd_server_beam_state_bytes(const spd_server* server);
+spd_status spd_server_save_beam(spd_server* server, int32_t beam, void* buf, size_t bytes);
+spd_status spd_server_load_beam(spd_server* server, int32_t beam, const void* buf, size_t bytes);
+
 /* Finish the chunks in flight, stop the worker and free everything. */
 void spd_server_destroy(spd_server* server);
 

@@ -151,6 +151,12 @@ def load():
         lib.spd_server_destroy.argtypes = [vp]
         lib.spd_server_info.argtypes = [vp, P(i32), P(i32), P(i64)]
         lib.spd_server_info.restype = ctypes.c_int
+        lib.spd_server_beam_state_bytes.argtypes = [vp]
+        lib.spd_server_beam_state_bytes.restype = ctypes.c_size_t
+        lib.spd_server_save_beam.argtypes = [vp, i32, vp, ctypes.c_size_t]
+        lib.spd_server_save_beam.restype = ctypes.c_int
+        lib.spd_server_load_beam.argtypes = [vp, i32, vp, ctypes.c_size_t]
+        lib.spd_server_load_beam.restype = ctypes.c_int
         lib.spd_server_destroy.restype = None
         lib.spd_batch_plan_destroy.argtypes = [vp]
         lib.spd_batch_plan_destroy.restype = None
@@ -648,6 +654,18 @@ class Server:
         a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(load().spd_server_counters(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return {"submitted": a.value, "admitted": b.value, "completed": c.value}
+
+    def save_beam(self, beam: int) -> bytes:
+        """Checkpoint of one idle beam (spd_server_save_beam)."""
+        n = load().spd_server_beam_state_bytes(self._h)
+        buf = ctypes.create_string_buffer(n)
+        _check(load().spd_server_save_beam(self._h, int(beam), buf, n))
+        return buf.raw
+
+    def load_beam(self, beam: int, state: bytes) -> None:
+        """Restore one idle beam from save_beam's bytes (spd_server_load_beam)."""
+        buf = ctypes.create_string_buffer(state, len(state))
+        _check(load().spd_server_load_beam(self._h, int(beam), buf, len(state)))
 
     def close(self):
         if getattr(self, "_h", None):

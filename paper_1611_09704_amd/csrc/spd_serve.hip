@@ -658,6 +658,129 @@ spd_status spd_server_info(spd_server* S, int32_t* pool_buffers, int32_t* n_stre
     return SPD_OK;
 }
 
+}  // extern "C"
+
+namespace spd {
+
+// A beam checkpoint: this header, then the running statistics [det_rows], the
+// detection halo [det_rows][H] and the filterbank halo [n_rows][dd_halo].
+struct BeamCheckpoint {
+    uint32_t magic;                        // 'SPDB'
+    uint32_t version;
+    uint64_t config;                       // fingerprint of the server configuration
+    int64_t next_seq;
+    int64_t rows, halo_bytes, fb_halo_bytes;
+};
+constexpr uint32_t kCheckpointMagic = 0x42445053u;
+
+static uint64_t fnv(uint64_t h, const void* p, size_t n)
+{
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 0x100000001b3ull;
+    return h;
+}
+
+// Everything a beam's state depends on: the geometry of its planes and the
+// detection parameters.
+static uint64_t config_fingerprint(const spd_server* S)
+{
+    uint64_t h = 0xcbf29ce484222325ull;
+    const int64_t geo[] = {S->cfg.n_rows, S->cfg.chunk_cols, S->det_rows, S->halo, S->dd_halo, S->dd_delay,
+                           (int64_t)S->esize, (int64_t)S->in_esize, (int64_t)S->cfg.dtype};
+    h = fnv(h, geo, sizeof(geo));
+    h = fnv(h, S->widths.data(), sizeof(int32_t) * S->widths.size());
+    const int32_t modes[] = {(int32_t)S->params.scope, (int32_t)S->params.sigma_mode};
+    h = fnv(h, modes, sizeof(modes));
+    h = fnv(h, &S->params.threshold, sizeof(S->params.threshold));
+    h = fnv(h, &S->params.auto_kappa, sizeof(S->params.auto_kappa));
+    return h;
+}
+
+static size_t halo_bytes(const spd_server* S) { return (size_t)S->det_rows * (size_t)S->halo * (size_t)S->esize; }
+static size_t fb_halo_bytes(const spd_server* S)
+{
+    return S->dd ? (size_t)S->cfg.n_rows * (size_t)S->dd_halo : 0;
+}
+static size_t checkpoint_bytes(const spd_server* S)
+{
+    return sizeof(BeamCheckpoint) + sizeof(spd_msd_state) * (size_t)S->det_rows + halo_bytes(S) + fb_halo_bytes(S);
+}
+
+// Called with S->mu held: no request of the beam waits or runs.
+static bool beam_idle(const spd_server* S, int beam)
+{
+    if (!S->beams[beam].inflight.empty()) return false;
+    for (const ServeReq& r : S->pending)
+        if (r.beam == beam) return false;
+    return true;
+}
+
+}  // namespace spd
+
+extern "C" {
+
+size_t spd_server_beam_state_bytes(const spd_server* S)
+{
+    return S ? spd::checkpoint_bytes(S) : 0;
+}
+
+spd_status spd_server_save_beam(spd_server* S, int32_t beam, void* buf, size_t bytes)
+{
+    using namespace spd;
+    clear_error();
+    if (!S || !buf) return fail(SPD_E_INVALID, "server and buffer are required");
+    if (beam < 0 || beam >= (int)S->beams.size()) return fail(SPD_E_INVALID, "beam %d out of range", beam);
+    const size_t need = checkpoint_bytes(S);
+    if (bytes < need) return fail(SPD_E_INVALID, "checkpoint needs %zu bytes, got %zu", need, bytes);
+    std::lock_guard<std::mutex> g(S->mu);
+    if (S->fault) return fail(S->fault, "server stopped after an error: %s", S->fault_msg.c_str());
+    if (!beam_idle(S, beam)) return fail(SPD_E_AGAIN, "beam %d has chunks pending or in flight", beam);
+    ServeBeam& b = S->beams[beam];
+    hipError_t e = hipSetDevice(S->device);
+    unsigned char* out = (unsigned char*)buf + sizeof(BeamCheckpoint);
+    if (e == hipSuccess) e = hipMemcpy(out, b.state, sizeof(spd_msd_state) * (size_t)S->det_rows, hipMemcpyDeviceToHost);
+    out += sizeof(spd_msd_state) * (size_t)S->det_rows;
+    if (e == hipSuccess && halo_bytes(S)) e = hipMemcpy(out, b.halo, halo_bytes(S), hipMemcpyDeviceToHost);
+    out += halo_bytes(S);
+    if (e == hipSuccess && fb_halo_bytes(S)) e = hipMemcpy(out, b.fb_halo, fb_halo_bytes(S), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return device_status(e, "checkpoint copy");
+    BeamCheckpoint h{kCheckpointMagic, 1u, config_fingerprint(S), b.next_submit, S->det_rows,
+                     (int64_t)halo_bytes(S), (int64_t)fb_halo_bytes(S)};
+    memcpy(buf, &h, sizeof(h));
+    return SPD_OK;
+}
+
+spd_status spd_server_load_beam(spd_server* S, int32_t beam, const void* buf, size_t bytes)
+{
+    using namespace spd;
+    clear_error();
+    if (!S || !buf) return fail(SPD_E_INVALID, "server and buffer are required");
+    if (beam < 0 || beam >= (int)S->beams.size()) return fail(SPD_E_INVALID, "beam %d out of range", beam);
+    const size_t need = checkpoint_bytes(S);
+    if (bytes != need) return fail(SPD_E_INVALID, "a checkpoint of this server is %zu bytes, got %zu", need, bytes);
+    BeamCheckpoint h;
+    memcpy(&h, buf, sizeof(h));
+    if (h.magic != kCheckpointMagic || h.version != 1u) return fail(SPD_E_INVALID, "not a beam checkpoint");
+    if (h.config != config_fingerprint(S) || h.rows != S->det_rows || h.halo_bytes != (int64_t)halo_bytes(S) ||
+        h.fb_halo_bytes != (int64_t)fb_halo_bytes(S))
+        return fail(SPD_E_INVALID, "checkpoint of a server with another configuration");
+    if (h.next_seq < 0) return fail(SPD_E_INVALID, "bad chunk number in checkpoint");
+    std::lock_guard<std::mutex> g(S->mu);
+    if (S->fault) return fail(S->fault, "server stopped after an error: %s", S->fault_msg.c_str());
+    if (!beam_idle(S, beam)) return fail(SPD_E_AGAIN, "beam %d has chunks pending or in flight", beam);
+    ServeBeam& b = S->beams[beam];
+    hipError_t e = hipSetDevice(S->device);
+    const unsigned char* in = (const unsigned char*)buf + sizeof(BeamCheckpoint);
+    if (e == hipSuccess) e = hipMemcpy(b.state, in, sizeof(spd_msd_state) * (size_t)S->det_rows, hipMemcpyHostToDevice);
+    in += sizeof(spd_msd_state) * (size_t)S->det_rows;
+    if (e == hipSuccess && halo_bytes(S)) e = hipMemcpy(b.halo, in, halo_bytes(S), hipMemcpyHostToDevice);
+    in += halo_bytes(S);
+    if (e == hipSuccess && fb_halo_bytes(S)) e = hipMemcpy(b.fb_halo, in, fb_halo_bytes(S), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return device_status(e, "checkpoint copy");
+    b.next_submit = h.next_seq;
+    return SPD_OK;
+}
+
 void spd_server_destroy(spd_server* S)
 {
     if (!S) return;

@@ -249,6 +249,16 @@ def test_server_validation(lib):
     assert need > 2 * 2 * 8 * (4096 + 15) * 2
 
 
+def test_server_checkpoint_validation(lib):
+    """Beam checkpoints: a NULL server has no checkpoint size, and saving or
+    restoring without a server or buffer is refused before any device work."""
+    assert lib.spd_server_beam_state_bytes(None) == 0
+    buf = ctypes.create_string_buffer(64)
+    assert lib.spd_server_save_beam(None, 0, buf, 64) == 1
+    assert lib.spd_server_load_beam(None, 0, buf, 64) == 1
+    assert lib.spd_server_save_beam(ctypes.c_void_p(0), 0, None, 0) == 1
+
+
 def test_server_pool_sizing(lib):
     """The shared pool of chunk buffers follows the device-memory budget: the
     beams' own state first, then as many buffers as fit, at most

@@ -287,3 +287,75 @@ def test_server_with_dedisp_same_alone_and_in_a_mix():
     for k in range(K):
         assert alone[(0, k)] == mix[(0, k)], "chunk %d differs" % k
     assert sum(len(v) for v in alone.values()) > 0
+
+
+def _keys(cands):
+    return sorted((int(x["row"]), int(x["t"]), float(x["snr"]), int(x["width"])) for x in cands)
+
+
+@pytest.mark.parametrize("dedisp", [False, True])
+def test_server_checkpoint_resume_equals_uninterrupted(dedisp):
+    """Stop two beams after two chunks, save their state, restore it into a
+    new server (swapped between beam slots) and stream the rest: every later
+    chunk's candidates equal, bit for bit, those of an uninterrupted server.
+    A checkpoint of another configuration is refused, and a restored beam
+    expects the saved chunk number next."""
+    K, k0, nb = 5, 2, 2
+    if dedisp:
+        C_ch, Lc = 24, 2600
+        band = (1450.0, 30.0 / C_ch, 64e-6)
+        kc = oracle.dedisp_channel_factors(C_ch, *band)
+        plan = B.DedispPlan(C_ch, *band, np.arange(8) * (11.0 / kc[-1]))
+        chunks = []
+        for b in range(nb):
+            fb = synth.filterbank(C_ch, K * Lc, seed=700 + b, device="cuda")
+            for k in range(1, K):
+                synth.inject_along(fb, oracle.dedisp_delays(np.arange(8) * (11.0 / kc[-1]), kc)[3], k * Lc - 40, 8, 30)
+            chunks.append([fb[:, k * Lc:(k + 1) * Lc].contiguous().cpu().pin_memory() for k in range(K)])
+        W, thr, kw, R = list(range(1, 33)), 6.0, dict(dedisp=plan), C_ch
+    else:
+        R, Lc = 6, 4096
+        chunks = [s[0] for s in _streams(nb, K, R, Lc, 48, torch.float16, seed=611)]
+        W, thr, kw = list(range(1, 49)), 5.5, {}
+    p = B.Params(W, thr, "row", "sqrtn" if dedisp else "auto", 1.0)
+    print("case: checkpoint/resume dedisp=%s" % dedisp, flush=True)
+
+    full = B.Server(nb, R, Lc, p, cand_capacity=8192, **kw)
+    for k in range(K):
+        for b in range(nb):
+            full.submit(b, k, chunks[b][k])
+    ref = {(r["beam"], r["seq"]): (r, c) for r, c in _drain(full, nb * K)}
+    full.close()
+
+    first = B.Server(nb, R, Lc, p, cand_capacity=8192, **kw)
+    for k in range(k0):
+        for b in range(nb):
+            first.submit(b, k, chunks[b][k])
+    _drain(first, nb * k0)
+    saved = [first.save_beam(b) for b in range(nb)]
+    first.close()
+
+    resumed = B.Server(nb, R, Lc, p, cand_capacity=8192, **kw)
+    resumed.load_beam(1, saved[0])                       # beam slots swapped on purpose
+    resumed.load_beam(0, saved[1])
+    with pytest.raises(B.SpdError):                      # the restored beam expects chunk k0
+        resumed.submit(1, 0, chunks[0][0])
+    for k in range(k0, K):
+        resumed.submit(1, k, chunks[0][k])
+        resumed.submit(0, k, chunks[1][k])
+    got = {(r["beam"], r["seq"]): (r, c) for r, c in _drain(resumed, nb * (K - k0))}
+    resumed.close()
+    n = 0
+    for k in range(k0, K):
+        for b, slot in ((0, 1), (1, 0)):
+            r0, c0 = ref[(b, k)]
+            r1, c1 = got[(slot, k)]
+            assert r1["t_offset"] == r0["t_offset"] and r1["n_cands"] == r0["n_cands"]
+            assert _keys(c1) == _keys(c0)
+            n += len(c0)
+    assert n > 0
+
+    other = B.Server(nb, R, Lc + 8, p, cand_capacity=8192, **kw)
+    with pytest.raises(B.SpdError):
+        other.load_beam(0, saved[0])
+    other.close()
