@@ -491,7 +491,16 @@ typedef struct {
     double submit_s;           /* arrival time given at submit (steady clock, seconds) */
     double start_s;            /* when the chunk was admitted */
     double done_s;             /* when its results reached the host */
+    int32_t flags;             /* SPD_SERVE_GAP: chunks before this one were missing */
+    int32_t reserved0;
 } spd_server_result;
+
+/* spd_server_result.flags: the chunk followed a gap in the beam's chunk
+ * numbers, so it was searched without the previous chunk's halo (windows
+ * that would start in the missing data are not evaluated; with
+ * de-dispersion in front it yields chunk_cols - max_delay starts, like chunk
+ * 0).  The running statistics carry on across the gap.                     */
+#define SPD_SERVE_GAP 1
 
 /* Device bytes a server with this configuration allocates (0 if invalid, or
  * if the budget cannot hold the beams' state plus one chunk buffer).  Host
@@ -519,8 +528,11 @@ spd_status spd_server_create_dedisp(const spd_server_config* cfg, const spd_para
                                     spd_server** server);
 
 /* Queue chunk `seq` of `beam` ([host] n_rows x chunk_cols elements of the
- * configured dtype, pinned memory recommended).  seq must be the beam's next
- * chunk number (0, 1, 2, ...).  The buffer must stay valid and unchanged
+ * configured dtype, pinned memory recommended).  seq must be at least the
+ * beam's next chunk number (0, 1, 2, ...); a larger one means the chunks in
+ * between are missing: the chunk is searched without a halo, its result
+ * carries SPD_SERVE_GAP, and its t_offset places it at sample seq*chunk_cols
+ * (a lower number is SPD_E_INVALID).  The buffer must stay valid and unchanged
  * until the chunk's result has been returned by spd_server_poll.
  * arrival_s: the chunk's arrival time on the steady clock in seconds (<= 0:
  * now); latency is measured from it.  Never blocks on the device.          */

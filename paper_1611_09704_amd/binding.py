@@ -23,6 +23,7 @@ SPD_F32, SPD_F16, SPD_U8 = 0, 1, 2
 SCOPES = {"row": 0, "plane": 1}
 SIGMA_MODES = {"sqrtn": 0, "linear": 1, "auto": 2, "linear_literal": 3}
 FLAG_ZERO_VAR, FLAG_LINEAR = 1, 2
+SERVE_GAP = 1             # spd_server_result.flags: the chunk followed missing chunks
 STATUS = {0: "SPD_OK", 1: "SPD_E_INVALID", 2: "SPD_E_UNSUPPORTED", 3: "SPD_E_NOMEM",
           4: "SPD_E_DEVICE", 5: "SPD_E_AGAIN"}
 
@@ -72,7 +73,8 @@ class SpdServerConfig(ctypes.Structure):
 class SpdServerResult(ctypes.Structure):
     _fields_ = [("beam", ctypes.c_int32), ("status", ctypes.c_int32), ("seq", ctypes.c_int64),
                 ("t_offset", ctypes.c_int64), ("n_cands", ctypes.c_int64), ("n_copied", ctypes.c_int64),
-                ("submit_s", ctypes.c_double), ("start_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+                ("submit_s", ctypes.c_double), ("start_s", ctypes.c_double), ("done_s", ctypes.c_double),
+                ("flags", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
 
 _lock = threading.Lock()
@@ -630,8 +632,8 @@ class Server:
         """chunk: a host tensor [n_rows, chunk_cols], kept alive until its result is polled."""
         if chunk.is_cuda or not chunk.is_contiguous():
             raise ValueError("chunk must be a contiguous host tensor (pinned for speed)")
-        self._keep[(beam, seq)] = chunk
         _check(load().spd_server_submit(self._h, int(beam), int(seq), chunk.data_ptr(), float(arrival_s)))
+        self._keep[(beam, seq)] = chunk      # until polled (a refused submit keeps nothing)
 
     def poll(self, wait_ms: int = 0):
         """(result dict, candidates array) of one finished chunk, or None."""

@@ -63,6 +63,7 @@ static double now_s()
 struct ServeReq {
     int beam = 0;
     int64_t seq = 0;
+    bool fresh = true;                     // no previous chunk to take the halo from (chunk 0, or after a gap)
     const void* host = nullptr;
     double submit_s = 0.0, start_s = 0.0, done_s = 0.0;
     int buf = 0;                           // pool buffer while admitted
@@ -133,33 +134,36 @@ struct spd_server {
 
 namespace spd {
 
-// New detection-plane columns chunk `seq` brings, and the global index of the
-// first of them.
-static int64_t new_cols(const spd_server* S, int64_t seq)
+// New detection-plane columns a chunk brings, and the global index of the
+// first of them.  A fresh chunk (chunk 0, or the first after a gap) has no
+// previous chunk in front: with de-dispersion it yields chunk_cols - max_delay
+// starts from its own first sample on.
+static int64_t new_cols(const spd_server* S, bool fresh)
 {
-    return S->dd && seq == 0 ? S->cfg.chunk_cols - S->dd_delay : S->cfg.chunk_cols;
+    return S->dd && fresh ? S->cfg.chunk_cols - S->dd_delay : S->cfg.chunk_cols;
 }
 
-static int64_t first_col(const spd_server* S, int64_t seq)
+static int64_t first_col(const spd_server* S, int64_t seq, bool fresh)
 {
-    return S->dd && seq > 0 ? seq * S->cfg.chunk_cols - S->dd_delay : seq * S->cfg.chunk_cols;
+    return S->dd && !fresh ? seq * S->cfg.chunk_cols - S->dd_delay : seq * S->cfg.chunk_cols;
 }
 
-// Global start of the chunk's first window (the halo's first column after chunk 0).
-static int64_t chunk_t_offset(const spd_server* S, int64_t seq)
+// Global start of the chunk's first window (the halo's first column when the
+// previous chunk is in front).
+static int64_t chunk_t_offset(const spd_server* S, int64_t seq, bool fresh)
 {
-    return seq == 0 ? 0 : first_col(S, seq) - S->halo;
+    return fresh ? first_col(S, seq, fresh) : first_col(S, seq, fresh) - S->halo;
 }
 
-static spd_plane view_plane(const spd_server* S, const ServeBuf& pb, int64_t seq)
+static spd_plane view_plane(const spd_server* S, const ServeBuf& pb, bool fresh)
 {
     spd_plane x;
     memset(&x, 0, sizeof x);
     const int64_t pitch = S->halo + S->cfg.chunk_cols;
     const char* base = (const char*)pb.plane;
-    if (seq == 0) {                                 // first chunk: no halo in front
+    if (fresh) {                                    // no halo in front
         x.data = base + S->halo * S->esize;
-        x.n_cols = new_cols(S, 0);
+        x.n_cols = new_cols(S, true);
     } else {
         x.data = base;
         x.n_cols = pitch;
@@ -177,12 +181,12 @@ static spd_plane view_plane(const spd_server* S, const ServeBuf& pb, int64_t seq
 // starts dd_halo - dd_delay (< 4) columns early so that its rows stay 4-byte
 // aligned; those first outputs repeat the previous chunk's last ones exactly
 // (whole-count sums) and land on the same columns of the detection halo.
-static spd_status dedisperse_chunk(spd_server* S, ServeBeam& b, ServeBuf& pb, int64_t seq, hipStream_t cs)
+static spd_status dedisperse_chunk(spd_server* S, ServeBeam& b, ServeBuf& pb, bool fresh, hipStream_t cs)
 {
     const int64_t C = S->cfg.chunk_cols, Hf = S->dd_halo, R = S->cfg.n_rows, H = S->halo;
     char* fb = (char*)pb.fb;
     hipError_t e;
-    if (seq > 0 && Hf > 0) {
+    if (!fresh && Hf > 0) {
         e = hipMemcpy2DAsync(fb, (size_t)S->fb_pitch, b.fb_halo, (size_t)Hf, (size_t)Hf, (size_t)R,
                              hipMemcpyDeviceToDevice, cs);
         if (e != hipSuccess) return device_status(e, "filterbank halo in");
@@ -195,9 +199,9 @@ static spd_status dedisperse_chunk(spd_server* S, ServeBeam& b, ServeBuf& pb, in
     f.dtype = SPD_U8;
     f.n_rows = R;
     f.row_stride = S->fb_pitch;
-    f.data = seq == 0 ? fb + Hf : fb;
-    f.n_cols = seq == 0 ? C : Hf + C;
-    const int64_t lead = seq == 0 ? 0 : Hf - S->dd_delay;
+    f.data = fresh ? fb + Hf : fb;
+    f.n_cols = fresh ? C : Hf + C;
+    const int64_t lead = fresh ? 0 : Hf - S->dd_delay;
     float* out = (float*)pb.plane + (H - lead);
     spd_status st = spd_dedisperse(S->dd, &f, out, H + C, cs);
     if (st) return st;
@@ -225,23 +229,23 @@ static spd_status launch_chunk(spd_server* S, ServeReq& r)
     spd_status st;
     // in order within the beam: its previous chunk has left the state and halos
     if ((e = hipStreamWaitEvent(cs, b.ready, 0)) != hipSuccess) return device_status(e, "wait beam");
-    if (r.seq > 0 && H > 0) {
+    if (!r.fresh && H > 0) {
         e = hipMemcpy2DAsync(base, pitch_b, b.halo, (size_t)H * S->esize, (size_t)H * S->esize, (size_t)D,
                              hipMemcpyDeviceToDevice, cs);
         if (e != hipSuccess) return device_status(e, "halo in");
     }
-    const spd_plane x = view_plane(S, pb, r.seq);
+    const spd_plane x = view_plane(S, pb, r.fresh);
     if (S->dd) {
         // de-dispersion needs every channel: one contiguous host-to-device copy
         e = hipMemcpyAsync(pb.stage, r.host, (size_t)R * C * S->in_esize, hipMemcpyHostToDevice, ps);
         if (e != hipSuccess) return device_status(e, "chunk copy-in");
         if ((e = hipEventRecord(pb.h2d[0], ps)) != hipSuccess) return device_status(e, "record h2d");
         if ((e = hipStreamWaitEvent(cs, pb.h2d[0], 0)) != hipSuccess) return device_status(e, "wait h2d");
-        if ((st = dedisperse_chunk(S, b, pb, r.seq, cs))) return st;
-        st = msd_compute(&x, &S->params, r.seq == 0 ? 0 : H, r.seq == 0 ? 0 : 1, b.state, b.stats, b.ws, b.ws_bytes,
+        if ((st = dedisperse_chunk(S, b, pb, r.fresh, cs))) return st;
+        st = msd_compute(&x, &S->params, r.fresh ? 0 : H, r.seq == 0 ? 0 : 1, b.state, b.stats, b.ws, b.ws_bytes,
                          cs);
         if (st) return st;
-        st = boxcar_snr(&x, &S->params, b.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq), pb.d_cand,
+        st = boxcar_snr(&x, &S->params, b.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq, r.fresh), pb.d_cand,
                         S->cfg.cand_capacity, pb.d_count, cs);
         if (st) return st;
     } else {
@@ -251,7 +255,7 @@ static spd_status launch_chunk(spd_server* S, ServeReq& r)
         const MsdLayout m = msd_layout(&x);
         if ((st = check_msd_workspace(&x, m, b.ws, b.ws_bytes))) return st;
         BoxcarPlan bp;
-        if ((st = plan_boxcar(&x, &S->params, b.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq), pb.d_cand,
+        if ((st = plan_boxcar(&x, &S->params, b.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq, r.fresh), pb.d_cand,
                               S->cfg.cand_capacity, pb.d_count, bp)))
             return st;
         if ((e = launch_zero_count(pb.d_count, cs)) != hipSuccess) return device_status(e, "count reset");
@@ -269,14 +273,14 @@ static spd_status launch_chunk(spd_server* S, ServeReq& r)
                                  (size_t)C * S->esize, (size_t)C * S->esize, (size_t)rows, hipMemcpyDeviceToDevice, cs);
             if (e != hipSuccess) return device_status(e, "chunk re-pitch");
             const spd_plane sub = row_slice(&x, r0, rows);
-            if ((st = enqueue_msd(&sub, &S->params, r.seq == 0 ? 0 : H, r.seq != 0, b.state + r0, b.stats + r0,
+            if ((st = enqueue_msd(&sub, &S->params, r.fresh ? 0 : H, r.seq != 0, b.state + r0, b.stats + r0,
                                   (double*)b.ws, m, cs)))
                 return st;
             if ((st = enqueue_boxcar(&sub, b.stats + r0, bp, r0, rows, cs))) return st;
         }
     }
     if (H > 0) {                                    // the last H columns become the beam's halo
-        e = hipMemcpy2DAsync(b.halo, (size_t)H * S->esize, base + new_cols(S, r.seq) * S->esize, pitch_b,
+        e = hipMemcpy2DAsync(b.halo, (size_t)H * S->esize, base + new_cols(S, r.fresh) * S->esize, pitch_b,
                              (size_t)H * S->esize, (size_t)D, hipMemcpyDeviceToDevice, cs);
         if (e != hipSuccess) return device_status(e, "halo out");
     }
@@ -335,10 +339,11 @@ static void worker_loop(spd_server* S)
                 memset(&d.res, 0, sizeof d.res);
                 d.res.beam = r.beam;
                 d.res.seq = r.seq;
+                d.res.flags = r.fresh && r.seq > 0 ? SPD_SERVE_GAP : 0;
                 d.res.submit_s = r.submit_s;
                 d.res.start_s = r.start_s;
                 d.res.done_s = now_s();
-                d.res.t_offset = chunk_t_offset(S, r.seq);
+                d.res.t_offset = chunk_t_offset(S, r.seq, r.fresh);
                 if (q != hipSuccess) {
                     d.res.status = SPD_E_DEVICE;
                 } else {
@@ -601,16 +606,17 @@ spd_status spd_server_submit(spd_server* S, int32_t beam, int64_t seq, const voi
     if (S->fault) return fail(S->fault, "server stopped after an error: %s", S->fault_msg.c_str());
     if (beam < 0 || beam >= (int)S->beams.size()) return fail(SPD_E_INVALID, "beam %d out of range", beam);
     ServeBeam& b = S->beams[beam];
-    if (seq != b.next_submit)
-        return fail(SPD_E_INVALID, "beam %d expects chunk %lld next, got %lld", beam, (long long)b.next_submit,
+    if (seq < b.next_submit)
+        return fail(SPD_E_INVALID, "beam %d expects chunk %lld or later, got %lld", beam, (long long)b.next_submit,
                     (long long)seq);
     ServeReq r;
     r.beam = beam;
     r.seq = seq;
+    r.fresh = seq == 0 || seq != b.next_submit;            // chunk 0, or chunks before it are missing
     r.host = host_chunk;
     r.submit_s = arrival_s > 0.0 ? arrival_s : now_s();
     S->pending.push_back(r);
-    ++b.next_submit;
+    b.next_submit = seq + 1;
     ++S->n_submitted;
     S->cv_work.notify_one();
     return SPD_OK;

@@ -162,7 +162,7 @@ def test_server_backpressure_and_order():
         srv.submit(0, k, streams[0][0][k])
         srv.submit(1, k, streams[1][0][k])
     with pytest.raises(B.SpdError):
-        srv.submit(0, K + 3, streams[0][0][0])   # sequence gap
+        srv.submit(0, 3, streams[0][0][0])       # a chunk number already taken
     res = _drain(srv, 2 * K)
     cnt = srv.counters()
     srv.close()
@@ -359,3 +359,60 @@ def test_server_checkpoint_resume_equals_uninterrupted(dedisp):
     with pytest.raises(B.SpdError):
         other.load_beam(0, saved[0])
     other.close()
+
+
+@pytest.mark.parametrize("dedisp", [False, True])
+def test_server_gap_restarts_the_halo(dedisp):
+    """Chunk 2 of a beam never arrives: chunk 3 is searched without a halo
+    (from its own first sample, like chunk 0), flagged, and placed at sample
+    3*chunk_cols; chunk 4 takes chunk 3's halo again.  The running statistics
+    carry on over the gap.  Every chunk's candidates match the streaming
+    oracle run over the same pieces."""
+    K, nb = 5, 1
+    if dedisp:
+        C_ch, Lc = 24, 2600
+        band = (1450.0, 30.0 / C_ch, 64e-6)
+        kc = oracle.dedisp_channel_factors(C_ch, *band)
+        dm = np.arange(8) * (11.0 / kc[-1])
+        plan = B.DedispPlan(C_ch, *band, dm)
+        md = plan.max_delay
+        fb = synth.filterbank(C_ch, K * Lc, seed=811, device="cuda")
+        delays = oracle.dedisp_delays(dm, kc)
+        for t0 in (Lc + 100, 3 * Lc + 7, 4 * Lc - md - 5):
+            synth.inject_along(fb, delays[5], t0, 6, 30)
+        full = fb.cpu().numpy()
+        chunks = [fb[:, k * Lc:(k + 1) * Lc].contiguous().cpu().pin_memory() for k in range(K)]
+        W, thr, kw, R = list(range(1, 33)), 6.0, dict(dedisp=plan), C_ch
+        # the de-dispersed series of each contiguous piece the server sees
+        pieces = {0: oracle.dedisperse(full[:, 0:2 * Lc], dm, kc), 3: oracle.dedisperse(full[:, 3 * Lc:5 * Lc], dm, kc)}
+        segs = {0: (pieces[0][:, 0:Lc - md], 0), 1: (pieces[0][:, Lc - md:2 * Lc - md], Lc - md),
+                3: (pieces[3][:, 0:Lc - md], 3 * Lc), 4: (pieces[3][:, Lc - md:2 * Lc - md], 4 * Lc - md)}
+    else:
+        R, Lc = 6, 4096
+        chunks = _streams(nb, K, R, Lc, 32, torch.float32, seed=812)[0][0]
+        W, thr, kw = list(range(1, 33)), 5.5, dict(dtype=torch.float32)
+        segs = {k: (chunks[k].double().numpy(), k * Lc) for k in (0, 1, 3, 4)}
+    H = W[-1] - 1
+    p = B.Params(W, thr, "row", "sqrtn", 1.0)
+    print("case: chunk gap dedisp=%s" % dedisp, flush=True)
+    srv = B.Server(nb, R, Lc, p, cand_capacity=8192, **kw)
+    for k in (0, 1, 3, 4):
+        srv.submit(0, k, chunks[k])
+    with pytest.raises(B.SpdError):
+        srv.submit(0, 2, chunks[2])                   # late: a number before the beam's next
+    got = {r["seq"]: (r, c) for r, c in _drain(srv, 4)}
+    srv.close()
+    state, prev, n = None, None, 0
+    for k in (0, 1, 3, 4):
+        seg, start = segs[k]
+        fresh = k in (0, 3)
+        view, ncb, toff = (seg, 0, start) if fresh else (np.concatenate([prev[:, -H:], seg], axis=1), H, start - H)
+        state, st, snr, widx = oracle.stream_step(view, W, new_col_begin=ncb, state=state, sigma_mode="sqrtn")
+        oc = oracle.select(snr, widx, W, thr, t_offset=toff)
+        r, c = got[k]
+        assert r["status"] == 0 and r["t_offset"] == toff, (k, r["t_offset"], toff)
+        assert r["flags"] == (B.SERVE_GAP if k == 3 else 0)
+        C.check_candidates(c, oc, thr, lambda row, t: snr[row, t - toff], C.width_rule(view, W, st, t_offset=toff))
+        n += len(c)
+        prev = seg
+    assert n > 0
