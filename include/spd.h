@@ -74,7 +74,8 @@ typedef enum {
     SPD_E_INVALID = 1,      /* bad argument (message in spd_last_error)         */
     SPD_E_UNSUPPORTED = 2,  /* valid request the library does not handle         */
     SPD_E_NOMEM = 3,        /* workspace too small / allocation failed          */
-    SPD_E_DEVICE = 4,       /* the HIP runtime reported an error                */
+    SPD_E_DEVICE = 4,       /* the HIP runtime reported an error, or serving
+                               work missed its deadline                         */
     SPD_E_AGAIN = 5         /* serving: queue full or nothing ready (retry)      */
 } spd_status;
 
@@ -479,6 +480,9 @@ typedef struct {
     int32_t slots_per_beam;    /* chunks of one beam on the device at once, 1..8 (2: the next copy overlaps work) */
     int32_t n_streams;         /* compute streams (each with a copy stream), 0..8; 0 = 2 */
     int64_t hbm_budget_bytes;  /* 0, or the most device memory the server may take; it sets the pool's buffers */
+    double deadline_s;         /* 0, or the longest a chunk may run on the device after admission: a chunk
+                                * still running later stops the server (SPD_E_DEVICE from submit and poll;
+                                * the work itself cannot be withdrawn from the device) */
 } spd_server_config;
 
 typedef struct {

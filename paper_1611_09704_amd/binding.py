@@ -67,7 +67,7 @@ class SpdServerConfig(ctypes.Structure):
     _fields_ = [("n_beams", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n_rows", ctypes.c_int64),
                 ("chunk_cols", ctypes.c_int64), ("cand_capacity", ctypes.c_int64),
                 ("slots_per_beam", ctypes.c_int32), ("n_streams", ctypes.c_int32),
-                ("hbm_budget_bytes", ctypes.c_int64)]
+                ("hbm_budget_bytes", ctypes.c_int64), ("deadline_s", ctypes.c_double)]
 
 
 class SpdServerResult(ctypes.Structure):
@@ -600,12 +600,13 @@ class Server:
 
     def __init__(self, n_beams: int, n_rows: int, chunk_cols: int, params: Params, dtype=torch.float16,
                  cand_capacity: int = 1 << 16, slots_per_beam: int = 2, hbm_budget_bytes: int = 0,
-                 dedisp: Optional["DedispPlan"] = None, n_streams: int = 0):
+                 dedisp: Optional["DedispPlan"] = None, n_streams: int = 0, deadline_s: float = 0.0):
         """With ``dedisp`` (a DedispPlan, kept alive by the server) the beams
         stream uint8 filterbank chunks [n_chan][chunk_cols], de-dispersed on
         the device in front of the detection stream.  ``hbm_budget_bytes``
         sizes the shared pool of chunk buffers; ``n_streams`` compute streams
-        (0: 2) each with a copy stream carry the work."""
+        (0: 2) each with a copy stream carry the work; a chunk still on the
+        device ``deadline_s`` after admission (0: no deadline) stops the server."""
         lib = load()
         if dedisp is not None:
             dtype = torch.uint8
@@ -613,7 +614,7 @@ class Server:
         self.params = params
         self.dedisp = dedisp
         self.cfg = SpdServerConfig(n_beams, dt, n_rows, chunk_cols, cand_capacity, slots_per_beam, n_streams,
-                                   hbm_budget_bytes)
+                                   hbm_budget_bytes, float(deadline_s))
         self.cap = cand_capacity
         self._buf = np.empty(cand_capacity, dtype=CANDIDATE_DTYPE)
         self._keep = {}

@@ -39,10 +39,12 @@
 #include <condition_variable>
 #include <deque>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
 #include "spd_abi_internal.h"
+#include "spd_admit.h"
 #include "spd_kernels.h"
 
 namespace spd {
@@ -298,34 +300,29 @@ static void worker_loop(spd_server* S)
 {
     (void)hipSetDevice(S->device);
     std::vector<char> blocked(S->beams.size());
+    std::vector<int> on_device(S->beams.size());
     std::unique_lock<std::mutex> lk(S->mu);
     while (!S->stop) {
         bool progress = false;
         // admission: arrival order across beams, chunk order within a beam, while a
         // pool buffer is free and the beam has fewer than slots_per_beam chunks in flight
-        std::fill(blocked.begin(), blocked.end(), 0);
-        for (auto it = S->pending.begin(); it != S->pending.end() && !S->free_bufs.empty() && S->fault == SPD_OK;) {
-            ServeBeam& b = S->beams[it->beam];
-            if (blocked[it->beam] || (int)b.inflight.size() >= S->cfg.slots_per_beam) {
-                blocked[it->beam] = 1;
-                ++it;
-                continue;
-            }
-            ServeReq r = *it;
-            it = S->pending.erase(it);
-            r.buf = S->free_bufs.back();
-            S->free_bufs.pop_back();
-            r.start_s = now_s();
-            const spd_status st = launch_chunk(S, r);
-            if (st) {
-                S->fault = st;
-                S->fault_msg = spd_last_error();
-                S->free_bufs.push_back(r.buf);
-                break;
-            }
-            b.inflight.push_back(r);
-            ++S->n_admitted;
-            progress = true;
+        if (S->fault == SPD_OK) {
+            for (size_t bi = 0; bi < S->beams.size(); ++bi) on_device[bi] = (int)S->beams[bi].inflight.size();
+            const int n = admit_pending(S->pending, S->free_bufs, on_device, S->cfg.slots_per_beam, blocked,
+                                        [S](ServeReq& r, int buf) {
+                                            r.buf = buf;
+                                            r.start_s = now_s();
+                                            const spd_status st = launch_chunk(S, r);
+                                            if (st) {
+                                                S->fault = st;
+                                                S->fault_msg = spd_last_error();
+                                                return false;
+                                            }
+                                            S->beams[r.beam].inflight.push_back(r);
+                                            ++S->n_admitted;
+                                            return true;
+                                        });
+            progress = progress || n > 0;
         }
         // completions: the oldest in-flight chunk of each beam; its buffer returns to the pool
         for (size_t bi = 0; bi < S->beams.size(); ++bi) {
@@ -334,7 +331,18 @@ static void worker_loop(spd_server* S)
                 ServeReq& r = b.inflight.front();
                 const ServeBuf& pb = S->pool[r.buf];
                 const hipError_t q = hipEventQuery(pb.done);
-                if (q == hipErrorNotReady) break;
+                if (q == hipErrorNotReady) {
+                    if (S->fault == SPD_OK && overdue(now_s(), r.start_s, S->cfg.deadline_s)) {
+                        // the work cannot be withdrawn from the device: stop admitting and report it
+                        S->fault = SPD_E_DEVICE;
+                        S->fault_msg = "chunk " + std::to_string((long long)r.seq) + " of beam " +
+                                       std::to_string(r.beam) + " still running " +
+                                       std::to_string(now_s() - r.start_s) + " s after admission (deadline " +
+                                       std::to_string(S->cfg.deadline_s) + " s)";
+                        S->cv_done.notify_all();
+                    }
+                    break;
+                }
                 ServeDone d;
                 memset(&d.res, 0, sizeof d.res);
                 d.res.beam = r.beam;
@@ -496,6 +504,7 @@ static spd_status create_server(const spd_server_config* cfg, const spd_params* 
     if (cfg->n_streams < 0 || cfg->n_streams > kServeMaxStreams)
         return fail(SPD_E_INVALID, "n_streams outside [0, %d]", kServeMaxStreams);
     if (cfg->hbm_budget_bytes < 0) return fail(SPD_E_INVALID, "hbm_budget_bytes < 0");
+    if (!(cfg->deadline_s >= 0.0) || cfg->deadline_s > 1e9) return fail(SPD_E_INVALID, "deadline_s must be in [0, 1e9]");
     int32_t n_chan = 0, n_dm = 0, max_delay = 0;
     int plan_device = 0, device = 0;
     int64_t dd_halo = 0, fb_pitch = 0;

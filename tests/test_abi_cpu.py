@@ -240,7 +240,8 @@ def test_server_validation(lib):
     for c, code, msg in [(cfg(n_beams=0), 1, "n_beams"), (cfg(dtype=B.SPD_U8), 2, "F32 or F16"),
                          (cfg(chunk_cols=8), 1, "chunk_cols"), (cfg(slots_per_beam=0), 1, "slots_per_beam"),
                          (cfg(cand_capacity=0), 1, "cand_capacity"), (cfg(hbm_budget_bytes=1000), 3, "budget"),
-                         (cfg(n_streams=9), 1, "n_streams"), (cfg(hbm_budget_bytes=-1), 1, "budget")]:
+                         (cfg(n_streams=9), 1, "n_streams"), (cfg(hbm_budget_bytes=-1), 1, "budget"),
+                         (cfg(deadline_s=-1.0), 1, "deadline_s"), (cfg(deadline_s=float("nan")), 1, "deadline_s")]:
         assert lib.spd_server_create(ctypes.byref(c), ctypes.byref(p.c), ctypes.byref(out)) == code
         assert out.value is None and msg in _err(lib)
     pp = B.Params([1, 2], 5.0, scope="plane")

@@ -416,3 +416,30 @@ def test_server_gap_restarts_the_halo(dedisp):
         n += len(c)
         prev = seg
     assert n > 0
+
+
+def test_server_deadline_stops_the_server():
+    """A chunk still on the device past the deadline stops the server: with a
+    1 us deadline (forced from the host; the work itself runs normally) poll
+    and submit report SPD_E_DEVICE naming the deadline, and close still waits
+    for the device work and returns."""
+    R, Lc = 256, 65536
+    W = list(range(1, 65))
+    chunks, _ = synth.stream_chunks(2, R, Lc, seed=9, device="cuda", wmax=64, dtype=torch.float32)
+    host = [c.cpu().pin_memory() for c in chunks]
+    srv = B.Server(1, R, Lc, B.Params(W, 6.0), dtype=torch.float32, cand_capacity=4096, deadline_s=1e-6)
+    err, delivered = None, 0
+    for k in range(len(host)):
+        try:
+            srv.submit(0, k, host[k])
+            for _ in range(20):
+                if srv.poll(wait_ms=200) is not None:
+                    delivered += 1
+        except B.SpdError as e:
+            err = e
+            break
+    assert err is not None and err.status == 4 and "deadline" in str(err), err
+    with pytest.raises(B.SpdError, match="deadline"):
+        srv.submit(0, len(host), host[0])
+    srv.close()
+    assert delivered <= len(host)
