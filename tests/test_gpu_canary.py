@@ -99,3 +99,84 @@ def test_outputs_stay_in_bounds(case, dtype):
         assert torch.equal(snr_full[:R, front:front + nout], snr)
         assert torch.equal(widx_full[:R, front:front + nout], widx)
         assert keys == ref
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16", "u8"])
+def test_statistics_stay_in_bounds(dtype):
+    """msd_compute writes units x 5 doubles: a canary row after them keeps its
+    value (row and plane scope, sqrt(N) and AUTO sigma_N)."""
+    x, scale, zero = _plane(5, 20011, dtype, seed=77)
+    for scope in ("row", "plane"):
+        for mode in ("sqrtn", "auto"):
+            p = B.Params(SKA, 6.0, scope, mode, 1.0)
+            units = p.n_units(x.shape[0])
+            full = torch.full((units + 1, B.STATS_FIELDS), -3.5, dtype=torch.float64, device=DEV)
+            B.msd_compute(x, p, scale=scale, zero=zero, stats=full[:units])
+            ref = B.msd_compute(x, p, scale=scale, zero=zero)
+            torch.cuda.synchronize()
+            assert torch.all(full[units:] == -3.5), "statistics written past the last unit"
+            assert torch.equal(full[:units], ref)
+
+
+def _raw_tail_untouched(full, cap, fill):
+    return bool(torch.all(full[cap:] == fill).item())
+
+
+def test_candidate_lists_stay_in_bounds():
+    """Every producer of a candidate list (fused threshold of boxcar_snr and of
+    the decimated search, select_candidates, cluster_candidates) writes at most
+    its capacity: records past it in a larger buffer keep their bytes, and the
+    count still reports the total."""
+    pl = synth.make_plane(6, 30011, seed=88, device=DEV, n_pulses=12, pulse_widths=range(1, 65), snr_range=(8, 30))
+    x = pl.x
+    p = B.Params(SKA, 2.5)
+    stats = B.msd_compute(x, p)
+    nout = x.shape[1] - p.nmax + 1
+    snr = torch.empty((6, nout), device=DEV)
+    widx = torch.empty((6, nout), dtype=torch.uint8, device=DEV)
+    big = B.new_candidates(1 << 20, DEV)
+    cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
+    B.boxcar_snr(x, p, stats, snr=snr, widx=widx, cand=big, cand_count=cnt)
+    torch.cuda.synchronize()
+    total = int(cnt.item())
+    assert 1000 < total < big.shape[0]
+    cap = 97
+    for name in ("boxcar", "select", "dit", "cluster"):
+        full = torch.full((cap + 64, big.shape[1]), 0xA5, dtype=torch.uint8, device=DEV)
+        c = torch.zeros(1, dtype=torch.int64, device=DEV)
+        if name == "boxcar":
+            B.boxcar_snr(x, p, stats, cand=full[:cap], cand_count=c)
+        elif name == "select":
+            B.select_candidates(snr, widx, p, cand=full[:cap], cand_count=c)
+        elif name == "dit":
+            pd = B.dit_params(3, 2.5)
+            sd = B.msd_compute(x, pd)
+            B.boxcar_snr_dit(x, pd, 3, sd, cand=full[:cap], cand_count=c)
+        else:
+            B.cluster_candidates(snr, big, cnt, 2, 8, peaks=full[:cap], peak_count=c)
+        torch.cuda.synchronize()
+        n = int(c.item())
+        print("case: %s list capacity %d, count %d" % (name, cap, n), flush=True)
+        assert n > cap, name
+        if name in ("boxcar", "select"):
+            assert n == total, name
+        assert _raw_tail_untouched(full, cap, 0xA5), "%s wrote past its capacity" % name
+
+
+def test_dedisp_output_stays_in_bounds():
+    """spd_dedisperse writes n_dm rows of n_samp - max_delay columns: canaries
+    before and after each row's outputs and a row after the last keep their
+    values, and the outputs equal the same call into a tight buffer."""
+    band = (1550.0, 300.0 / 256, 64e-6)
+    dm = [0.0, 3.0, 7.5, 12.0, 40.0]
+    fb = synth.filterbank(256, 3001, seed=5, device=DEV)
+    plan = B.DedispPlan(256, *band, dm)
+    n_out = fb.shape[1] - plan.max_delay
+    front, back = 3, 5
+    full = torch.full((len(dm) + 1, front + n_out + back), -9.0, device=DEV)
+    plan.run(fb, out=full[:len(dm), front:])
+    ref = plan.run(fb)
+    torch.cuda.synchronize()
+    assert torch.all(full[:len(dm), :front] == -9.0) and torch.all(full[:len(dm), front + n_out:] == -9.0)
+    assert torch.all(full[len(dm):] == -9.0)
+    assert torch.equal(full[:len(dm), front:front + n_out], ref)
