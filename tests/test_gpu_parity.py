@@ -288,47 +288,53 @@ def test_ska_full_size_sampled_rows():
     torch.cuda.empty_cache()
 
 
-def test_ska_full_size_bench_layout_both_lists():
+def test_ska_full_size_bench_layout_all_forms():
     """The 4,096 x 2^20 SKA-like plane in exactly the launch configuration the
     benchmark times: msd_compute then boxcar_snr into output rows padded to
     64-byte multiples (the vector-store path), with the fused candidate list,
-    for the 136-width list and for widths 1..16 (the streaming form); sampled
-    rows against the oracle, and the rows' candidates against the oracle's."""
+    for the 136-width list and for widths 1..16 (the streaming form), with the
+    plane stored as FP32, FP16 and U8 (per-row zero at the row mean, as the
+    benchmark's precision leg stores it); sampled rows against the oracle on
+    the stored values, and those rows' candidates against the oracle's."""
     cfg = synth.ska(device=DEV)
     pl = cfg["plane"]
-    x = pl.x
-    R, L = x.shape
+    xs = pl.x
+    R, L = xs.shape
     print("ska bench layout: generated", flush=True)
     rng = np.random.default_rng(123)
     rows = sorted(set(pl.bright_rows[:4]) | {p.row for p in pl.pulses[8:14]} |
                   set(rng.choice(R, 4, replace=False).tolist()))
-    x64 = x[rows].cpu().to(torch.float64).numpy()
+    q, sc, zr = synth.quantize_u8(xs, pl.row_sigma, row_mu=pl.row_mu)
+    forms = {"f32": (xs, None, None), "f16": (synth.quantize_f16(xs), None, None), "u8": (q, sc, zr)}
     flat_snr = torch.empty(R * L, dtype=torch.float32, device=DEV)
     flat_widx = torch.empty(R * L, dtype=torch.uint8, device=DEV)
-    for W in (cfg["widths"], list(range(1, 17))):
-        p = B.Params(W, cfg["threshold"], "row", "auto", 1.0)
-        nout = L - p.nmax + 1
-        po = (nout + 15) // 16 * 16
-        snr = flat_snr[:R * po].view(R, po)[:, :nout]
-        widx = flat_widx[:R * po].view(R, po)[:, :nout]
-        cand = B.new_candidates(1 << 21, DEV)
-        cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
-        stats = B.msd_compute(x, p)
-        B.boxcar_snr(x, p, stats, snr=snr, widx=widx, cand=cand, cand_count=cnt)
-        torch.cuda.synchronize()
-        n = int(cnt.item())
-        assert n <= cand.shape[0]
-        _, ost, osnr, owidx = oracle.stream_step(x64, W, sigma_mode="auto", kappa=1.0)
-        C.check_stats(stats[rows].cpu().numpy(), ost, True)
-        worst, nmis = C.check_snr_widx(x64, W, snr[rows].cpu().numpy(), widx[rows].cpu().numpy(), osnr, owidx,
-                                       ost, rows=rows)
-        oc = oracle.select(osnr, owidx, W, cfg["threshold"])
-        oc["row"] = np.asarray(rows)[oc["row"]]
-        rset = set(rows)
-        gc = np.array([c for c in B.candidates_to_numpy(cand, n) if int(c["row"]) in rset], dtype=B.CANDIDATE_DTYPE)
-        C.check_candidates(gc, oc, cfg["threshold"], lambda r, t: osnr[rows.index(r), t],
-                           C.width_rule(x64, W, ost, rows=rows))
-        print("ska bench layout |W|=%d: rows=%d max|dSNR|=%.3g width mismatches=%d candidates=%d" %
-              (len(W), len(rows), worst, nmis, n), flush=True)
-    del x, flat_snr, flat_widx
+    for name, (x, s_, z_) in forms.items():
+        x64 = C.plane_f64(x[rows], None if s_ is None else s_[rows], None if z_ is None else z_[rows])
+        for W in (cfg["widths"], list(range(1, 17))):
+            p = B.Params(W, cfg["threshold"], "row", "auto", 1.0)
+            nout = L - p.nmax + 1
+            po = (nout + 15) // 16 * 16
+            snr = flat_snr[:R * po].view(R, po)[:, :nout]
+            widx = flat_widx[:R * po].view(R, po)[:, :nout]
+            cand = B.new_candidates(1 << 21, DEV)
+            cnt = torch.zeros(1, dtype=torch.int64, device=DEV)
+            stats = B.msd_compute(x, p, scale=s_, zero=z_)
+            B.boxcar_snr(x, p, stats, scale=s_, zero=z_, snr=snr, widx=widx, cand=cand, cand_count=cnt)
+            torch.cuda.synchronize()
+            n = int(cnt.item())
+            assert n <= cand.shape[0]
+            _, ost, osnr, owidx = oracle.stream_step(x64, W, sigma_mode="auto", kappa=1.0)
+            C.check_stats(stats[rows].cpu().numpy(), ost, True)
+            worst, nmis = C.check_snr_widx(x64, W, snr[rows].cpu().numpy(), widx[rows].cpu().numpy(), osnr,
+                                           owidx, ost, rows=rows)
+            oc = oracle.select(osnr, owidx, W, cfg["threshold"])
+            oc["row"] = np.asarray(rows)[oc["row"]]
+            rset = set(rows)
+            gc = np.array([c for c in B.candidates_to_numpy(cand, n) if int(c["row"]) in rset],
+                          dtype=B.CANDIDATE_DTYPE)
+            C.check_candidates(gc, oc, cfg["threshold"], lambda r, t: osnr[rows.index(r), t],
+                               C.width_rule(x64, W, ost, rows=rows))
+            print("ska bench layout %s |W|=%d: rows=%d max|dSNR|=%.3g width mismatches=%d candidates=%d" %
+                  (name, len(W), len(rows), worst, nmis, n), flush=True)
+    del xs, forms, q, flat_snr, flat_widx
     torch.cuda.empty_cache()
