@@ -968,18 +968,22 @@ def precision_speed(dev, B, synth, sk, steps, warmup):
         for name, (x, s_, z_) in planes.items():
             stats = torch.empty((R, B.STATS_FIELDS), dtype=torch.float64, device=dev)
             ws = torch.empty(B.workspace_bytes(x, p, s_, z_), dtype=torch.uint8, device=dev)
-            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            evm = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
             for rep in range(warmup + steps):
-                if rep == warmup:
+                k = rep - warmup
+                if k == 0:
                     ev[0].record()
+                if k >= 0:
+                    evm[k][0].record()
                 B.msd_compute(x, p, scale=s_, zero=z_, stats=stats, workspace=ws)
-                if rep == warmup:
-                    ev[1].record()
+                if k >= 0:
+                    evm[k][1].record()
                 B.boxcar_snr(x, p, stats, scale=s_, zero=z_, snr=snr, widx=widx, cand=cand, cand_count=count)
-            ev[2].record()
+            ev[1].record()
             torch.cuda.synchronize()
-            t_msd = ev[0].elapsed_time(ev[1])
-            t_all = ev[0].elapsed_time(ev[2]) / steps
+            t_msd = sum(a.elapsed_time(b) for a, b in evm) / steps      # mean over the timed steps
+            t_all = ev[0].elapsed_time(ev[1]) / steps
             speed["%s/%s" % (wname, name)] = {"msd_ms": round(t_msd, 4), "step_ms": round(t_all, 3),
                                               "GSamples_per_s": round(R * L / t_all / 1e6, 3),
                                               "msd_GB_per_s": round(R * L * x.element_size() / t_msd / 1e6, 1)}
