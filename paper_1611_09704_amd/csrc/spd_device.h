@@ -475,11 +475,12 @@ __device__ __forceinline__ void wave_sync()
 // run and FP64 across runs, and the block's S = sum d^2 - (sum d)^2/n is
 // formed in FP64.
 
-constexpr int kRun = 16;                // consecutive starts per lane
-constexpr int kRunStep = 64 * kRun;     // starts per wave step (U8); wave spans are multiples of 4 steps
-// Steps per iteration of the U8 walk, their loads in flight together (one for
-// F32 / F16, whose wider windows fill the registers).
-constexpr int kU8Steps = 2;
+constexpr int kRun = 16;                // consecutive starts per lane (F16; 8 for F32)
+// The U8 walk: longer runs (its per-run fold, a wave scan and 64-bit sums, is
+// then paid once per 32 starts), one step per iteration; wave spans are
+// multiples of its step.
+constexpr int kRunU8 = 32;
+constexpr int kRunStepU8 = 64 * kRunU8;
 
 // 4*NDW bytes from `p` with aligned dword loads.  RA (realign): p may sit off a
 // 4-byte boundary by sh = p & 3 (the same for every lane of the wave); one more
@@ -694,7 +695,8 @@ __device__ void msd_block_xy_f(const PlaneArg& pl, int64_t r, int64_t b, int64_t
 }
 
 // One U8 run's widest-boxcar sums in integers, fed start by start (as RunAcc):
-// |c_k| <= 255*kRun, so c_k^2 and the run's sums fit in int32.
+// |c_k| <= 255*k for k <= kRunU8, so c_k^2 and the run's sums (sum of c_k^2 at
+// most 255^2 * 11440 < 2^30) fit in int32.
 struct RunAccI {
     int c = 0, sc = 0, qc = 0;
     template <bool ALL>
@@ -712,9 +714,10 @@ struct RunAccI {
     }
 };
 
-// Folds a U8 step into the lane's y sums: y0 and the carry are at most
-// 255*nmax < 2^21; a lane's sum of y over its <= 16 runs (a block spans at most
-// 65536 columns, 16384 per wave) stays below 2^31; the sum of y^2 is 64-bit.
+// Folds a U8 run into the lane's y sums: y0 and the carry are at most
+// 255*nmax < 2^21; a lane's sum of y over its <= 8 runs of 32 starts (a block
+// spans at most 65536 columns, 16384 per wave) stays below 2^31; the sum of y^2
+// is 64-bit.
 __device__ __forceinline__ void u8_fold(const RunAccI& ra, int ny, uint32_t& sy1, long long& sy2, int& carry)
 {
     const int inc = wave_inclusive_scan_i(ra.c);
@@ -732,48 +735,38 @@ __device__ __forceinline__ void walk_u8(const uint8_t* row, int64_t w0, int64_t 
                                         int64_t ncols, int32_t nmax, uint32_t& sx1, uint32_t& sx2, uint32_t& sy1,
                                         long long& sy2, int& carry)
 {
-    constexpr int kRunSteps = kU8Steps, SPAN = kRunSteps * kRunStep, NW = kRun / 4;
+    constexpr int SPAN = kRunStepU8, NW = kRunU8 / 4;
     const int lane = threadIdx.x & 63;
     const uint32_t sho = (uint32_t)((uintptr_t)row & 3), shn = (uint32_t)(((uintptr_t)row + nmax) & 3);
     for (int64_t u = w0; u < w1; u += SPAN) {
+        const int64_t t0 = u + kRunU8 * lane;
+        RunAccI ra;
         if (u >= xlo && u + SPAN <= min(w1, yhi) && u + SPAN + nmax + 4 <= ncols) {
-            uint32_t wo[kRunSteps][NW], wn[kRunSteps][NW];
+            uint32_t wo[NW], wn[NW];
+            load_window<NW, RAO>(row + t0, sho, wo);
+            load_window<NW, RAN>(row + t0 + nmax, shn, wn);
 #pragma unroll
-            for (int j = 0; j < kRunSteps; ++j) {
-                const int64_t t0 = u + j * kRunStep + kRun * lane;
-                load_window<NW, RAO>(row + t0, sho, wo[j]);
-                load_window<NW, RAN>(row + t0 + nmax, shn, wn[j]);
+            for (int i = 0; i < NW; ++i) {
+                u8_word(wo[i], sx1, sx2);
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    ra.add<true>((int)((wo[i] >> (8 * k)) & 255u), (int)((wn[i] >> (8 * k)) & 255u), true);
             }
-#pragma unroll
-            for (int j = 0; j < kRunSteps; ++j) {
-                RunAccI ra;
-#pragma unroll
-                for (int i = 0; i < NW; ++i) {
-                    u8_word(wo[j][i], sx1, sx2);
-#pragma unroll
-                    for (int k = 0; k < 4; ++k)
-                        ra.add<true>((int)((wo[j][i] >> (8 * k)) & 255u), (int)((wn[j][i] >> (8 * k)) & 255u), true);
-                }
-                u8_fold(ra, kRun, sy1, sy2, carry);
-            }
+            u8_fold(ra, kRunU8, sy1, sy2, carry);
         } else {
-            for (int j = 0; j < kRunSteps && u + j * kRunStep < w1; ++j) {
-                const int64_t us = u + j * kRunStep, t0 = us + kRun * lane;
-                const bool with_y = us < yhi;
-                RunAccI ra;
+            const bool with_y = u < yhi;
 #pragma unroll 1
-                for (int k = 0; k < kRun; ++k) {
-                    const int64_t c = t0 + k;
-                    const uint32_t q = c < ncols ? (uint32_t)row[c] : 0u;
-                    const uint32_t qn = with_y && c + nmax < ncols ? (uint32_t)row[c + nmax] : 0u;
-                    if (c >= xlo && c < w1) {
-                        sx1 += q;
-                        sx2 += q * q;
-                    }
-                    ra.add<false>((int)q, (int)qn, c < yhi);
+            for (int k = 0; k < kRunU8; ++k) {
+                const int64_t c = t0 + k;
+                const uint32_t q = c < ncols ? (uint32_t)row[c] : 0u;
+                const uint32_t qn = with_y && c + nmax < ncols ? (uint32_t)row[c + nmax] : 0u;
+                if (c >= xlo && c < w1) {
+                    sx1 += q;
+                    sx2 += q * q;
                 }
-                if (with_y) u8_fold(ra, (int)max(min(yhi - t0, (int64_t)kRun), (int64_t)0), sy1, sy2, carry);
+                ra.add<false>((int)q, (int)qn, c < yhi);
             }
+            if (with_y) u8_fold(ra, (int)max(min(yhi - t0, (int64_t)kRunU8), (int64_t)0), sy1, sy2, carry);
         }
     }
 }
