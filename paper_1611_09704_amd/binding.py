@@ -613,6 +613,8 @@ class Server:
         dt = {torch.float32: SPD_F32, torch.float16: SPD_F16, torch.uint8: SPD_U8}[dtype]
         self.params = params
         self.dedisp = dedisp
+        self.dtype = dtype
+        self.shape = (int(n_rows), int(chunk_cols))
         self.cfg = SpdServerConfig(n_beams, dt, n_rows, chunk_cols, cand_capacity, slots_per_beam, n_streams,
                                    hbm_budget_bytes, float(deadline_s))
         self.cap = cand_capacity
@@ -630,9 +632,14 @@ class Server:
         return load().spd_server_device_bytes(ctypes.byref(self.cfg), ctypes.byref(self.params.c))
 
     def submit(self, beam: int, seq: int, chunk: torch.Tensor, arrival_s: float = 0.0) -> None:
-        """chunk: a host tensor [n_rows, chunk_cols], kept alive until its result is polled."""
+        """chunk: a host tensor [n_rows, chunk_cols] of the server's dtype, kept
+        alive until its result is polled.  The C call takes a bare pointer, so a
+        malformed chunk is refused here, before anything is enqueued."""
         if chunk.is_cuda or not chunk.is_contiguous():
             raise ValueError("chunk must be a contiguous host tensor (pinned for speed)")
+        if tuple(chunk.shape) != self.shape or chunk.dtype != self.dtype:
+            raise ValueError("chunk must be %s %s, got %s %s" % (self.dtype, list(self.shape), chunk.dtype,
+                                                                 list(chunk.shape)))
         _check(load().spd_server_submit(self._h, int(beam), int(seq), chunk.data_ptr(), float(arrival_s)))
         self._keep[(beam, seq)] = chunk      # until polled (a refused submit keeps nothing)
 

@@ -163,6 +163,10 @@ def test_server_backpressure_and_order():
         srv.submit(1, k, streams[1][0][k])
     with pytest.raises(B.SpdError):
         srv.submit(0, 3, streams[0][0][0])       # a chunk number already taken
+    with pytest.raises(ValueError):              # malformed chunks are refused before the C call
+        srv.submit(0, K, streams[0][0][0][:, :-1].contiguous())
+    with pytest.raises(ValueError):
+        srv.submit(0, K, streams[0][0][0].to(torch.float16))
     res = _drain(srv, 2 * K)
     cnt = srv.counters()
     srv.close()
