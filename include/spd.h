@@ -483,11 +483,17 @@ typedef struct {
     double deadline_s;         /* 0, or the longest a chunk may run on the device after admission: a chunk
                                 * still running later stops the server (SPD_E_DEVICE from submit and poll;
                                 * the work itself cannot be withdrawn from the device) */
+    int64_t overflow_capacity; /* 0, or > cand_capacity: a chunk that finds more than cand_capacity
+                                * candidates is searched again, from the plane and statistics still in
+                                * its buffer, into one list of this capacity (allocated at creation and
+                                * counted in the device bytes), and all its candidates are delivered
+                                * (flag SPD_SERVE_RERUN) */
 } spd_server_config;
 
 typedef struct {
     int32_t beam;
-    int32_t status;            /* SPD_OK, SPD_E_NOMEM (candidates beyond capacity), SPD_E_DEVICE */
+    int32_t status;            /* SPD_OK, SPD_E_NOMEM (candidates beyond the capacity, and beyond
+                                * overflow_capacity if set), SPD_E_DEVICE */
     int64_t seq;               /* chunk number within the beam */
     int64_t t_offset;          /* global sample index of this chunk's first window start */
     int64_t n_cands;           /* candidates found in the chunk */
@@ -505,6 +511,9 @@ typedef struct {
  * de-dispersion in front it yields chunk_cols - max_delay starts, like chunk
  * 0).  The running statistics carry on across the gap.                     */
 #define SPD_SERVE_GAP 1
+/* spd_server_result.flags: the chunk overflowed cand_capacity and was searched
+ * again into the overflow list (spd_server_config.overflow_capacity).       */
+#define SPD_SERVE_RERUN 2
 
 /* Device bytes a server with this configuration allocates (0 if invalid, or
  * if the budget cannot hold the beams' state plus one chunk buffer).  Host

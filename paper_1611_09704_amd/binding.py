@@ -24,6 +24,7 @@ SCOPES = {"row": 0, "plane": 1}
 SIGMA_MODES = {"sqrtn": 0, "linear": 1, "auto": 2, "linear_literal": 3}
 FLAG_ZERO_VAR, FLAG_LINEAR = 1, 2
 SERVE_GAP = 1             # spd_server_result.flags: the chunk followed missing chunks
+SERVE_RERUN = 2           # spd_server_result.flags: the chunk overflowed and was searched again
 STATUS = {0: "SPD_OK", 1: "SPD_E_INVALID", 2: "SPD_E_UNSUPPORTED", 3: "SPD_E_NOMEM",
           4: "SPD_E_DEVICE", 5: "SPD_E_AGAIN"}
 
@@ -67,7 +68,8 @@ class SpdServerConfig(ctypes.Structure):
     _fields_ = [("n_beams", ctypes.c_int32), ("dtype", ctypes.c_int32), ("n_rows", ctypes.c_int64),
                 ("chunk_cols", ctypes.c_int64), ("cand_capacity", ctypes.c_int64),
                 ("slots_per_beam", ctypes.c_int32), ("n_streams", ctypes.c_int32),
-                ("hbm_budget_bytes", ctypes.c_int64), ("deadline_s", ctypes.c_double)]
+                ("hbm_budget_bytes", ctypes.c_int64), ("deadline_s", ctypes.c_double),
+                ("overflow_capacity", ctypes.c_int64)]
 
 
 class SpdServerResult(ctypes.Structure):
@@ -600,13 +602,16 @@ class Server:
 
     def __init__(self, n_beams: int, n_rows: int, chunk_cols: int, params: Params, dtype=torch.float16,
                  cand_capacity: int = 1 << 16, slots_per_beam: int = 2, hbm_budget_bytes: int = 0,
-                 dedisp: Optional["DedispPlan"] = None, n_streams: int = 0, deadline_s: float = 0.0):
+                 dedisp: Optional["DedispPlan"] = None, n_streams: int = 0, deadline_s: float = 0.0,
+                 overflow_capacity: int = 0):
         """With ``dedisp`` (a DedispPlan, kept alive by the server) the beams
         stream uint8 filterbank chunks [n_chan][chunk_cols], de-dispersed on
         the device in front of the detection stream.  ``hbm_budget_bytes``
         sizes the shared pool of chunk buffers; ``n_streams`` compute streams
         (0: 2) each with a copy stream carry the work; a chunk still on the
-        device ``deadline_s`` after admission (0: no deadline) stops the server."""
+        device ``deadline_s`` after admission (0: no deadline) stops the server;
+        with ``overflow_capacity`` (> cand_capacity) a chunk past cand_capacity
+        is searched again and all its candidates (up to that many) delivered."""
         lib = load()
         if dedisp is not None:
             dtype = torch.uint8
@@ -616,9 +621,9 @@ class Server:
         self.dtype = dtype
         self.shape = (int(n_rows), int(chunk_cols))
         self.cfg = SpdServerConfig(n_beams, dt, n_rows, chunk_cols, cand_capacity, slots_per_beam, n_streams,
-                                   hbm_budget_bytes, float(deadline_s))
-        self.cap = cand_capacity
-        self._buf = np.empty(cand_capacity, dtype=CANDIDATE_DTYPE)
+                                   hbm_budget_bytes, float(deadline_s), int(overflow_capacity))
+        self.cap = max(int(cand_capacity), int(overflow_capacity))
+        self._buf = np.empty(self.cap, dtype=CANDIDATE_DTYPE)
         self._keep = {}
         h = ctypes.c_void_p()
         if dedisp is None:

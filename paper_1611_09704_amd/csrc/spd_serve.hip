@@ -81,6 +81,7 @@ struct ServeBuf {
     void* plane = nullptr;                 // device [det_rows][H + C]: halo, then the chunk's columns
     void* stage = nullptr;                 // device [n_rows][C], the contiguous copy-in target
     void* fb = nullptr;                    // device [n_chan][fb_pitch] filterbank (de-dispersion)
+    spd_row_stats* stats = nullptr;        // device [det_rows]: the statistics this chunk was searched with
     spd_candidate* d_cand = nullptr;
     int64_t* d_count = nullptr;
     spd_candidate* h_cand = nullptr;       // pinned
@@ -96,7 +97,6 @@ struct ServeBeam {
     void* fb_halo = nullptr;               // device [n_chan][dd_halo]: last filterbank columns (de-dispersion)
     hipEvent_t ready = nullptr;            // the beam's previous chunk has left its state and halos
     spd_msd_state* state = nullptr;
-    spd_row_stats* stats = nullptr;
     void* ws = nullptr;
     size_t ws_bytes = 0;
 };
@@ -122,6 +122,12 @@ struct spd_server {
     std::vector<spd::ServeBeam> beams;
     std::vector<spd::ServeBuf> pool;
     std::vector<int> free_bufs;
+    // the overflow list (overflow_capacity > 0): a chunk past cand_capacity is searched again into it
+    spd_candidate* ovf_d_cand = nullptr;
+    int64_t* ovf_d_count = nullptr;
+    spd_candidate* ovf_h_cand = nullptr;   // pinned
+    int64_t* ovf_h_count = nullptr;
+    hipStream_t ovf_stream = nullptr;
     std::deque<spd::ServeReq> pending;     // submitted, not admitted, in arrival order
     size_t device_bytes = 0;
     std::mutex mu;
@@ -244,10 +250,10 @@ static spd_status launch_chunk(spd_server* S, ServeReq& r)
         if ((e = hipEventRecord(pb.h2d[0], ps)) != hipSuccess) return device_status(e, "record h2d");
         if ((e = hipStreamWaitEvent(cs, pb.h2d[0], 0)) != hipSuccess) return device_status(e, "wait h2d");
         if ((st = dedisperse_chunk(S, b, pb, r.fresh, cs))) return st;
-        st = msd_compute(&x, &S->params, r.fresh ? 0 : H, r.seq == 0 ? 0 : 1, b.state, b.stats, b.ws, b.ws_bytes,
+        st = msd_compute(&x, &S->params, r.fresh ? 0 : H, r.seq == 0 ? 0 : 1, b.state, pb.stats, b.ws, b.ws_bytes,
                          cs);
         if (st) return st;
-        st = boxcar_snr(&x, &S->params, b.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq, r.fresh), pb.d_cand,
+        st = boxcar_snr(&x, &S->params, pb.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq, r.fresh), pb.d_cand,
                         S->cfg.cand_capacity, pb.d_count, cs);
         if (st) return st;
     } else {
@@ -257,7 +263,7 @@ static spd_status launch_chunk(spd_server* S, ServeReq& r)
         const MsdLayout m = msd_layout(&x);
         if ((st = check_msd_workspace(&x, m, b.ws, b.ws_bytes))) return st;
         BoxcarPlan bp;
-        if ((st = plan_boxcar(&x, &S->params, b.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq, r.fresh), pb.d_cand,
+        if ((st = plan_boxcar(&x, &S->params, pb.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq, r.fresh), pb.d_cand,
                               S->cfg.cand_capacity, pb.d_count, bp)))
             return st;
         if ((e = launch_zero_count(pb.d_count, cs)) != hipSuccess) return device_status(e, "count reset");
@@ -275,10 +281,10 @@ static spd_status launch_chunk(spd_server* S, ServeReq& r)
                                  (size_t)C * S->esize, (size_t)C * S->esize, (size_t)rows, hipMemcpyDeviceToDevice, cs);
             if (e != hipSuccess) return device_status(e, "chunk re-pitch");
             const spd_plane sub = row_slice(&x, r0, rows);
-            if ((st = enqueue_msd(&sub, &S->params, r.fresh ? 0 : H, r.seq != 0, b.state + r0, b.stats + r0,
+            if ((st = enqueue_msd(&sub, &S->params, r.fresh ? 0 : H, r.seq != 0, b.state + r0, pb.stats + r0,
                                   (double*)b.ws, m, cs)))
                 return st;
-            if ((st = enqueue_boxcar(&sub, b.stats + r0, bp, r0, rows, cs))) return st;
+            if ((st = enqueue_boxcar(&sub, pb.stats + r0, bp, r0, rows, cs))) return st;
         }
     }
     if (H > 0) {                                    // the last H columns become the beam's halo
@@ -294,6 +300,29 @@ static spd_status launch_chunk(spd_server* S, ServeReq& r)
     if (e != hipSuccess) return device_status(e, "candidates copy-out");
     if ((e = hipEventRecord(pb.done, cs)) != hipSuccess) return device_status(e, "record done");
     return SPD_OK;
+}
+
+// A chunk that found more than cand_capacity candidates, searched again into
+// the overflow list: its buffer still holds the plane it was searched on and
+// the statistics it was searched with (the beam's later chunks have buffers
+// of their own), so the rerun gives the same candidates.  Blocks the calling
+// thread until the list and its count are on the host.
+static spd_status rerun_chunk(spd_server* S, const ServeReq& r)
+{
+    const ServeBuf& pb = S->pool[r.buf];
+    const spd_plane x = view_plane(S, pb, r.fresh);
+    hipStream_t s = S->ovf_stream;
+    hipError_t e = launch_zero_count(S->ovf_d_count, s);
+    if (e != hipSuccess) return device_status(e, "overflow count reset");
+    spd_status st = boxcar_snr(&x, &S->params, pb.stats, nullptr, nullptr, 0, chunk_t_offset(S, r.seq, r.fresh),
+                               S->ovf_d_cand, S->cfg.overflow_capacity, S->ovf_d_count, s);
+    if (st) return st;
+    e = hipMemcpyAsync(S->ovf_h_count, S->ovf_d_count, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(S->ovf_h_cand, S->ovf_d_cand, sizeof(spd_candidate) * (size_t)S->cfg.overflow_capacity,
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? SPD_OK : device_status(e, "overflow rerun");
 }
 
 static void worker_loop(spd_server* S)
@@ -358,8 +387,27 @@ static void worker_loop(spd_server* S)
                     const int64_t n = *pb.h_count;
                     d.res.n_cands = n;
                     d.res.status = n > S->cfg.cand_capacity ? SPD_E_NOMEM : SPD_OK;
-                    const int64_t k = n < S->cfg.cand_capacity ? n : S->cfg.cand_capacity;
-                    d.cands.assign(pb.h_cand, pb.h_cand + k);
+                    if (n > S->cfg.cand_capacity && S->cfg.overflow_capacity > 0) {
+                        // only this thread touches the in-flight lists, the buffer and the
+                        // overflow list: submit and poll go on during the rerun
+                        lk.unlock();
+                        const spd_status rs = rerun_chunk(S, r);
+                        lk.lock();
+                        if (rs == SPD_OK) {
+                            const int64_t n2 = *S->ovf_h_count;
+                            const int64_t k = std::min<int64_t>(n2, S->cfg.overflow_capacity);
+                            d.res.n_cands = n2;
+                            d.res.status = n2 > S->cfg.overflow_capacity ? SPD_E_NOMEM : SPD_OK;
+                            d.res.flags |= SPD_SERVE_RERUN;
+                            d.cands.assign(S->ovf_h_cand, S->ovf_h_cand + k);
+                        } else {
+                            d.res.status = rs;
+                        }
+                    }
+                    if (!(d.res.flags & SPD_SERVE_RERUN)) {
+                        const int64_t k = n < S->cfg.cand_capacity ? n : S->cfg.cand_capacity;
+                        d.cands.assign(pb.h_cand, pb.h_cand + k);
+                    }
                     for (auto& c : d.cands) c.beam = (uint32_t)r.beam;
                 }
                 S->free_bufs.push_back(r.buf);
@@ -400,6 +448,7 @@ static size_t serve_ws_bytes(int64_t rows, int64_t halo, int64_t cols)
 // the number of pool buffers the budget allows.
 struct ServeSizes {
     size_t per_beam = 0, per_buf = 0;
+    size_t fixed = 0;                    // every beam's state plus the overflow list
     int64_t buffers = 0;                 // 0: the budget does not hold the beams' state and one buffer
     size_t total = 0;
 };
@@ -409,20 +458,26 @@ static ServeSizes serve_sizes(const spd_server_config* cfg, int64_t H, int64_t d
 {
     ServeSizes z;
     const int in_es = elem_size(cfg->dtype);
-    z.per_beam = (size_t)det_rows * (sizeof(spd_msd_state) + sizeof(spd_row_stats)) +
+    z.per_beam = (size_t)det_rows * sizeof(spd_msd_state) +
                  serve_ws_bytes(det_rows, H, cfg->chunk_cols) + (size_t)det_rows * (size_t)H * det_esize +
                  (dd ? (size_t)cfg->n_rows * (size_t)dd_halo : 0);
     z.per_buf = (size_t)det_rows * (size_t)(H + cfg->chunk_cols) * det_esize +
                 (size_t)cfg->n_rows * (size_t)cfg->chunk_cols * in_es +
                 (dd ? (size_t)cfg->n_rows * (size_t)fb_pitch : 0) +
-                (size_t)cfg->cand_capacity * sizeof(spd_candidate) + sizeof(int64_t);
+                (size_t)cfg->cand_capacity * sizeof(spd_candidate) + sizeof(int64_t) +
+                (size_t)det_rows * sizeof(spd_row_stats);
     const int64_t most = (int64_t)cfg->n_beams * cfg->slots_per_beam;
-    const size_t beams = z.per_beam * (size_t)cfg->n_beams;
+    // the beams' own state and the overflow list come first
+    const size_t beams = z.per_beam * (size_t)cfg->n_beams +
+                         (cfg->overflow_capacity > 0 ? (size_t)cfg->overflow_capacity * sizeof(spd_candidate) +
+                                                               sizeof(int64_t)
+                                                     : 0);
     if (cfg->hbm_budget_bytes <= 0) {
         z.buffers = most;
     } else if ((size_t)cfg->hbm_budget_bytes > beams) {
         z.buffers = std::min<int64_t>(most, (int64_t)(((size_t)cfg->hbm_budget_bytes - beams) / z.per_buf));
     }
+    z.fixed = beams;
     z.total = beams + (size_t)z.buffers * z.per_buf;
     return z;
 }
@@ -433,8 +488,10 @@ static void free_server(spd_server* S)
         if (S->compute[q]) (void)hipStreamSynchronize(S->compute[q]);
         if (S->copy[q]) (void)hipStreamSynchronize(S->copy[q]);
     }
+    if (S->ovf_stream) (void)hipStreamSynchronize(S->ovf_stream);
     for (auto& pb : S->pool) {
         if (pb.plane) (void)hipFree(pb.plane);
+        if (pb.stats) (void)hipFree(pb.stats);
         if (pb.stage) (void)hipFree(pb.stage);
         if (pb.fb) (void)hipFree(pb.fb);
         if (pb.d_cand) (void)hipFree(pb.d_cand);
@@ -449,13 +506,17 @@ static void free_server(spd_server* S)
         if (b.fb_halo) (void)hipFree(b.fb_halo);
         if (b.ready) (void)hipEventDestroy(b.ready);
         if (b.state) (void)hipFree(b.state);
-        if (b.stats) (void)hipFree(b.stats);
         if (b.ws) (void)hipFree(b.ws);
     }
+    if (S->ovf_d_cand) (void)hipFree(S->ovf_d_cand);
+    if (S->ovf_d_count) (void)hipFree(S->ovf_d_count);
+    if (S->ovf_h_cand) (void)hipHostFree(S->ovf_h_cand);
+    if (S->ovf_h_count) (void)hipHostFree(S->ovf_h_count);
     for (int q = 0; q < S->n_streams; ++q) {
         if (S->compute[q]) (void)hipStreamDestroy(S->compute[q]);
         if (S->copy[q]) (void)hipStreamDestroy(S->copy[q]);
     }
+    if (S->ovf_stream) (void)hipStreamDestroy(S->ovf_stream);
     delete S;
 }
 
@@ -474,7 +535,7 @@ size_t spd_server_device_bytes(const spd_server_config* cfg, const spd_params* p
     const ServeSizes z = serve_sizes(cfg, H, cfg->n_rows, elem_size(cfg->dtype), 0, 0, false);
     if (z.buffers < 1) {
         fail(SPD_E_NOMEM, "budget %lld bytes < %zu for the beams' state and one chunk buffer",
-             (long long)cfg->hbm_budget_bytes, z.per_beam * (size_t)cfg->n_beams + z.per_buf);
+             (long long)cfg->hbm_budget_bytes, z.fixed + z.per_buf);
         return 0;
     }
     return z.total;
@@ -505,6 +566,9 @@ static spd_status create_server(const spd_server_config* cfg, const spd_params* 
         return fail(SPD_E_INVALID, "n_streams outside [0, %d]", kServeMaxStreams);
     if (cfg->hbm_budget_bytes < 0) return fail(SPD_E_INVALID, "hbm_budget_bytes < 0");
     if (!(cfg->deadline_s >= 0.0) || cfg->deadline_s > 1e9) return fail(SPD_E_INVALID, "deadline_s must be in [0, 1e9]");
+    if (cfg->overflow_capacity != 0 &&
+        (cfg->overflow_capacity <= cfg->cand_capacity || cfg->overflow_capacity > ((int64_t)1 << 31)))
+        return fail(SPD_E_INVALID, "overflow_capacity must be 0 or in (cand_capacity, 2^31]");
     int32_t n_chan = 0, n_dm = 0, max_delay = 0;
     int plan_device = 0, device = 0;
     int64_t dd_halo = 0, fb_pitch = 0;
@@ -524,7 +588,7 @@ static spd_status create_server(const spd_server_config* cfg, const spd_params* 
     const ServeSizes z = serve_sizes(cfg, nmax - 1, det_rows, esize, dd_halo, fb_pitch, dd != nullptr);
     if (z.buffers < 1)
         return fail(SPD_E_NOMEM, "budget %lld bytes < %zu for the beams' state and one chunk buffer",
-                    (long long)cfg->hbm_budget_bytes, z.per_beam * (size_t)cfg->n_beams + z.per_buf);
+                    (long long)cfg->hbm_budget_bytes, z.fixed + z.per_buf);
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess) return device_status(e, "hipGetDevice");
     if (dd && plan_device != device)
@@ -558,6 +622,7 @@ static spd_status create_server(const spd_server_config* cfg, const spd_params* 
         e = hipMalloc(&pb.plane, (size_t)D * (size_t)(H + cfg->chunk_cols) * esize);
         if (e == hipSuccess) e = hipMalloc(&pb.stage, (size_t)cfg->n_rows * (size_t)cfg->chunk_cols * S->in_esize);
         if (e == hipSuccess && dd) e = hipMalloc(&pb.fb, (size_t)cfg->n_rows * (size_t)fb_pitch);
+        if (e == hipSuccess) e = hipMalloc((void**)&pb.stats, sizeof(spd_row_stats) * D);
         if (e == hipSuccess) e = hipMalloc((void**)&pb.d_cand, sizeof(spd_candidate) * cfg->cand_capacity);
         if (e == hipSuccess) e = hipMalloc((void**)&pb.d_count, sizeof(int64_t));
         if (e == hipSuccess) e = hipHostMalloc((void**)&pb.h_cand, sizeof(spd_candidate) * cfg->cand_capacity, 0);
@@ -572,11 +637,18 @@ static spd_status create_server(const spd_server_config* cfg, const spd_params* 
         if (e == hipSuccess && dd && dd_halo > 0) e = hipMalloc(&b.fb_halo, (size_t)cfg->n_rows * (size_t)dd_halo);
         if (e == hipSuccess) e = hipMalloc((void**)&b.state, sizeof(spd_msd_state) * D);
         if (e == hipSuccess) e = hipMemset(b.state, 0, sizeof(spd_msd_state) * D);
-        if (e == hipSuccess) e = hipMalloc((void**)&b.stats, sizeof(spd_row_stats) * D);
         b.ws_bytes = ws_bytes;
         if (e == hipSuccess) e = hipMalloc(&b.ws, ws_bytes);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b.ready, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventRecord(b.ready, S->compute[0]);
+    }
+    if (e == hipSuccess && cfg->overflow_capacity > 0) {
+        e = hipMalloc((void**)&S->ovf_d_cand, sizeof(spd_candidate) * (size_t)cfg->overflow_capacity);
+        if (e == hipSuccess) e = hipMalloc((void**)&S->ovf_d_count, sizeof(int64_t));
+        if (e == hipSuccess)
+            e = hipHostMalloc((void**)&S->ovf_h_cand, sizeof(spd_candidate) * (size_t)cfg->overflow_capacity, 0);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&S->ovf_h_count, sizeof(int64_t), 0);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->ovf_stream, hipStreamNonBlocking);
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {

@@ -241,7 +241,9 @@ def test_server_validation(lib):
                          (cfg(chunk_cols=8), 1, "chunk_cols"), (cfg(slots_per_beam=0), 1, "slots_per_beam"),
                          (cfg(cand_capacity=0), 1, "cand_capacity"), (cfg(hbm_budget_bytes=1000), 3, "budget"),
                          (cfg(n_streams=9), 1, "n_streams"), (cfg(hbm_budget_bytes=-1), 1, "budget"),
-                         (cfg(deadline_s=-1.0), 1, "deadline_s"), (cfg(deadline_s=float("nan")), 1, "deadline_s")]:
+                         (cfg(deadline_s=-1.0), 1, "deadline_s"), (cfg(deadline_s=float("nan")), 1, "deadline_s"),
+                         (cfg(overflow_capacity=-1), 1, "overflow_capacity"),
+                         (cfg(overflow_capacity=100), 1, "overflow_capacity")]:
         assert lib.spd_server_create(ctypes.byref(c), ctypes.byref(p.c), ctypes.byref(out)) == code
         assert out.value is None and msg in _err(lib)
     pp = B.Params([1, 2], 5.0, scope="plane")
@@ -275,8 +277,11 @@ def test_server_pool_sizing(lib):
     all2, all1 = need(), need(slots_per_beam=1)
     per_buf = (all2 - all1) // 4
     beams = all1 - 4 * per_buf
-    # one buffer: the chunk with its halo (FP16), the staged chunk, 100 candidates and a count
-    assert per_buf == 8 * (15 + 4096) * 2 + 8 * 4096 * 2 + 100 * 24 + 8
+    # one buffer: the chunk with its halo (FP16), the staged chunk, 100 candidates and a count,
+    # and the statistics the chunk is searched with (5 doubles per row)
+    assert per_buf == 8 * (15 + 4096) * 2 + 8 * 4096 * 2 + 100 * 24 + 8 + 8 * 40
+    # the overflow list is allocated once, beside the beams' state
+    assert need(overflow_capacity=1000) == all2 + 1000 * 24 + 8
     assert beams > 4 * 8 * 15 * 2                               # halos, statistics, workspaces
     for k in range(1, 9):
         assert need(hbm_budget_bytes=beams + k * per_buf + per_buf // 3) == beams + k * per_buf

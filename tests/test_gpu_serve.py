@@ -447,3 +447,35 @@ def test_server_deadline_stops_the_server():
         srv.submit(0, len(host), host[0])
     srv.close()
     assert delivered <= len(host)
+
+
+def test_server_overflow_rerun_delivers_every_candidate():
+    """A chunk past cand_capacity is searched again from its buffer (the plane
+    and the statistics it was searched with; the beam's next chunk has its
+    own) into the overflow list: every candidate is delivered, flagged
+    SERVE_RERUN, the same set as a server whose list holds them all.  Past the
+    overflow capacity the result is SPD_E_NOMEM with the total count."""
+    R, Lc, K, nb = 16, 8192, 4, 2
+    p = B.Params(list(range(1, 17)), 2.0)
+    streams = _streams(nb, K, R, Lc, 16, torch.float32, seed=31)
+
+    def serve(**kw):
+        srv = B.Server(nb, R, Lc, p, dtype=torch.float32, **kw)
+        for k in range(K):
+            for b in range(nb):
+                srv.submit(b, k, streams[b][0][k])
+        res = {(r["beam"], r["seq"]): (r, c) for r, c in _drain(srv, nb * K)}
+        srv.close()
+        return res
+
+    ref = serve(cand_capacity=1 << 20)
+    small = serve(cand_capacity=64, overflow_capacity=1 << 20)
+    tight = serve(cand_capacity=64, overflow_capacity=100)
+    for key, (r0, c0) in ref.items():
+        assert r0["status"] == 0 and r0["n_cands"] > 100, key
+        r1, c1 = small[key]
+        assert r1["status"] == 0 and r1["flags"] & B.SERVE_RERUN and r1["n_cands"] == r0["n_cands"], key
+        assert _keys(c1) == _keys(c0), "chunk %s: the rerun's candidates differ" % (key,)
+        r2, c2 = tight[key]
+        assert r2["status"] == 3 and r2["flags"] & B.SERVE_RERUN and r2["n_cands"] == r0["n_cands"], key
+        assert len(c2) == 100 and set(_keys(c2)) <= set(_keys(c0))
