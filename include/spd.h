@@ -553,7 +553,9 @@ spd_status spd_server_submit(spd_server* server, int32_t beam, int64_t seq, cons
                              double arrival_s);
 
 /* Take one finished chunk: its result and up to `cap` candidates ([host]
- * buffer).  Waits up to wait_ms for one; SPD_E_AGAIN if none finished.    */
+ * buffer; a chunk searched again after an overflow brings up to
+ * overflow_capacity, the rest are dropped and n_copied says how many were
+ * copied).  Waits up to wait_ms for one; SPD_E_AGAIN if none finished.    */
 spd_status spd_server_poll(spd_server* server, spd_server_result* result, spd_candidate* cands, int64_t cap,
                            int32_t wait_ms);
 
